@@ -1,0 +1,538 @@
+"""FP64 CPU oracle of the HOG sliding-window face detector.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports, links or
+calls this module; it exists so that tests, the smoke check and the CPU
+baseline leg of the benchmark can check the HIP path against a plain,
+slow, obviously correct statement of what the detector computes.
+
+Every function follows the paper's algorithm breakdown of the face
+detector (Sec. IV-A, "Algorithm breakdown") in order: image pyramid,
+gradient computation, histogramisation, normalisation, feature
+computation, linear classification and non-maximum suppression.  Where the
+paper is silent or ambiguous, the reading taken is named (R1..R16) and the
+same numbering is used in the design notes.
+
+Arithmetic is numpy float64 unless a step is integer by definition.  The
+code is vectorised over pixels and cells only; there is no tiling,
+fusion or reordering of the steps.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from functools import lru_cache
+
+import mpmath
+import numpy as np
+
+CELL = 8            # 8x8-pixel cells (Sec. IV-A, histogramisation)
+NBINS = 18          # eighteen signed orientations (Sec. IV-A, gradient computation)
+NORIENT = 9         # unsigned orientations: bins o and o+9 are opposite directions
+WIN = 10            # 80x80 px = 10x10-cell detection window (Sec. IV-A, classification)
+NFEAT = 31          # 18 signed + 9 unsigned + 4 energy features (Sec. IV-A, features)
+MIN_SIDE = 80       # pyramid stops below the 80 px window (Sec. IV-A)
+SCALE_NUM, SCALE_DEN = 5, 6   # 5/6 downscale step (Sec. IV-A)
+CLIP = 0.2          # truncation of normalised values (R8)
+EPS = 1e-4          # added to block energies before the square root (R7)
+TEXTURE = 1.0 / math.sqrt(18.0)   # weight of the 4 energy features (R8)
+
+
+# ---------------------------------------------------------------- pyramid
+@dataclasses.dataclass(frozen=True)
+class Level:
+    """One pyramid level: scale s = p/q relative to the frame."""
+    k: int
+    p: int
+    q: int
+    h: int
+    w: int
+
+    @property
+    def cy(self) -> int:
+        return self.h // CELL
+
+    @property
+    def cx(self) -> int:
+        return self.w // CELL
+
+    @property
+    def rows(self) -> int:          # window rows r = 0 .. cy-10
+        return self.cy - WIN + 1
+
+    @property
+    def cols(self) -> int:
+        return self.cx - WIN + 1
+
+
+def pyramid(h: int, w: int, upsample: int = 1) -> list[Level]:
+    """Pyramid levels k = 0, 1, ... with s_k = upsample * (5/6)^k, sizes
+    floor(h*s_k) x floor(w*s_k), kept while both sides are >= 80 px.
+
+    Sec. IV-A: the image is scaled down in 5/6 steps until a side is
+    smaller than the 80x80 window.  R1: every level is sized directly from
+    the frame with exact integer arithmetic.  R3: ``upsample`` = 2 applies
+    the 2x enlargement (Sec. III-B upscales test images 2x) in the same
+    composite scale."""
+    out = []
+    k = 0
+    while True:
+        p, q = upsample * SCALE_NUM ** k, SCALE_DEN ** k
+        hk, wk = (h * p) // q, (w * p) // q
+        if min(hk, wk) < MIN_SIDE:
+            return out
+        out.append(Level(k, p, q, hk, wk))
+        k += 1
+
+
+def axis_taps(n_out: int, n_in: int, p: int, q: int):
+    """Bilinear taps along one axis for scale p/q (R2).
+
+    Output sample i sits at source coordinate (i + 1/2) * q/p - 1/2
+    (pixel centres aligned).  Its integer part i0 and the fractional part,
+    rounded half-up to a multiple of 1/256, give the taps i0 and i0 + 1
+    (clamped to the source) with weights (256 - a)/256 and a/256.  All of
+    it is exact integer arithmetic."""
+    i0 = np.empty(n_out, np.int64)
+    i1 = np.empty(n_out, np.int64)
+    a8 = np.empty(n_out, np.int64)
+    den = 2 * p
+    for i in range(n_out):
+        num = (2 * i + 1) * q - p
+        base = num // den                # floor, also for negative num
+        rem = num - base * den           # in [0, den)
+        a = (256 * rem + p) // (2 * p)   # round(256 * rem/den), halves up
+        if a == 256:
+            base, a = base + 1, 0
+        i0[i] = min(max(base, 0), n_in - 1)
+        i1[i] = min(max(base + 1, 0), n_in - 1)
+        a8[i] = a
+    return i0, i1, a8
+
+
+def resample(frame: np.ndarray, lv: Level) -> np.ndarray:
+    """Level image L_k = bilinear resample of the frame itself at scale
+    s_k (R2).  With integer frames every value is a multiple of 2^-16
+    below 256, so the float64 result is exact."""
+    U = np.asarray(frame, np.float64)
+    H, W = U.shape
+    y0, y1, ay = axis_taps(lv.h, H, lv.p, lv.q)
+    x0, x1, ax = axis_taps(lv.w, W, lv.p, lv.q)
+    wy0, wy1 = (256 - ay) / 256.0, ay / 256.0
+    wx0, wx1 = (256 - ax) / 256.0, ax / 256.0
+    L = ((wy0[:, None] * wx0[None, :]) * U[np.ix_(y0, x0)]
+         + (wy0[:, None] * wx1[None, :]) * U[np.ix_(y0, x1)]
+         + (wy1[:, None] * wx0[None, :]) * U[np.ix_(y1, x0)]
+         + (wy1[:, None] * wx1[None, :]) * U[np.ix_(y1, x1)])
+    return L
+
+
+def resample_transpose(dL: np.ndarray, lv: Level, H: int, W: int) -> np.ndarray:
+    """Adjoint of :func:`resample`: scatters level values back onto the
+    frame with the same tap weights."""
+    y0, y1, ay = axis_taps(lv.h, H, lv.p, lv.q)
+    x0, x1, ax = axis_taps(lv.w, W, lv.p, lv.q)
+    wy = ((256 - ay) / 256.0, ay / 256.0)
+    wx = ((256 - ax) / 256.0, ax / 256.0)
+    dU = np.zeros((H, W))
+    for ys, wyv in zip((y0, y1), wy):
+        for xs, wxv in zip((x0, x1), wx):
+            np.add.at(dU, (ys[:, None], xs[None, :]),
+                      (wyv[:, None] * wxv[None, :]) * dL)
+    return dU
+
+
+# -------------------------------------------------------------- gradients
+def gradients(L: np.ndarray):
+    """Central differences [-1, 0, 1] along x and y (y pointing down).
+    The one-pixel border of the level has zero gradient (R4)."""
+    gx = np.zeros_like(L)
+    gy = np.zeros_like(L)
+    gx[1:-1, 1:-1] = L[1:-1, 2:] - L[1:-1, :-2]
+    gy[1:-1, 1:-1] = L[2:, 1:-1] - L[:-2, 1:-1]
+    return gx, gy
+
+
+def _nearest_double(x) -> float:
+    return float(mpmath.nstr(x, 40, strip_zeros=False))
+
+
+@lru_cache(maxsize=1)
+def orientation_table():
+    """c_o = cos(o*pi/9), s_o = sin(o*pi/9), o = 0..8, each the float64
+    nearest to the exact value.  Correct rounding makes the table mirror
+    exactly: c_{9-o} = -c_o and s_{9-o} = s_o (R5)."""
+    mpmath.mp.dps = 60
+    c = np.array([_nearest_double(mpmath.cos(o * mpmath.pi / 9)) for o in range(NORIENT)])
+    s = np.array([_nearest_double(mpmath.sin(o * mpmath.pi / 9)) for o in range(NORIENT)])
+    for o in range(1, 5):
+        assert c[9 - o] == -c[o] and s[9 - o] == s[o]
+    return c, s
+
+
+def orientation_bins(gx: np.ndarray, gy: np.ndarray) -> np.ndarray:
+    """Hard orientation bin in 0..17 (Sec. IV-A: one of eighteen signed
+    directions; R5).
+
+    For o = 0..8 the projection d_o = gx*c_o + gy*s_o is formed as two
+    rounded float64 products and a rounded sum (no fused multiply-add).
+    Scanning o upwards from best = 0, d_o > best selects bin o and
+    -d_o > best selects the opposite bin o + 9; ties keep the earlier
+    choice."""
+    c, s = orientation_table()
+    best = np.zeros(gx.shape)
+    bins = np.zeros(gx.shape, np.int64)
+    for o in range(NORIENT):
+        d = gx * c[o] + gy * s[o]
+        up = d > best
+        best = np.where(up, d, best)
+        bins = np.where(up, o, bins)
+        dn = -d > best
+        best = np.where(dn, -d, best)
+        bins = np.where(dn, o + NORIENT, bins)
+    return bins
+
+
+# ---------------------------------------------------------- histograms
+def _tent(n_pix: int):
+    """Cell index and weight of the lower cell along one axis for each
+    pixel: cell j is centred on pixel 8j + 3.5 (R6)."""
+    xp = (np.arange(n_pix) + 0.5) / CELL - 0.5
+    ix = np.floor(xp).astype(np.int64)
+    return ix, xp - ix
+
+
+def cell_histograms(L: np.ndarray, gx=None, gy=None):
+    """18-bin histograms of 8x8 cells, hist[cy][cx][18] (Sec. IV-A,
+    histogramisation).  Every pixel of the cell grid (x < 8*cx,
+    y < 8*cy) adds mag * (bilinear weight) to its bin in the four nearest
+    cells; weights of cells outside the grid are dropped (R4, R6)."""
+    if gx is None:
+        gx, gy = gradients(L)
+    mag = np.sqrt(gx * gx + gy * gy)
+    bins = orientation_bins(gx, gy)
+    H, W = L.shape
+    cy, cx = H // CELL, W // CELL
+    hist = np.zeros((cy, cx, NBINS))
+    iy, ay = _tent(CELL * cy)
+    ix, ax = _tent(CELL * cx)
+    m = mag[:CELL * cy, :CELL * cx]
+    b = bins[:CELL * cy, :CELL * cx]
+    for di, wy in ((0, 1.0 - ay), (1, ay)):
+        ci = iy + di
+        for dj, wx in ((0, 1.0 - ax), (1, ax)):
+            cj = ix + dj
+            v = m * wy[:, None] * wx[None, :]
+            ci2 = np.broadcast_to(ci[:, None], v.shape)
+            cj2 = np.broadcast_to(cj[None, :], v.shape)
+            ok = (ci2 >= 0) & (ci2 < cy) & (cj2 >= 0) & (cj2 < cx)
+            np.add.at(hist, (ci2[ok], cj2[ok], b[ok]), v[ok])
+    return hist
+
+
+def cell_energy(hist: np.ndarray) -> np.ndarray:
+    """energy = sum_{n=0..8} (h_n + h_{n+9})^2 (Sec. IV-A, normalisation;
+    Sec. V-A, energy kernel)."""
+    u = hist[..., :NORIENT] + hist[..., NORIENT:]
+    return (u * u).sum(-1)
+
+
+BLOCKS = ((-1, -1), (-1, 1), (1, -1), (1, 1))
+
+
+def block_energies(E: np.ndarray) -> np.ndarray:
+    """B[cy][cx][4]: summed energy of the four 2x2-cell blocks that contain
+    each cell, in the order of BLOCKS, with zero energy outside the grid
+    (R7: the cell and its eight neighbours, grouped into four blocks)."""
+    cy, cx = E.shape
+    P = np.zeros((cy + 2, cx + 2))
+    P[1:-1, 1:-1] = E
+    B = np.empty((cy, cx, 4))
+    for k, (dy, dx) in enumerate(BLOCKS):
+        B[..., k] = (E + P[1 + dy:1 + dy + cy, 1:1 + cx]
+                     + P[1:1 + cy, 1 + dx:1 + dx + cx]
+                     + P[1 + dy:1 + dy + cy, 1 + dx:1 + dx + cx])
+    return B
+
+
+def features_from_hist(hist: np.ndarray) -> np.ndarray:
+    """31-d cell features (Sec. IV-A, feature computation; R8):
+    n_k = (B_k + eps)^-1/2 for the four blocks, T(v) = min(v, 0.2),
+      F[b]      = 1/2 sum_k T(h_b n_k)                 b < 18 (signed)
+      F[18 + o] = 1/2 sum_k T((h_o + h_{o+9}) n_k)     o < 9  (unsigned)
+      F[27 + k] = 1/sqrt(18) sum_b T(h_b n_k)          k < 4  (energy)"""
+    n = 1.0 / np.sqrt(block_energies(cell_energy(hist)) + EPS)
+    u = hist[..., :NORIENT] + hist[..., NORIENT:]
+    cy, cx, _ = hist.shape
+    F = np.zeros((cy, cx, NFEAT))
+    for k in range(4):
+        nk = n[..., k:k + 1]
+        t = np.minimum(hist * nk, CLIP)
+        F[..., :NBINS] += 0.5 * t
+        F[..., NBINS:NBINS + NORIENT] += 0.5 * np.minimum(u * nk, CLIP)
+        F[..., 27 + k] = TEXTURE * t.sum(-1)
+    return F
+
+
+def level_features(frame: np.ndarray, lv: Level) -> np.ndarray:
+    return features_from_hist(cell_histograms(resample(frame, lv)))
+
+
+def pyramid_features(frame: np.ndarray, upsample: int = 1):
+    H, W = np.asarray(frame).shape
+    return [(lv, level_features(frame, lv)) for lv in pyramid(H, W, upsample)]
+
+
+# ------------------------------------------------------------- scoring
+def window_scores(F: np.ndarray, W: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """S[f][r][c] = b_f + sum_{dr,dc<10} sum_{ch<31} W_f[dr][dc][ch] F[r+dr][c+dc][ch]
+    for every 10x10-cell window anchored at its top-left cell (Sec. IV-A,
+    classification; R9)."""
+    W = np.asarray(W, np.float64)
+    b = np.asarray(b, np.float64)
+    cy, cx, _ = F.shape
+    R, C = cy - WIN + 1, cx - WIN + 1
+    S = np.zeros((W.shape[0], R, C)) + b[:, None, None]
+    for dr in range(WIN):
+        for dc in range(WIN):
+            S += np.einsum("rcx,fx->frc", F[dr:dr + R, dc:dc + C], W[:, dr, dc])
+    return S
+
+
+def _round_div(num, den):
+    """floor(num/den + 1/2) for non-negative integers (exact)."""
+    return (2 * num + den) // (2 * den)
+
+
+def window_box(lv: Level, r, c):
+    """Half-open frame-pixel box of window (r, c) of level lv: the window
+    covers level pixels [8c, 8c+80) x [8r, 8r+80), mapped back by the exact
+    inverse scale q/p and rounded to the nearest integer (R12)."""
+    x0 = _round_div(8 * np.asarray(c, np.int64) * lv.q, lv.p)
+    x1 = _round_div((8 * np.asarray(c, np.int64) + 80) * lv.q, lv.p)
+    y0 = _round_div(8 * np.asarray(r, np.int64) * lv.q, lv.p)
+    y1 = _round_div((8 * np.asarray(r, np.int64) + 80) * lv.q, lv.p)
+    return x0, y0, x1, y1
+
+
+CAND_DTYPE = np.dtype([("score", "f8"), ("f", "i4"), ("k", "i4"), ("r", "i4"), ("c", "i4"),
+                       ("x0", "i8"), ("y0", "i8"), ("x1", "i8"), ("y1", "i8")])
+
+
+def candidates(frame, W, b, thresh: float = 0.0, upsample: int = 1, levels_out=None):
+    """All windows with score strictly above the threshold, over every
+    filter and pyramid level (Sec. IV-A; Sec. V-A, detection kernel;
+    R10)."""
+    H, Wd = np.asarray(frame).shape
+    rows = []
+    for lv in pyramid(H, Wd, upsample):
+        S = window_scores(level_features(frame, lv), W, b)
+        if levels_out is not None:
+            levels_out.append((lv, S))
+        f, r, c = np.nonzero(S > thresh)
+        if len(f) == 0:
+            continue
+        x0, y0, x1, y1 = window_box(lv, r, c)
+        a = np.empty(len(f), CAND_DTYPE)
+        a["score"], a["f"], a["k"], a["r"], a["c"] = S[f, r, c], f, lv.k, r, c
+        a["x0"], a["y0"], a["x1"], a["y1"] = x0, y0, x1, y1
+        rows.append(a)
+    return np.concatenate(rows) if rows else np.empty(0, CAND_DTYPE)
+
+
+def rank_order(c: np.ndarray) -> np.ndarray:
+    """Total order of candidates: score descending, then filter, level,
+    row and column ascending (R13)."""
+    return np.lexsort((c["c"], c["r"], c["k"], c["f"], -c["score"]))
+
+
+def nms(c: np.ndarray, iou: float = 0.5) -> np.ndarray:
+    """Greedy non-maximum suppression pooled over filters and levels of a
+    frame (Sec. IV-A: detections of one face reduced to the best-scoring
+    one; R13).  In rank order a candidate is kept unless its IoU with an
+    already kept box exceeds ``iou``; the test I > iou * U is done on exact
+    integer areas (for 0.5: 2I > U)."""
+    num, den = float(iou).as_integer_ratio()
+    c = c[rank_order(c)]
+    keep = np.zeros(len(c), bool)
+    kx0 = np.empty(0, np.int64)
+    ky0, kx1, ky1 = kx0.copy(), kx0.copy(), kx0.copy()
+    for i in range(len(c)):
+        x0, y0, x1, y1 = int(c["x0"][i]), int(c["y0"][i]), int(c["x1"][i]), int(c["y1"][i])
+        if len(kx0):
+            iw = np.maximum(0, np.minimum(kx1, x1) - np.maximum(kx0, x0))
+            ih = np.maximum(0, np.minimum(ky1, y1) - np.maximum(ky0, y0))
+            inter = iw * ih
+            union = (x1 - x0) * (y1 - y0) + (kx1 - kx0) * (ky1 - ky0) - inter
+            if np.any(inter * den > num * union):
+                continue
+        keep[i] = True
+        kx0 = np.append(kx0, x0)
+        ky0 = np.append(ky0, y0)
+        kx1 = np.append(kx1, x1)
+        ky1 = np.append(ky1, y1)
+    return c[keep]
+
+
+def detect(frame, W, b, thresh: float = 0.0, iou: float = 0.5, upsample: int = 1):
+    """Frame in, kept face boxes and scores out, in rank order."""
+    return nms(candidates(frame, W, b, thresh, upsample), iou)
+
+
+# ------------------------------------------------- training (dW, db)
+def hinge_loss(S, y, W, lam: float = 1e-4) -> float:
+    """Mean hinge loss plus lam * ||W||^2 (bias not regularised; R15)."""
+    S = np.asarray(S, np.float64)
+    y = np.asarray(y, np.float64)
+    return float(np.maximum(0.0, 1.0 - y * S).mean() + lam * np.sum(np.asarray(W, np.float64) ** 2))
+
+
+def hinge_dscore(S, y) -> np.ndarray:
+    """d loss / d S_i = -y_i / N where y_i S_i < 1, else 0."""
+    S = np.asarray(S, np.float64)
+    y = np.asarray(y, np.float64)
+    return np.where(y * S < 1.0, -y, 0.0) / len(S)
+
+
+def filter_grad(Fw: np.ndarray, dS: np.ndarray):
+    """dS/dW_f is the window's feature block and dS/db = 1, so
+    dW = sum_i dS_i F_i and db = sum_i dS_i."""
+    return np.tensordot(dS, Fw, axes=(0, 0)), float(np.sum(dS))
+
+
+# --------------------------------------------- pixel gradient (dpixels)
+def top_windows(frame, W, b, k: int = 10, upsample: int = 1):
+    """The k highest window scores of a frame over every filter and level
+    (all windows, before thresholding and NMS), in rank order (R14)."""
+    H, Wd = np.asarray(frame).shape
+    rows = []
+    for lv in pyramid(H, Wd, upsample):
+        S = window_scores(level_features(frame, lv), W, b)
+        f, r, c = np.meshgrid(np.arange(S.shape[0]), np.arange(S.shape[1]),
+                              np.arange(S.shape[2]), indexing="ij")
+        a = np.empty(S.size, CAND_DTYPE)
+        a["score"], a["f"], a["k"] = S.ravel(), f.ravel(), lv.k
+        a["r"], a["c"] = r.ravel(), c.ravel()
+        a["x0"] = a["y0"] = a["x1"] = a["y1"] = 0
+        rows.append(a)
+    allw = np.concatenate(rows)
+    return allw[rank_order(allw)[:k]]
+
+
+def level_forward(frame, lv: Level) -> dict:
+    """Every intermediate of one level, for the backward pass."""
+    L = resample(frame, lv)
+    gx, gy = gradients(L)
+    mag = np.sqrt(gx * gx + gy * gy)
+    bins = orientation_bins(gx, gy)
+    hist = cell_histograms(L, gx, gy)
+    E = cell_energy(hist)
+    B = block_energies(E)
+    return dict(L=L, gx=gx, gy=gy, mag=mag, bins=bins, hist=hist, E=E, B=B,
+                n=1.0 / np.sqrt(B + EPS))
+
+
+def dfeatures_to_dhist(st: dict, dF: np.ndarray) -> np.ndarray:
+    """Backward of the 31-d projection and the block normalisation:
+    d(loss)/d(hist) from d(loss)/d(F).  Clip states (v < 0.2 passes, else
+    the derivative is 0) are those of the forward pass."""
+    hist, n, B = st["hist"], st["n"], st["B"]
+    u = hist[..., :NORIENT] + hist[..., NORIENT:]
+    dh = np.zeros_like(hist)
+    du = np.zeros_like(u)
+    dn = np.zeros_like(n)
+    for k in range(4):
+        nk = n[..., k:k + 1]
+        hn = hist * nk
+        pas = (hn < CLIP).astype(np.float64)
+        g = 0.5 * dF[..., :NBINS] + TEXTURE * dF[..., 27 + k:28 + k]
+        dh += g * pas * nk
+        dn[..., k] += (g * pas * hist).sum(-1)
+        un = u * nk
+        pu = (un < CLIP).astype(np.float64)
+        gu = 0.5 * dF[..., NBINS:NBINS + NORIENT]
+        du += gu * pu * nk
+        dn[..., k] += (gu * pu * u).sum(-1)
+    dB = dn * (-0.5) * (B + EPS) ** -1.5
+    cy, cx = dB.shape[:2]
+    dE = np.zeros((cy + 2, cx + 2))
+    for k, (dy, dx) in enumerate(BLOCKS):
+        g = dB[..., k]
+        dE[1:1 + cy, 1:1 + cx] += g
+        dE[1 + dy:1 + dy + cy, 1:1 + cx] += g
+        dE[1:1 + cy, 1 + dx:1 + dx + cx] += g
+        dE[1 + dy:1 + dy + cy, 1 + dx:1 + dx + cx] += g
+    dE = dE[1:-1, 1:-1]
+    du += 2.0 * u * dE[..., None]
+    dh[..., :NORIENT] += du
+    dh[..., NORIENT:] += du
+    return dh
+
+
+def dhist_to_dlevel(st: dict, dh: np.ndarray) -> np.ndarray:
+    """Backward of histogramisation, magnitude and central differences:
+    d/d(level pixels) from d/d(hist).  Bins and bilinear weights are
+    constants; d mag / d(gx, gy) = (gx, gy)/mag, taken as 0 at mag = 0."""
+    L, gx, gy, mag, bins = st["L"], st["gx"], st["gy"], st["mag"], st["bins"]
+    cy, cx, _ = dh.shape
+    iy, ay = _tent(CELL * cy)
+    ix, ax = _tent(CELL * cx)
+    b = bins[:CELL * cy, :CELL * cx]
+    dmag = np.zeros_like(L)
+    acc = np.zeros((CELL * cy, CELL * cx))
+    for di, wy in ((0, 1.0 - ay), (1, ay)):
+        ci = iy + di
+        for dj, wx in ((0, 1.0 - ax), (1, ax)):
+            cj = ix + dj
+            ci2 = np.broadcast_to(ci[:, None], b.shape)
+            cj2 = np.broadcast_to(cj[None, :], b.shape)
+            ok = (ci2 >= 0) & (ci2 < cy) & (cj2 >= 0) & (cj2 < cx)
+            g = np.zeros(b.shape)
+            g[ok] = dh[ci2[ok], cj2[ok], b[ok]]
+            acc += g * wy[:, None] * wx[None, :]
+    dmag[:CELL * cy, :CELL * cx] = acc
+    safe = np.where(mag > 0, mag, 1.0)
+    dgx = np.where(mag > 0, dmag * gx / safe, 0.0)
+    dgy = np.where(mag > 0, dmag * gy / safe, 0.0)
+    dL = np.zeros_like(L)
+    dL[1:-1, 2:] += dgx[1:-1, 1:-1]
+    dL[1:-1, :-2] -= dgx[1:-1, 1:-1]
+    dL[2:, 1:-1] += dgy[1:-1, 1:-1]
+    dL[:-2, 1:-1] -= dgy[1:-1, 1:-1]
+    return dL
+
+
+def topk_pixel_grad(frame, W, b, k: int = 10, upsample: int = 1, windows=None):
+    """d(sum of the top-k window scores)/d(frame pixels), analytic, float64.
+    Bins, clip states and the top-k membership are held at their values
+    at the given frame (R14)."""
+    U = np.asarray(frame, np.float64)
+    H, Wd = U.shape
+    if windows is None:
+        windows = top_windows(U, W, b, k, upsample)
+    W64 = np.asarray(W, np.float64)
+    dU = np.zeros((H, Wd))
+    for lv in pyramid(H, Wd, upsample):
+        sel = windows[windows["k"] == lv.k]
+        if len(sel) == 0:
+            continue
+        st = level_forward(U, lv)
+        dF = np.zeros((lv.cy, lv.cx, NFEAT))
+        for w in sel:
+            dF[w["r"]:w["r"] + WIN, w["c"]:w["c"] + WIN] += W64[w["f"]]
+        dL = dhist_to_dlevel(st, dfeatures_to_dhist(st, dF))
+        dU += resample_transpose(dL, lv, H, Wd)
+    return dU, windows
+
+
+def topk_objective(frame, W, b, windows, upsample: int = 1) -> float:
+    """Sum of the scores of the given windows, recomputed from the frame."""
+    U = np.asarray(frame, np.float64)
+    H, Wd = U.shape
+    tot = 0.0
+    for lv in pyramid(H, Wd, upsample):
+        sel = windows[windows["k"] == lv.k]
+        if len(sel) == 0:
+            continue
+        S = window_scores(level_features(U, lv), W, b)
+        tot += float(S[sel["f"], sel["r"], sel["c"]].sum())
+    return tot

@@ -1,0 +1,367 @@
+"""Pins of the float64 oracle against what the paper and mathematics fix.
+
+None of these re-types the oracle's own formulas: each one checks a
+closed form, an invariant, a special case or an independent formulation.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import hog
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+# ------------------------------------------------------------ constants
+def test_paper_constants():
+    g = _gold("paper_constants.json")
+    assert hog.CELL == g["cell_px"]["value"]
+    assert hog.NBINS == g["signed_bins"]["value"]
+    assert hog.NFEAT == g["features"]["value"] == sum(g["features"]["parts"])
+    assert hog.WIN == g["window_cells"]["value"]
+    assert hog.WIN * hog.CELL == g["window_px"]["value"]
+    assert hog.WIN * hog.WIN * hog.NFEAT == g["window_weights"]["value"]
+    assert (hog.SCALE_NUM, hog.SCALE_DEN) == (g["scale_step"]["num"], g["scale_step"]["den"])
+    assert hog.MIN_SIDE == g["min_side_px"]["value"]
+    t = g["classifier_tile"]
+    assert t["block_cols"] + hog.WIN - 1 == t["needed_cols"]
+
+
+def test_orientation_table_exact_and_mirrored():
+    c, s = hog.orientation_table()
+    for o in range(9):
+        a = o * math.pi / 9
+        assert abs(c[o] - math.cos(a)) <= 2 * np.spacing(1.0)
+        assert abs(s[o] - math.sin(a)) <= 2 * np.spacing(1.0)
+    for o in range(1, 5):
+        assert c[9 - o] == -c[o] and s[9 - o] == s[o]
+    assert c[0] == 1.0 and s[0] == 0.0 and c[3] == 0.5
+
+
+# ------------------------------------------------------------- pyramid
+def test_pyramid_sizes_golden():
+    g = _gold("pyramid_levels.json")
+    for key in ("240x320_u1", "480x640_u1", "80x80_u1"):
+        h, w = map(int, key.split("_")[0].split("x"))
+        assert [[lv.h, lv.w] for lv in hog.pyramid(h, w)] == g[key]
+    lv = hog.pyramid(480, 640)
+    assert [l.rows * l.cols for l in lv] == g["480x640_u1_windows_per_level"]
+    big = hog.pyramid(1080, 1920, 2)
+    assert len(big) == g["1080x1920_u2_n_levels"]
+    assert [big[0].h, big[0].w] == g["1080x1920_u2_first"]
+    assert [big[-1].h, big[-1].w] == g["1080x1920_u2_last"]
+
+
+@pytest.mark.parametrize("h,w,u", [(240, 320, 1), (480, 640, 1), (97, 331, 1), (100, 120, 2), (1080, 1920, 2)])
+def test_pyramid_stop_rule(h, w, u):
+    lv = hog.pyramid(h, w, u)
+    assert min(lv[-1].h, lv[-1].w) >= 80
+    s_next = u * (5 / 6) ** (lv[-1].k + 1)
+    assert min(math.floor(h * s_next + 1e-9), math.floor(w * s_next + 1e-9)) < 80
+    for l in lv:
+        assert abs(l.h - h * l.p / l.q) < 1 and abs(l.w - w * l.p / l.q) < 1
+
+
+def test_pyramid_too_small():
+    assert hog.pyramid(79, 500) == []
+    assert len(hog.pyramid(80, 80)) == 1
+
+
+def test_resample_identity_and_constant():
+    rng = np.random.default_rng(5)
+    U = rng.integers(0, 256, (120, 150)).astype(np.uint8)
+    lv = hog.pyramid(120, 150)
+    assert np.array_equal(hog.resample(U, lv[0]), U.astype(np.float64))
+    C = np.full((120, 150), 77, np.uint8)
+    for l in lv:
+        assert np.all(hog.resample(C, l) == 77.0)
+    for l in hog.pyramid(120, 150, 2):
+        assert np.all(hog.resample(C, l) == 77.0)
+
+
+@pytest.mark.parametrize("u", [1, 2])
+def test_resample_reproduces_linear_ramp(u):
+    """Bilinear sampling reproduces a linear function at the pixel-centre
+    aligned source coordinate (i + 1/2)/s - 1/2, up to the 1/256 weight
+    quantisation (at most 1/512 px), away from the clamped border."""
+    H, W = 200, 260
+    U = np.tile(np.arange(W, dtype=np.float64), (H, 1))
+    for l in hog.pyramid(H, W, u):
+        L = hog.resample(U, l)
+        xs = (np.arange(l.w) + 0.5) * l.q / l.p - 0.5
+        inner = (xs >= 0) & (xs <= W - 1)
+        err = np.abs(L[l.h // 2, inner] - xs[inner])
+        assert err.max() <= 1 / 512 + 1e-12
+
+
+def test_resample_values_exact_dyadic():
+    rng = np.random.default_rng(6)
+    U = rng.integers(0, 256, (130, 170)).astype(np.uint8)
+    for l in hog.pyramid(130, 170, 2):
+        L = hog.resample(U, l)
+        q = L * 65536.0
+        assert np.array_equal(q, np.round(q)) and L.max() <= 255 and L.min() >= 0
+
+
+def test_resample_adjoint():
+    rng = np.random.default_rng(7)
+    H, W = 150, 190
+    x = rng.standard_normal((H, W))
+    for u in (1, 2):
+        for l in hog.pyramid(H, W, u):
+            y = rng.standard_normal((l.h, l.w))
+            lhs = np.sum(hog.resample(x, l) * y)
+            rhs = np.sum(x * hog.resample_transpose(y, l, H, W))
+            assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(lhs))
+
+
+# ------------------------------------------------------- P1 constant
+def test_constant_image_all_zero():
+    U = np.full((160, 200), 123, np.uint8)
+    W = np.random.default_rng(0).normal(0, 0.1, (2, 10, 10, 31))
+    b = np.array([-0.5, 0.25])
+    for lv, F in hog.pyramid_features(U):
+        L = hog.resample(U, lv)
+        gx, gy = hog.gradients(L)
+        assert not gx.any() and not gy.any()
+        assert not hog.cell_histograms(L).any()
+        assert not F.any()
+        S = hog.window_scores(F, W, b)
+        assert np.all(S == b[:, None, None])
+
+
+# ----------------------------------------------------- P2 ramp bins
+def _bin_by_angle(gx, gy):
+    if gx == 0:
+        return 4 if gy > 0 else 13
+    deg = math.degrees(math.atan2(gy, gx)) % 360
+    return int((deg + 10) // 20) % 18
+
+
+def _ramp(a, b, H=96, W=96):
+    y, x = np.mgrid[0:H, 0:W].astype(np.float64)
+    return 128 + a * (x - W / 2) + b * (y - H / 2)
+
+
+@pytest.mark.parametrize("a,b", [(a, b) for a in range(-3, 4) for b in range(-3, 4) if (a, b) != (0, 0)])
+def test_ramp_bin_is_nearest_direction(a, b):
+    U = _ramp(a, b)
+    gx, gy = hog.gradients(U)
+    assert np.all(gx[1:-1, 1:-1] == 2 * a) and np.all(gy[1:-1, 1:-1] == 2 * b)
+    bins = hog.orientation_bins(gx[1:-1, 1:-1], gy[1:-1, 1:-1])
+    assert np.all(bins == _bin_by_angle(2 * a, 2 * b))
+
+
+def test_named_edge_directions():
+    # (gx, gy) -> bin, y pointing down, angle measured from +x towards +y
+    cases = {(1, 0): 0, (2, 1): 1, (1, 1): 2, (1, 2): 3, (0, 1): 4, (-1, 2): 6,
+             (-1, 1): 7, (-1, 0): 9, (-1, -1): 11, (0, -1): 13, (1, -2): 15, (1, -1): 16}
+    for (gx, gy), want in cases.items():
+        got = hog.orientation_bins(np.array([float(gx)]), np.array([float(gy)]))[0]
+        assert got == want, (gx, gy, got, want)
+
+
+# -------------------------------------------- P3 closed-form features
+@pytest.mark.parametrize("a,b", [(1, 0), (2, 1), (1, 1), (-1, 2), (0, -1), (3, -2)])
+def test_ramp_closed_form_features(a, b):
+    U = _ramp(a, b)
+    lv = hog.pyramid(96, 96)[0]
+    L = hog.resample(U, lv)
+    hist = hog.cell_histograms(L)
+    F = hog.features_from_hist(hist)
+    mag = 2 * math.hypot(a, b)
+    bn = _bin_by_angle(2 * a, 2 * b)
+    cy = 12
+    for i in range(1, cy - 1):
+        for j in range(1, cy - 1):
+            want = np.zeros(18)
+            want[bn] = 64 * mag
+            assert np.allclose(hist[i, j], want, rtol=1e-13, atol=1e-12)
+    want = np.zeros(31)
+    want[bn] = 0.4
+    want[18 + bn % 9] = 0.4
+    want[27:] = 0.2 / math.sqrt(18)
+    for i in range(2, cy - 2):
+        for j in range(2, cy - 2):
+            assert np.allclose(F[i, j], want, rtol=0, atol=1e-12)
+
+
+# ------------------------------------------------------ P4 cell mass
+def _tent_matrix(n_cells, n_pix):
+    c = (np.arange(n_pix) + 0.5) / 8 - 0.5
+    return np.maximum(0.0, 1.0 - np.abs(c[None, :] - np.arange(n_cells)[:, None]))
+
+
+def test_cell_mass_equals_tent_weighted_magnitude():
+    rng = np.random.default_rng(11)
+    U = rng.integers(0, 256, (150, 175)).astype(np.uint8)
+    for lv in hog.pyramid(150, 175):
+        L = hog.resample(U, lv)
+        gx, gy = hog.gradients(L)
+        mag = np.sqrt(gx * gx + gy * gy)[:8 * lv.cy, :8 * lv.cx]
+        want = _tent_matrix(lv.cy, 8 * lv.cy) @ mag @ _tent_matrix(lv.cx, 8 * lv.cx).T
+        got = hog.cell_histograms(L).sum(-1)
+        assert np.allclose(got, want, rtol=1e-12, atol=1e-9)
+
+
+# ------------------------------------------------------- P5 symmetries
+SIGNED_H = np.array([(9 - b) % 18 for b in range(18)])
+UNSIGNED_H = np.array([(9 - o) % 9 for o in range(9)])
+SIGNED_V = np.array([(18 - b) % 18 for b in range(18)])
+
+
+def _perm_h():
+    p = np.empty(31, np.int64)
+    p[:18] = SIGNED_H
+    p[18:27] = 18 + UNSIGNED_H
+    p[27:] = 27 + np.array([1, 0, 3, 2])
+    return p
+
+
+def _perm_v():
+    p = np.empty(31, np.int64)
+    p[:18] = SIGNED_V
+    p[18:27] = 18 + UNSIGNED_H
+    p[27:] = 27 + np.array([2, 3, 0, 1])
+    return p
+
+
+def _level0(U):
+    lv = hog.pyramid(*U.shape)[0]
+    L = hog.resample(U, lv)
+    hist = hog.cell_histograms(L)
+    return lv, hist, hog.features_from_hist(hist)
+
+
+def test_horizontal_flip_permutes_bins_and_features():
+    rng = np.random.default_rng(12)
+    U = rng.uniform(0, 255, (104, 120))        # continuous values: no exact ties
+    _, h1, F1 = _level0(U)
+    _, h2, F2 = _level0(U[:, ::-1])
+    p = _perm_h()
+    # F2[i][cx-1-j][p[ch]] == F1[i][j][ch]
+    assert np.allclose(h2[:, ::-1][..., SIGNED_H], h1, rtol=1e-12, atol=1e-10)
+    assert np.allclose(F2[:, ::-1][..., p], F1, rtol=1e-12, atol=1e-12)
+    W = rng.normal(0, 0.1, (1, 10, 10, 31))
+    Wf = np.empty_like(W)
+    Wf[0][:, :, p] = W[0][:, ::-1, :]          # W'[dr][dc'][p[ch]] = W[dr][9-dc'][ch]
+    S1 = hog.window_scores(F1, W, [0.1])
+    S2 = hog.window_scores(F2, Wf, [0.1])
+    assert np.allclose(S2[:, :, ::-1], S1, rtol=1e-12, atol=1e-12)
+
+
+def test_vertical_flip_and_contrast_inversion():
+    rng = np.random.default_rng(13)
+    U = rng.uniform(0, 255, (96, 112))
+    _, h1, F1 = _level0(U)
+    _, h2, F2 = _level0(U[::-1, :])
+    assert np.allclose(h2[::-1][..., SIGNED_V], h1, rtol=1e-12, atol=1e-10)
+    assert np.allclose(F2[::-1][..., _perm_v()], F1, rtol=1e-12, atol=1e-12)
+    _, h3, F3 = _level0(255.0 - U)
+    inv = np.array([(b + 9) % 18 for b in range(18)])
+    assert np.allclose(h3[..., inv], h1, rtol=1e-12, atol=1e-10)
+    assert np.allclose(F3[..., 18:], F1[..., 18:], rtol=1e-12, atol=1e-12)
+    assert np.allclose(F3[..., :18][..., inv], F1[..., :18], rtol=1e-12, atol=1e-12)
+
+
+# ------------------------------------------------ P6 scale invariance
+def test_contrast_scale_and_offset_invariance():
+    rng = np.random.default_rng(14)
+    U = rng.integers(20, 200, (112, 128)).astype(np.float64)
+    _, _, F = _level0(U)
+    _, _, F2 = _level0(2.0 * U)
+    _, _, F3 = _level0(U + 37.0)
+    assert np.allclose(F2, F, rtol=0, atol=1e-8)
+    assert np.array_equal(F3, F)
+
+
+# ----------------------------------------------------- P9 one-hot
+def test_one_hot_filter_reads_feature():
+    rng = np.random.default_rng(15)
+    F = rng.uniform(0, 0.4, (14, 17, 31))
+    for dr, dc, ch in [(0, 0, 0), (9, 9, 30), (3, 7, 12), (5, 0, 27)]:
+        W = np.zeros((1, 10, 10, 31))
+        W[0, dr, dc, ch] = 1.0
+        S = hog.window_scores(F, W, [-0.5])
+        assert np.array_equal(S[0], F[dr:dr + 5, dc:dc + 8, ch] - 0.5)
+    W1, W2 = rng.normal(0, 1, (2, 1, 10, 10, 31))
+    lin = hog.window_scores(F, W1 + W2, [0.0])
+    assert np.allclose(lin, hog.window_scores(F, W1, [0.0]) + hog.window_scores(F, W2, [0.0]),
+                       rtol=1e-12, atol=1e-12)
+
+
+# ------------------------------------------------------ boxes / NMS
+def test_window_box_level0_and_scaled():
+    lv = hog.pyramid(480, 640)
+    assert hog.window_box(lv[0], 3, 5) == (40, 24, 120, 104)
+    x0, y0, x1, y1 = hog.window_box(lv[1], 0, 0)     # s = 5/6: 80 px -> 96 px
+    assert (x0, y0, x1, y1) == (0, 0, 96, 96)
+    x0, _, x1, _ = hog.window_box(lv[2], 0, 1)       # 8*36/25 = 11.52 -> 12; 88*36/25 = 126.72 -> 127
+    assert (x0, x1) == (12, 127)
+
+
+def _cands(boxes, scores, f=None):
+    c = np.zeros(len(boxes), hog.CAND_DTYPE)
+    for i, (bx, s) in enumerate(zip(boxes, scores)):
+        c[i]["score"] = s
+        c[i]["c"] = i
+        c[i]["f"] = 0 if f is None else f[i]
+        c[i]["x0"], c[i]["y0"], c[i]["x1"], c[i]["y1"] = bx
+    return c
+
+
+def test_nms_hand_cases():
+    # same-level neighbours 1 and 2 cells apart: IoU 0.8182 and 0.6667 -> suppressed;
+    # 4 cells apart: 48*80 / (2*6400 - 3840) = 0.4286 -> kept
+    a, b1, b2, b4 = (0, 0, 80, 80), (8, 0, 88, 80), (16, 0, 96, 80), (32, 0, 112, 80)
+    assert len(hog.nms(_cands([a, b1], [2.0, 1.0]))) == 1
+    assert len(hog.nms(_cands([a, b2], [2.0, 1.0]))) == 1
+    assert len(hog.nms(_cands([a, b4], [2.0, 1.0]))) == 2
+    # exact IoU = 1/2 is not suppressed (strict >): I = 20*40 = 800,
+    # U = 1200 + 1200 - 800 = 1600
+    k = hog.nms(_cands([(0, 0, 30, 40), (10, 0, 40, 40)], [1.0, 0.5]))
+    assert len(k) == 2
+    # suppression chain: A > B > C, A suppresses B, B would suppress C but B is gone
+    A, B, C = (0, 0, 80, 80), (16, 0, 96, 80), (32, 0, 112, 80)
+    kept = hog.nms(_cands([A, B, C], [3.0, 2.0, 1.0]))
+    assert sorted(kept["c"].tolist()) == [0, 2]
+
+
+def test_nms_properties_random():
+    rng = np.random.default_rng(16)
+    n = 400
+    x0 = rng.integers(0, 300, n)
+    y0 = rng.integers(0, 200, n)
+    sz = rng.integers(60, 140, n)
+    boxes = list(zip(x0, y0, x0 + sz, y0 + sz))
+    scores = rng.normal(size=n)
+    c = _cands(boxes, scores)
+    kept = hog.nms(c)
+
+    def iou2(p, q):
+        iw = max(0, min(p["x1"], q["x1"]) - max(p["x0"], q["x0"]))
+        ih = max(0, min(p["y1"], q["y1"]) - max(p["y0"], q["y0"]))
+        inter = iw * ih
+        union = (p["x1"] - p["x0"]) * (p["y1"] - p["y0"]) + (q["x1"] - q["x0"]) * (q["y1"] - q["y0"]) - inter
+        return 2 * inter > union
+
+    for i in range(len(kept)):
+        for j in range(i + 1, len(kept)):
+            assert not iou2(kept[i], kept[j])
+    kept_ids = set(kept["c"].tolist())
+    for cand in c:
+        if cand["c"] in kept_ids:
+            continue
+        assert any(iou2(cand, k) and (k["score"] > cand["score"]) for k in kept)
+    assert np.array_equal(hog.nms(kept), kept)
+    perm = rng.permutation(n)
+    assert np.array_equal(hog.nms(c[perm]), kept)
+    assert np.all(np.diff(kept["score"]) <= 0)
