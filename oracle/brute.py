@@ -4,7 +4,8 @@ TEST INFRASTRUCTURE ONLY.  It pins the vectorised float64 oracle in
 ``oracle/hog.py`` by computing the same quantities a second way, written
 from the paper's description rather than from that module:
 
-* pyramid taps with exact rational arithmetic (``fractions.Fraction``);
+* pyramid taps with exact rational arithmetic (``fractions.Fraction``)
+  on the fixed-point inverse scale;
 * orientation from the gradient angle (``math.atan2``) as the nearest of
   the 18 directions 0, 20, ..., 340 degrees, instead of projections;
 * cell votes from the tent weight max(0, 1 - |distance to cell centre|)
@@ -32,10 +33,16 @@ def pyramid_sizes(h, w, upsample=1):
         k += 1
 
 
+def inverse_scale(s):
+    """1/s rounded half-up to a multiple of 2^-40."""
+    return Fraction(math.floor(Fraction(1, 1) / s * 2 ** 40 + Fraction(1, 2)), 2 ** 40)
+
+
 def taps(i, n_in, s):
     """Source taps of output sample i at scale s (pixel centres aligned,
-    weight of the second tap rounded half-up to 1/256)."""
-    xs = (Fraction(2 * i + 1, 2)) / s - Fraction(1, 2)
+    inverse scale in 2^-40 fixed point, weight of the second tap rounded
+    half-up to 1/256)."""
+    xs = Fraction(2 * i + 1, 2) * inverse_scale(s) - Fraction(1, 2)
     i0 = math.floor(xs)
     a = math.floor(256 * (xs - i0) + Fraction(1, 2))
     if a == 256:
@@ -146,8 +153,8 @@ def scores(F, W, b):
 def box(s, r, c):
     def rnd(v):
         return math.floor(v + Fraction(1, 2))
-    return (rnd(Fraction(8 * c) / s), rnd(Fraction(8 * r) / s),
-            rnd(Fraction(8 * c + 80) / s), rnd(Fraction(8 * r + 80) / s))
+    inv = inverse_scale(s)
+    return (rnd(8 * c * inv), rnd(8 * r * inv), rnd((8 * c + 80) * inv), rnd((8 * r + 80) * inv))
 
 
 def detect(U, W, b, thresh=0.0, iou=0.5, upsample=1):

@@ -84,23 +84,35 @@ def pyramid(h: int, w: int, upsample: int = 1) -> list[Level]:
         k += 1
 
 
-def axis_taps(n_out: int, n_in: int, p: int, q: int):
-    """Bilinear taps along one axis for scale p/q (R2).
+SIG_BITS = 40
+
+
+def inverse_scale_fixed(lv: Level) -> int:
+    """The inverse scale q/p of a level as a fixed-point integer with 40
+    fractional bits, rounded half-up (R2)."""
+    return (lv.q * (1 << (SIG_BITS + 1)) + lv.p) // (2 * lv.p)
+
+
+def axis_taps(n_out: int, n_in: int, lv: Level):
+    """Bilinear taps along one axis of level lv (R2).
 
     Output sample i sits at source coordinate (i + 1/2) * q/p - 1/2
-    (pixel centres aligned).  Its integer part i0 and the fractional part,
-    rounded half-up to a multiple of 1/256, give the taps i0 and i0 + 1
-    (clamped to the source) with weights (256 - a)/256 and a/256.  All of
-    it is exact integer arithmetic."""
+    (pixel centres aligned), with q/p taken as the fixed-point value SIG
+    of :func:`inverse_scale_fixed`: xs = ((2i + 1) * SIG - 2^40) / 2^41.
+    Its integer part i0 and the fractional part, rounded half-up to a
+    multiple of 1/256, give the taps i0 and i0 + 1 (clamped to the
+    source) with weights (256 - a)/256 and a/256.  All of it is exact
+    integer arithmetic."""
+    sig = inverse_scale_fixed(lv)
+    one = 1 << (SIG_BITS + 1)
     i0 = np.empty(n_out, np.int64)
     i1 = np.empty(n_out, np.int64)
     a8 = np.empty(n_out, np.int64)
-    den = 2 * p
     for i in range(n_out):
-        num = (2 * i + 1) * q - p
-        base = num // den                # floor, also for negative num
-        rem = num - base * den           # in [0, den)
-        a = (256 * rem + p) // (2 * p)   # round(256 * rem/den), halves up
+        t = (2 * i + 1) * sig - (1 << SIG_BITS)
+        base = t // one                  # floor, also for negative t
+        frac = t - base * one            # in [0, 2^41)
+        a = (256 * frac + one // 2) // one
         if a == 256:
             base, a = base + 1, 0
         i0[i] = min(max(base, 0), n_in - 1)
@@ -115,8 +127,8 @@ def resample(frame: np.ndarray, lv: Level) -> np.ndarray:
     below 256, so the float64 result is exact."""
     U = np.asarray(frame, np.float64)
     H, W = U.shape
-    y0, y1, ay = axis_taps(lv.h, H, lv.p, lv.q)
-    x0, x1, ax = axis_taps(lv.w, W, lv.p, lv.q)
+    y0, y1, ay = axis_taps(lv.h, H, lv)
+    x0, x1, ax = axis_taps(lv.w, W, lv)
     wy0, wy1 = (256 - ay) / 256.0, ay / 256.0
     wx0, wx1 = (256 - ax) / 256.0, ax / 256.0
     L = ((wy0[:, None] * wx0[None, :]) * U[np.ix_(y0, x0)]
@@ -129,8 +141,8 @@ def resample(frame: np.ndarray, lv: Level) -> np.ndarray:
 def resample_transpose(dL: np.ndarray, lv: Level, H: int, W: int) -> np.ndarray:
     """Adjoint of :func:`resample`: scatters level values back onto the
     frame with the same tap weights."""
-    y0, y1, ay = axis_taps(lv.h, H, lv.p, lv.q)
-    x0, x1, ax = axis_taps(lv.w, W, lv.p, lv.q)
+    y0, y1, ay = axis_taps(lv.h, H, lv)
+    x0, x1, ax = axis_taps(lv.w, W, lv)
     wy = ((256 - ay) / 256.0, ay / 256.0)
     wx = ((256 - ax) / 256.0, ax / 256.0)
     dU = np.zeros((H, W))
@@ -298,20 +310,20 @@ def window_scores(F: np.ndarray, W: np.ndarray, b: np.ndarray) -> np.ndarray:
     return S
 
 
-def _round_div(num, den):
-    """floor(num/den + 1/2) for non-negative integers (exact)."""
-    return (2 * num + den) // (2 * den)
-
-
 def window_box(lv: Level, r, c):
     """Half-open frame-pixel box of window (r, c) of level lv: the window
-    covers level pixels [8c, 8c+80) x [8r, 8r+80), mapped back by the exact
-    inverse scale q/p and rounded to the nearest integer (R12)."""
-    x0 = _round_div(8 * np.asarray(c, np.int64) * lv.q, lv.p)
-    x1 = _round_div((8 * np.asarray(c, np.int64) + 80) * lv.q, lv.p)
-    y0 = _round_div(8 * np.asarray(r, np.int64) * lv.q, lv.p)
-    y1 = _round_div((8 * np.asarray(r, np.int64) + 80) * lv.q, lv.p)
-    return x0, y0, x1, y1
+    covers level pixels [8c, 8c+80) x [8r, 8r+80); each edge is mapped back
+    by the fixed-point inverse scale SIG/2^40 and rounded half-up to an
+    integer (R12)."""
+    sig = inverse_scale_fixed(lv)
+    half = 1 << (SIG_BITS - 1)
+
+    def edge(v):
+        return (np.asarray(v, np.int64) * sig + half) >> SIG_BITS
+
+    c = np.asarray(c, np.int64)
+    r = np.asarray(r, np.int64)
+    return edge(8 * c), edge(8 * r), edge(8 * c + 80), edge(8 * r + 80)
 
 
 CAND_DTYPE = np.dtype([("score", "f8"), ("f", "i4"), ("k", "i4"), ("r", "i4"), ("c", "i4"),
