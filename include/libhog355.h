@@ -1,0 +1,193 @@
+/*
+ * libhog355 — HOG sliding-window face detection on AMD Instinct MI355X
+ * (gfx950), as a C ABI.
+ *
+ * The method is the HOG face detector of arXiv 2006.00816, Sec. IV-A
+ * ("Algorithm breakdown"): an image pyramid in 5/6 steps down to the
+ * 80x80 window, central-difference gradients discretised into 18 signed
+ * orientations, 18-bin histograms of 8x8-pixel cells with bilinear votes,
+ * normalisation by the energy of neighbouring 2x2-cell blocks into 31
+ * features per cell, a linear 10x10x31 filter per face rotation scored at
+ * every window, a threshold, and non-maximum suppression.  Sec. V-A
+ * describes the paper's GPU kernels for the same steps.
+ *
+ * Conventions for every entry point:
+ *  - Pointers are DEVICE pointers unless the comment says "host".
+ *  - The caller owns every buffer, including the workspace `ws`; the
+ *    library allocates no device memory in these calls.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = default stream)
+ *    and the call returns without waiting for it, except where noted.
+ *  - Return value: HOG_OK (0) when the work was enqueued, a negative
+ *    HOG_E_* code when the host-side checks rejected the arguments (then
+ *    nothing was enqueued).  HOG_E_HIP means a launch failed.  No
+ *    exception crosses the ABI.
+ *  - Frames are 8-bit grayscale, row-major, `pitch` bytes per row
+ *    (pitch >= w).  Sides are limited to 80 <= h, w <= 4096; smaller
+ *    frames have no pyramid level and yield no detections.
+ *  - Filters are float32 [nf][10][10][31] (row, column, channel of the
+ *    window), bias float32 [nf].  1 <= nf <= 32.
+ *  - Distinct workspaces may be used concurrently from several host
+ *    threads and streams; one workspace must not be used by two calls in
+ *    flight at the same time.
+ */
+#ifndef LIBHOG355_H
+#define LIBHOG355_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HOG_OK            0
+#define HOG_E_INVAL      -1   /* bad argument (null pointer, bad size, bad option) */
+#define HOG_E_TOO_LARGE  -2   /* frame side above 4096 px, or too many filters */
+#define HOG_E_WORKSPACE  -3   /* ws_bytes below hog_workspace_bytes() */
+#define HOG_E_CAP        -4   /* an output capacity argument is out of range */
+#define HOG_E_HIP        -5   /* a HIP launch or runtime call failed */
+#define HOG_E_NOTIMPL    -6
+
+#define HOG_MAX_SIDE     4096
+#define HOG_MAX_FILTERS  32
+#define HOG_MAX_LEVELS   28
+#define HOG_MAX_DETS     4096 /* largest per-frame detection capacity */
+
+/* Detection parameters (Sec. IV-A, classification and NMS). */
+typedef struct hog_params {
+    int32_t upsample;  /* 1, or 2 to start the pyramid at twice the frame size
+                          (Sec. III-B evaluates on 2x upscaled images) */
+    float   thresh;    /* a window is a candidate iff score > thresh (strict) */
+    float   iou;       /* greedy NMS drops a box whose IoU with a kept,
+                          better-ranked box exceeds iou (tested on integer
+                          areas as inter > iou * union) */
+} hog_params;
+
+/* One pyramid level.  Level k has scale s_k = upsample * (5/6)^k and size
+ * floor(h * s_k) x floor(w * s_k); levels continue while both sides are at
+ * least 80 px (Sec. IV-A).  Cells are 8x8 px: cy = h/8, cx = w/8.  A window
+ * is 10x10 cells anchored at its top-left cell: rows = cy-9, cols = cx-9
+ * anchors.  `sig` is the inverse scale 1/s_k in fixed point with 40
+ * fractional bits, rounded half-up; it defines the resampling taps and the
+ * mapping of window boxes back to frame pixels. */
+typedef struct hog_level {
+    int32_t k, h, w, cy, cx, rows, cols;
+    int32_t reserved;
+    int64_t sig;
+    int64_t feat_offset;   /* float offset of this level in hog_features() output */
+    int64_t score_offset;  /* float offset of this level in hog_scores() output */
+} hog_level;
+
+/* One detection: filter f of level k at window (row, col); the half-open
+ * box [x0, x1) x [y0, y1) is in frame pixels. */
+typedef struct hog_det {
+    int32_t frame, filter, level, row, col;
+    int32_t x0, y0, x1, y1;
+    float   score;
+} hog_det;
+
+/* Version of the library, as major*10000 + minor*100 + patch.  Host only. */
+int hog_version(void);
+
+/* Static string naming a status code.  Host only. */
+const char* hog_strerror(int status);
+
+/* The float64 direction table of the orientation decision, cos(o*pi/9) and
+ * sin(o*pi/9) for o = 0..8, each the double nearest to the exact value
+ * (host arrays of 9).  Sec. IV-A discretises the gradient into 18 signed
+ * directions; the decision picks the direction of largest |projection|.
+ * Host only. */
+int hog_orientation_table(double* cos9, double* sin9);
+
+/* The pyramid of an h x w frame (host output array `levels` of capacity
+ * max_levels; *n_levels receives the count, 0 for frames below 80 px).
+ * feat_offset/score_offset are filled for nf filters.  Host only. */
+int hog_pyramid(int h, int w, int upsample, int nf,
+                hog_level* levels, int max_levels, int* n_levels);
+
+/* Bytes of workspace needed by the calls below for n_frames frames of
+ * h x w and nf filters.  0 on invalid arguments.  Host only. */
+size_t hog_workspace_bytes(int h, int w, int upsample, int n_frames, int nf);
+
+/* 31-d features of every cell of every level (Sec. IV-A, gradient
+ * computation through feature computation; Sec. V-A, gradient-histogram,
+ * energy and feature kernels).  Output `feat` (float32, capacity feat_cap
+ * floats) holds level k at levels[k].feat_offset as [cy][cx][31]:
+ * 18 signed + 9 unsigned + 4 block-energy features. */
+int hog_features(const uint8_t* frame, int h, int w, int pitch, int upsample,
+                 float* feat, int64_t feat_cap,
+                 void* ws, size_t ws_bytes, void* stream);
+
+/* Window scores S_f(k, r, c) = bias_f + <filter_f, features of the 10x10
+ * window at (r, c) of level k> for every filter, level and window
+ * (Sec. IV-A, linear classification; Sec. V-A, classifier kernels).
+ * Output `scores` (float32, capacity scores_cap floats) holds level k at
+ * levels[k].score_offset as [nf][rows][cols]. */
+int hog_scores(const uint8_t* frame, int h, int w, int pitch, int upsample,
+               const float* filters, const float* bias, int nf,
+               float* scores, int64_t scores_cap,
+               void* ws, size_t ws_bytes, void* stream);
+
+/* Detect faces in one frame: features, scores, threshold, box mapping and
+ * NMS pooled over filters and levels (Sec. IV-A; Sec. V-A detection kernel
+ * and non-maximum suppression).  Writes up to `cap` detections (1 <= cap
+ * <= HOG_MAX_DETS) to `dets`, best first: score descending, then filter,
+ * level, row, column ascending.  `n_dets` (device int) receives the number
+ * of kept detections, which may exceed cap (extra rows are dropped). */
+int hog_detect(const hog_params* prm, const uint8_t* frame, int h, int w, int pitch,
+               const float* filters, const float* bias, int nf,
+               hog_det* dets, int cap, int* n_dets,
+               void* ws, size_t ws_bytes, void* stream);
+
+/* hog_detect for n frames of one size in one set of launches covering
+ * every frame and pyramid level (Sec. V-A, image combinations: an extra
+ * grid dimension selects the image).  Frame i starts at
+ * frames + i * frame_stride.  dets is [n][cap], n_dets is [n]. */
+int hog_detect_batch(const hog_params* prm, const uint8_t* frames, int n,
+                     int h, int w, int pitch, int64_t frame_stride,
+                     const float* filters, const float* bias, int nf,
+                     hog_det* dets, int cap, int* n_dets,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/* A hipGraph holding the launches of one hog_detect_batch call with fixed
+ * buffers, for replay.  The caller refreshes the frame buffer between
+ * replays.  Creation captures on `stream` and returns after instantiation;
+ * it enqueues no work.  Launch enqueues one replay on `stream`. */
+typedef struct hog_graph hog_graph;
+int hog_graph_create(hog_graph** out, const hog_params* prm, const uint8_t* frames, int n,
+                     int h, int w, int pitch, int64_t frame_stride,
+                     const float* filters, const float* bias, int nf,
+                     hog_det* dets, int cap, int* n_dets,
+                     void* ws, size_t ws_bytes, void* stream);
+int hog_graph_launch(hog_graph* g, void* stream);
+int hog_graph_destroy(hog_graph* g);
+
+/* Inspection of one pyramid level of one frame (test entry point).
+ * `level_px` (float32 [h_k][w_k]) receives the resampled level, `bins`
+ * (uint8 [h_k][w_k]) the orientation bin of every pixel (0 where the
+ * gradient is zero), `hist` (float32 [cy][cx][18]) the cell histograms.
+ * Any output may be NULL. */
+int hog_level_maps(const uint8_t* frame, int h, int w, int pitch, int upsample, int level,
+                   float* level_px, uint8_t* bins, float* hist,
+                   void* ws, size_t ws_bytes, void* stream);
+
+/* The orientation decision alone (test entry point): bins[i] for the
+ * integer gradient (gx[i], gy[i]) in units of 2^-16 (|gx|, |gy| < 2^24),
+ * n <= 2^31 - 1.  Sec. IV-A: one of eighteen signed directions. */
+int hog_orient_bins(const int32_t* gx, const int32_t* gy, int64_t n,
+                    uint8_t* bins, void* stream);
+
+/* Kernel timing with HIP events, for benchmarks.  While enabled, each
+ * launch of the library's kernels outside graph capture is bracketed by
+ * two events on its stream.  hog_profile_read synchronises on the recorded
+ * events and returns the summed milliseconds and the launch count of the
+ * kernel named `kernel` ("hist", "feat", "score", "nms", "geom").  Not
+ * thread-safe.  Host only. */
+int hog_profile_enable(int on);
+int hog_profile_reset(void);
+int hog_profile_read(const char* kernel, double* total_ms, int64_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIBHOG355_H */

@@ -1,0 +1,507 @@
+// C ABI of libhog355: argument checks, pyramid planning, workspace layout,
+// launch sequences, hipGraph capture and kernel timing.
+#include <string.h>
+
+#include <algorithm>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "hog_internal.h"
+
+using namespace hog;
+
+namespace {
+
+struct Plan {
+    LevelTable T;
+    int n = 0, nf = 0, groups = 0;
+    // workspace offsets (bytes)
+    size_t o_taps = 0, o_boxes = 0, o_bpack = 0, o_hist = 0, o_feat = 0, o_key = 0, o_state = 0, total = 0;
+    long long packed_floats = 0, dense_floats = 0;
+};
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+typedef __int128 i128;
+
+// Levels of an h x w frame: scale s_k = u 5^k / 6^k, size floor(h s_k) x
+// floor(w s_k), kept while both sides are >= 80 px (Sec. IV-A).
+int pyramid_levels(int h, int w, int u, int* hk, int* wk, long long* sig, int maxl) {
+    int n = 0;
+    i128 p = u, q = 1;
+    for (int k = 0; k < 64; ++k) {
+        const i128 hh = (i128)h * p / q, ww = (i128)w * p / q;
+        if (hh < MIN_SIDE || ww < MIN_SIDE) break;
+        if (n >= maxl) return -1;
+        hk[n] = (int)hh;
+        wk[n] = (int)ww;
+        // inverse scale q/p with 40 fractional bits, rounded half-up
+        sig[n] = (long long)((q * ((i128)1 << (SIG_BITS + 1)) + p) / (2 * p));
+        ++n;
+        p *= 5;
+        q *= 6;
+    }
+    return n;
+}
+
+int check_frame(int h, int w, int upsample) {
+    if (h <= 0 || w <= 0 || (upsample != 1 && upsample != 2)) return HOG_E_INVAL;
+    if (h > MAX_SIDE || w > MAX_SIDE) return HOG_E_TOO_LARGE;
+    return HOG_OK;
+}
+
+// Box side bounds of a level: an edge is round(v sig / 2^40), so a side of
+// 80 level px spans floor(80 s^-1) or ceil(80 s^-1) frame px; one more
+// pixel of slack on each side keeps the bounds conservative.
+void box_bounds(long long sig, int* lo, int* hi) {
+    const i128 num = (i128)80 * sig;
+    const long long fl = (long long)(num >> SIG_BITS);
+    *lo = (int)fl - 1;
+    *hi = (int)fl + 2;
+}
+
+int make_plan(int h, int w, int u, int n, int nf, Plan* P) {
+    int st = check_frame(h, w, u);
+    if (st) return st;
+    if (n < 1 || nf < 0) return HOG_E_INVAL;
+    if (nf > MAX_FILTERS) return HOG_E_TOO_LARGE;
+    int hk[MAX_LEVELS], wk[MAX_LEVELS];
+    long long sig[MAX_LEVELS];
+    const int nl = pyramid_levels(h, w, u, hk, wk, sig, MAX_LEVELS);
+    if (nl < 0) return HOG_E_TOO_LARGE;
+    LevelTable& T = P->T;
+    memset(&T, 0, sizeof(T));
+    T.n = nl;
+    T.h = h;
+    T.w = w;
+    T.upsample = u;
+    int taps = 0, boxes = 0, th = 0, tf = 0, ts = 0;
+    long long hist = 0, feat = 0, pos = 0, pk = 0, sc = 0;
+    for (int k = 0; k < nl; ++k) {
+        DevLevel& L = T.L[k];
+        L.k = k;
+        L.h = hk[k];
+        L.w = wk[k];
+        L.cy = hk[k] / CELL;
+        L.cx = wk[k] / CELL;
+        L.rows = L.cy - WIN + 1;
+        L.cols = L.cx - WIN + 1;
+        L.apr = (L.cols + SHIFT - 1) / SHIFT;
+        L.sig = sig[k];
+        L.tap_y = taps;
+        taps += L.h;
+        L.tap_x = taps;
+        taps += L.w;
+        L.box_r = boxes;
+        boxes += L.rows;
+        L.box_c = boxes;
+        boxes += L.cols;
+        L.hist_off = (int)hist;
+        hist += (long long)L.cy * L.cx;
+        L.feat_off = (int)feat;
+        feat += (long long)L.cy * (L.cx + 2) * FPAD;
+        L.pos_off = (int)pos;
+        pos += (long long)L.rows * L.cols;
+        L.pk_off = (int)pk;
+        pk += (long long)L.cy * L.cx * NFEAT;
+        L.sc_off = (int)sc;
+        sc += (long long)(nf > 0 ? nf : 1) * L.rows * L.cols;
+        L.th_off = th;
+        th += ((L.cy + TCY - 1) / TCY) * ((L.cx + TCX - 1) / TCX);
+        L.tf_off = tf;
+        tf += (L.cy * (L.cx + 2) + FEAT_THREADS - 1) / FEAT_THREADS;
+        L.ts_off = ts;
+        ts += (L.rows * L.apr + ANCHORS_PER_WG - 1) / ANCHORS_PER_WG;
+        box_bounds(L.sig, &L.wmin, &L.wmax);
+        L.hmin = L.wmin;
+        L.hmax = L.wmax;
+    }
+    if (feat > 0x7fffffffLL || hist > 0x7fffffffLL / HSTRIDE || pk > 0x7fffffffLL || sc > 0x7fffffffLL)
+        return HOG_E_TOO_LARGE;
+    // levels whose boxes can reach IoU > 1/2 with this level's boxes: the
+    // IoU of two boxes is at most (smaller area) / (larger area)
+    for (int k = 0; k < nl; ++k) {
+        DevLevel& L = T.L[k];
+        L.nms_klo = k;
+        L.nms_khi = k;
+        for (int k2 = 0; k2 < nl; ++k2) {
+            const DevLevel& M = T.L[k2];
+            const long long amax_s = (long long)std::min(L.wmax, M.wmax) * std::min(L.hmax, M.hmax);
+            const long long amin_b = (long long)std::max(L.wmin, M.wmin) * std::max(L.hmin, M.hmin);
+            if (2 * amax_s > amin_b) {
+                L.nms_klo = std::min(L.nms_klo, k2);
+                L.nms_khi = std::max(L.nms_khi, k2);
+            }
+        }
+    }
+    T.th_total = th;
+    T.tf_total = tf;
+    T.ts_total = ts;
+    T.hist_frame = (int)hist;
+    T.feat_frame = (int)feat;
+    T.pos_frame = (int)pos;
+    T.taps_total = taps;
+    T.boxes_total = boxes;
+    P->n = n;
+    P->nf = nf;
+    P->groups = nf > 0 ? (nf + FGROUP - 1) / FGROUP : 0;
+    P->packed_floats = pk;
+    P->dense_floats = sc;
+    size_t o = 0;
+    P->o_taps = o;
+    o = align256(o + sizeof(int4) * (size_t)std::max(taps, 1));
+    P->o_boxes = o;
+    o = align256(o + sizeof(int2) * (size_t)std::max(boxes, 1));
+    P->o_bpack = o;
+    o = align256(o + sizeof(float4) * (size_t)std::max(P->groups, 1) * BPACK_PER_GROUP);
+    P->o_hist = o;
+    o = align256(o + sizeof(float) * (size_t)n * std::max(hist, 1LL) * HSTRIDE);
+    P->o_feat = o;
+    o = align256(o + sizeof(float) * (size_t)n * std::max(feat, 1LL));
+    P->o_key = o;
+    o = align256(o + sizeof(unsigned long long) * (size_t)n * std::max(pos, 1LL));
+    P->o_state = o;
+    o = align256(o + sizeof(int) * (size_t)n * std::max(pos, 1LL));
+    P->total = o;
+    return HOG_OK;
+}
+
+template <class T>
+T* at(void* ws, size_t off) {
+    return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+// ------------------------------------------------------------ profiling
+struct ProfRec {
+    std::string name;
+    hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+
+bool capturing(hipStream_t s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) return false;
+    return cs != hipStreamCaptureStatusNone;
+}
+
+template <class F>
+int timed(const char* name, hipStream_t s, F&& launch) {
+    const bool prof = g_prof_on && !capturing(s);
+    ProfRec rec;
+    if (prof) {
+        rec.name = name;
+        if (hipEventCreate(&rec.a) != hipSuccess || hipEventCreate(&rec.b) != hipSuccess) return HOG_E_HIP;
+        if (hipEventRecord(rec.a, s) != hipSuccess) return HOG_E_HIP;
+    }
+    if (launch() != hipSuccess) return HOG_E_HIP;
+    if (prof) {
+        if (hipEventRecord(rec.b, s) != hipSuccess) return HOG_E_HIP;
+        std::lock_guard<std::mutex> g(g_prof_mu);
+        g_prof.push_back(rec);
+    }
+    return HOG_OK;
+}
+
+#define HOG_TRY(x)                 \
+    do {                           \
+        const int _st = (x);       \
+        if (_st != HOG_OK) return _st; \
+    } while (0)
+
+int check_ws(const Plan& P, void* ws, size_t ws_bytes) {
+    if (!ws) return HOG_E_INVAL;
+    if (ws_bytes < P.total) return HOG_E_WORKSPACE;
+    return HOG_OK;
+}
+
+int run_pixels(const Plan& P, const uint8_t* frames, long long fstride, int pitch, void* ws, float* packed,
+               const float* filters, hipStream_t s, bool zero_keys) {
+    const LevelTable& T = P.T;
+    HOG_TRY(timed("geom", s, [&] {
+        return launch_setup(T, at<int4>(ws, P.o_taps), at<int2>(ws, P.o_boxes), filters, P.nf,
+                            at<float4>(ws, P.o_bpack), zero_keys ? at<unsigned long long>(ws, P.o_key) : nullptr,
+                            (long long)P.n * T.pos_frame, s);
+    }));
+    HOG_TRY(timed("hist", s, [&] {
+        return launch_hist(T, frames, fstride, pitch, P.n, at<int4>(ws, P.o_taps), at<float>(ws, P.o_hist), s);
+    }));
+    HOG_TRY(timed("feat", s, [&] {
+        return launch_feat(T, P.n, at<float>(ws, P.o_hist), at<float>(ws, P.o_feat), packed, s);
+    }));
+    return HOG_OK;
+}
+
+int detect_sequence(const Plan& P, const hog_params* prm, const uint8_t* frames, long long fstride, int pitch,
+                    const float* filters, const float* bias, hog_det* dets, int cap, int* n_dets, void* ws,
+                    hipStream_t s) {
+    const LevelTable& T = P.T;
+    if (T.n == 0) {
+        // no pyramid level: zero detections for every frame
+        return timed("fill", s, [&] { return launch_fill(n_dets, P.n, 0, s); });
+    }
+    const bool multi = P.groups > 1;
+    HOG_TRY(run_pixels(P, frames, fstride, pitch, ws, nullptr, filters, s, multi));
+    HOG_TRY(timed("score", s, [&] {
+        return launch_score(T, P.n, at<float>(ws, P.o_feat), at<float4>(ws, P.o_bpack), bias, P.nf, prm->thresh,
+                            nullptr, at<unsigned long long>(ws, P.o_key), multi, s);
+    }));
+    // iou (a float32 in [2^-10, 1)) as the exact binary fraction num / 2^e,
+    // e <= 34, so that inter * 2^e stays below 2^63
+    double v = prm->iou;
+    int e = 0;
+    while (v != (double)(long long)v) {
+        v *= 2.0;
+        ++e;
+    }
+    const long long num = (long long)v, den = 1LL << e;
+    HOG_TRY(timed("nms", s, [&] {
+        return launch_nms(T, P.n, at<unsigned long long>(ws, P.o_key), at<int>(ws, P.o_state),
+                          at<int2>(ws, P.o_boxes), num, den, dets, cap, n_dets, s);
+    }));
+    return HOG_OK;
+}
+
+int check_detect_args(const hog_params* prm, const void* frames, int pitch, int w, const float* filters,
+                      const float* bias, int nf, const hog_det* dets, int cap, const int* n_dets) {
+    if (!prm || !frames || !filters || !bias || !dets || !n_dets) return HOG_E_INVAL;
+    if (pitch < w) return HOG_E_INVAL;
+    if (nf < 1) return HOG_E_INVAL;
+    if (nf > MAX_FILTERS) return HOG_E_TOO_LARGE;
+    if (cap < 1 || cap > MAX_DETS) return HOG_E_CAP;
+    if (!(prm->iou >= 0x1p-10f && prm->iou < 1.f)) return HOG_E_INVAL;
+    if (prm->thresh != prm->thresh) return HOG_E_INVAL;
+    return HOG_OK;
+}
+
+}  // namespace
+
+struct hog_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+int hog_version(void) { return 100; }
+
+const char* hog_strerror(int st) {
+    switch (st) {
+        case HOG_OK: return "ok";
+        case HOG_E_INVAL: return "invalid argument";
+        case HOG_E_TOO_LARGE: return "frame or filter count above the supported maximum";
+        case HOG_E_WORKSPACE: return "workspace smaller than hog_workspace_bytes()";
+        case HOG_E_CAP: return "output capacity out of range";
+        case HOG_E_HIP: return "HIP launch or runtime failure";
+        case HOG_E_NOTIMPL: return "not implemented";
+        default: return "unknown status";
+    }
+}
+
+int hog_orientation_table(double* c, double* s) {
+    if (!c || !s) return HOG_E_INVAL;
+    orientation_table_host(c, s);
+    return HOG_OK;
+}
+
+int hog_pyramid(int h, int w, int upsample, int nf, hog_level* levels, int max_levels, int* n_levels) {
+    if (!n_levels || (max_levels > 0 && !levels)) return HOG_E_INVAL;
+    Plan P;
+    HOG_TRY(make_plan(h, w, upsample, 1, nf < 0 ? 0 : nf, &P));
+    *n_levels = P.T.n;
+    for (int k = 0; k < P.T.n && k < max_levels; ++k) {
+        const DevLevel& L = P.T.L[k];
+        hog_level& o = levels[k];
+        o.k = k;
+        o.h = L.h;
+        o.w = L.w;
+        o.cy = L.cy;
+        o.cx = L.cx;
+        o.rows = L.rows;
+        o.cols = L.cols;
+        o.reserved = 0;
+        o.sig = L.sig;
+        o.feat_offset = L.pk_off;
+        o.score_offset = L.sc_off;
+    }
+    return P.T.n > max_levels ? HOG_E_CAP : HOG_OK;
+}
+
+size_t hog_workspace_bytes(int h, int w, int upsample, int n_frames, int nf) {
+    Plan P;
+    if (make_plan(h, w, upsample, n_frames, nf, &P) != HOG_OK) return 0;
+    return P.total;
+}
+
+int hog_features(const uint8_t* frame, int h, int w, int pitch, int upsample, float* feat, int64_t feat_cap,
+                 void* ws, size_t ws_bytes, void* stream) {
+    if (!frame || !feat || pitch < w) return HOG_E_INVAL;
+    Plan P;
+    HOG_TRY(make_plan(h, w, upsample, 1, 0, &P));
+    HOG_TRY(check_ws(P, ws, ws_bytes));
+    if (feat_cap < P.packed_floats) return HOG_E_CAP;
+    if (P.T.n == 0) return HOG_OK;
+    return run_pixels(P, frame, 0, pitch, ws, feat, nullptr, (hipStream_t)stream, false);
+}
+
+int hog_scores(const uint8_t* frame, int h, int w, int pitch, int upsample, const float* filters,
+               const float* bias, int nf, float* scores, int64_t scores_cap, void* ws, size_t ws_bytes,
+               void* stream) {
+    if (!frame || !filters || !bias || !scores || pitch < w || nf < 1) return HOG_E_INVAL;
+    Plan P;
+    HOG_TRY(make_plan(h, w, upsample, 1, nf, &P));
+    HOG_TRY(check_ws(P, ws, ws_bytes));
+    if (scores_cap < P.dense_floats) return HOG_E_CAP;
+    if (P.T.n == 0) return HOG_OK;
+    hipStream_t s = (hipStream_t)stream;
+    HOG_TRY(run_pixels(P, frame, 0, pitch, ws, nullptr, filters, s, false));
+    return timed("score", s, [&] {
+        return launch_score(P.T, 1, at<float>(ws, P.o_feat), at<float4>(ws, P.o_bpack), bias, nf, 0.f, scores,
+                            nullptr, false, s);
+    });
+}
+
+int hog_detect_batch(const hog_params* prm, const uint8_t* frames, int n, int h, int w, int pitch,
+                     int64_t frame_stride, const float* filters, const float* bias, int nf, hog_det* dets, int cap,
+                     int* n_dets, void* ws, size_t ws_bytes, void* stream) {
+    HOG_TRY(check_detect_args(prm, frames, pitch, w, filters, bias, nf, dets, cap, n_dets));
+    if (n < 1 || (n > 1 && frame_stride < (int64_t)pitch * h)) return HOG_E_INVAL;
+    Plan P;
+    HOG_TRY(make_plan(h, w, prm->upsample, n, nf, &P));
+    HOG_TRY(check_ws(P, ws, ws_bytes));
+    return detect_sequence(P, prm, frames, frame_stride, pitch, filters, bias, dets, cap, n_dets, ws,
+                           (hipStream_t)stream);
+}
+
+int hog_detect(const hog_params* prm, const uint8_t* frame, int h, int w, int pitch, const float* filters,
+               const float* bias, int nf, hog_det* dets, int cap, int* n_dets, void* ws, size_t ws_bytes,
+               void* stream) {
+    return hog_detect_batch(prm, frame, 1, h, w, pitch, 0, filters, bias, nf, dets, cap, n_dets, ws, ws_bytes,
+                            stream);
+}
+
+int hog_graph_create(hog_graph** out, const hog_params* prm, const uint8_t* frames, int n, int h, int w,
+                     int pitch, int64_t frame_stride, const float* filters, const float* bias, int nf,
+                     hog_det* dets, int cap, int* n_dets, void* ws, size_t ws_bytes, void* stream) {
+    if (!out) return HOG_E_INVAL;
+    *out = nullptr;
+    HOG_TRY(check_detect_args(prm, frames, pitch, w, filters, bias, nf, dets, cap, n_dets));
+    if (n < 1 || (n > 1 && frame_stride < (int64_t)pitch * h)) return HOG_E_INVAL;
+    Plan P;
+    HOG_TRY(make_plan(h, w, prm->upsample, n, nf, &P));
+    HOG_TRY(check_ws(P, ws, ws_bytes));
+    hipStream_t cs = (hipStream_t)stream;
+    bool own = false;
+    if (!cs) {
+        if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return HOG_E_HIP;
+        own = true;
+    }
+    hog_graph* g = new hog_graph();
+    int st = HOG_OK;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        st = HOG_E_HIP;
+    } else {
+        st = detect_sequence(P, prm, frames, frame_stride, pitch, filters, bias, dets, cap, n_dets, ws, cs);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(cs, &graph);
+        if (st == HOG_OK && e != hipSuccess) st = HOG_E_HIP;
+        g->graph = graph;
+        if (st == HOG_OK && hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess)
+            st = HOG_E_HIP;
+    }
+    if (own) (void)hipStreamDestroy(cs);
+    if (st != HOG_OK) {
+        hog_graph_destroy(g);
+        return st;
+    }
+    *out = g;
+    return HOG_OK;
+}
+
+int hog_graph_launch(hog_graph* g, void* stream) {
+    if (!g || !g->exec) return HOG_E_INVAL;
+    return hipGraphLaunch(g->exec, (hipStream_t)stream) == hipSuccess ? HOG_OK : HOG_E_HIP;
+}
+
+int hog_graph_destroy(hog_graph* g) {
+    if (!g) return HOG_E_INVAL;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return HOG_OK;
+}
+
+int hog_level_maps(const uint8_t* frame, int h, int w, int pitch, int upsample, int level, float* level_px,
+                   uint8_t* bins, float* hist, void* ws, size_t ws_bytes, void* stream) {
+    if (!frame || pitch < w) return HOG_E_INVAL;
+    Plan P;
+    HOG_TRY(make_plan(h, w, upsample, 1, 0, &P));
+    HOG_TRY(check_ws(P, ws, ws_bytes));
+    if (level < 0 || level >= P.T.n) return HOG_E_INVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const LevelTable& T = P.T;
+    HOG_TRY(timed("geom", s, [&] {
+        return launch_setup(T, at<int4>(ws, P.o_taps), at<int2>(ws, P.o_boxes), nullptr, 0, nullptr, nullptr, 0, s);
+    }));
+    if (level_px || bins) {
+        HOG_TRY(timed("maps", s, [&] {
+            return launch_level_maps(T, level, frame, pitch, at<int4>(ws, P.o_taps), level_px, bins, s);
+        }));
+    }
+    if (hist) {
+        HOG_TRY(timed("hist", s, [&] {
+            return launch_hist(T, frame, 0, pitch, 1, at<int4>(ws, P.o_taps), at<float>(ws, P.o_hist), s);
+        }));
+        const DevLevel& L = T.L[level];
+        const float* src = at<float>(ws, P.o_hist) + (size_t)L.hist_off * HSTRIDE;
+        if (hipMemcpy2DAsync(hist, NBINS * sizeof(float), src, HSTRIDE * sizeof(float), NBINS * sizeof(float),
+                             (size_t)L.cy * L.cx, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return HOG_E_HIP;
+    }
+    return HOG_OK;
+}
+
+int hog_orient_bins(const int32_t* gx, const int32_t* gy, int64_t n, uint8_t* bins, void* stream) {
+    if (n < 0 || n > 0x7fffffffLL) return HOG_E_INVAL;
+    if (n > 0 && (!gx || !gy || !bins)) return HOG_E_INVAL;
+    return launch_orient(gx, gy, n, bins, (hipStream_t)stream) == hipSuccess ? HOG_OK : HOG_E_HIP;
+}
+
+int hog_profile_enable(int on) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof_on = on != 0;
+    return HOG_OK;
+}
+
+int hog_profile_reset(void) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    for (auto& r : g_prof) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    g_prof.clear();
+    return HOG_OK;
+}
+
+int hog_profile_read(const char* kernel, double* total_ms, int64_t* count) {
+    if (!kernel || !total_ms || !count) return HOG_E_INVAL;
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    double tot = 0.0;
+    int64_t cnt = 0;
+    for (auto& r : g_prof) {
+        if (r.name != kernel) continue;
+        if (hipEventSynchronize(r.b) != hipSuccess) return HOG_E_HIP;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return HOG_E_HIP;
+        tot += ms;
+        ++cnt;
+    }
+    *total_ms = tot;
+    *count = cnt;
+    return HOG_OK;
+}
+
+}  // extern "C"

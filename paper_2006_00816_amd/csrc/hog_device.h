@@ -1,0 +1,113 @@
+// Device helpers shared by the gfx950 kernels.
+#pragma once
+
+#include "hog_internal.h"
+
+namespace hog {
+
+// cos(o*pi/9), sin(o*pi/9) for o = 0..8 as the doubles nearest to the exact
+// values.  Correct rounding keeps the table mirror-symmetric:
+// cos(pi - a) = -cos(a) and sin(pi - a) = sin(a) hold bit for bit.
+#define HOG_C1 0.9396926207859083840541093
+#define HOG_C2 0.7660444431189780352023927
+#define HOG_C4 0.1736481776669303488517166
+#define HOG_S1 0.3420201433256687330440996
+#define HOG_S2 0.6427876096865393263226434
+#define HOG_S3 0.8660254037844386467637232
+#define HOG_S4 0.984807753012208059366743
+
+static __device__ __host__ inline double dir_cos(int o) {
+    switch (o) {
+        case 0: return 1.0;
+        case 1: return HOG_C1;
+        case 2: return HOG_C2;
+        case 3: return 0.5;
+        case 4: return HOG_C4;
+        case 5: return -HOG_C4;
+        case 6: return -0.5;
+        case 7: return -HOG_C2;
+        default: return -HOG_C1;
+    }
+}
+static __device__ __host__ inline double dir_sin(int o) {
+    switch (o) {
+        case 0: return 0.0;
+        case 1: case 8: return HOG_S1;
+        case 2: case 7: return HOG_S2;
+        case 3: case 6: return HOG_S3;
+        default: return HOG_S4;
+    }
+}
+
+// Reference decision in float64: the projections d_o = gx*c_o + gy*s_o are
+// formed as two rounded products and a rounded sum (no fused multiply-add);
+// scanning o = 0..8 from best = 0, d_o > best picks bin o and -d_o > best
+// picks the opposite bin o + 9.  Gradients are integers in units of 2^-16;
+// a power-of-two scale changes no rounding, so they are used as is.
+static __device__ __noinline__ int orient_bin_f64(int gxi, int gyi) {
+#pragma clang fp contract(off)
+    const double gx = (double)gxi, gy = (double)gyi;
+    double best = 0.0;
+    int bin = 0;
+#pragma unroll
+    for (int o = 0; o < NORIENT; ++o) {
+        const double px = gx * dir_cos(o);
+        const double py = gy * dir_sin(o);
+        const double d = px + py;
+        if (d > best) {
+            best = d;
+            bin = o;
+        } else if (-d > best) {
+            best = -d;
+            bin = o + NORIENT;
+        }
+    }
+    return bin;
+}
+
+// Orientation bin of an integer gradient (0 for a zero gradient).
+//
+// Fast path: fold the gradient into the first quadrant (|gx|, |gy|) and
+// count how many of the sector boundaries 10, 30, 50, 70 degrees lie below
+// its angle, from the signs of t_b = |gy| cos b - |gx| sin b; unfold by the
+// signs of gx, gy (an angle of exactly 90 or 270 degrees goes to bin 4 or
+// 13, the first of the two tied directions).  In float32 each t_b carries
+// an error below 2e-7 (|gx| + |gy|); when every |t_b| exceeds 1e-6 (|gx| +
+// |gy|) the signs are exact and the float64 scan above, whose own error is
+// some 1e-16 of the magnitude, picks the same bin.  Otherwise the float64
+// scan itself decides.
+static __device__ inline int orient_bin(int gxi, int gyi) {
+    const float ax = fabsf((float)gxi), ay = fabsf((float)gyi);
+    const float t0 = fmaf(ay, 0.984807753012f, -ax * 0.173648177667f);
+    const float t1 = fmaf(ay, 0.866025403784f, -ax * 0.5f);
+    const float t2 = fmaf(ay, 0.642787609687f, -ax * 0.766044443119f);
+    const float t3 = fmaf(ay, 0.342020143326f, -ax * 0.939692620786f);
+    const float m = fminf(fminf(fabsf(t0), fabsf(t1)), fminf(fabsf(t2), fabsf(t3)));
+    if (m <= 1e-6f * (ax + ay)) return orient_bin_f64(gxi, gyi);
+    const int j = (t0 > 0.f) + (t1 > 0.f) + (t2 > 0.f) + (t3 > 0.f);
+    const bool upper = (gyi > 0) || (gyi == 0 && gxi > 0);
+    if (upper) return gxi >= 0 ? j : NORIENT - j;
+    return gxi <= 0 ? NORIENT + j : (NBINS - j) % NBINS;
+}
+
+// Fixed-point resampling tap: returns {i0, i1, a8, 0} for output index i
+// of an axis with n_in source samples at inverse scale sig (40 fractional
+// bits): source coordinate ((2i+1) sig - 2^40) / 2^41, weight a8/256 on
+// the second tap, rounded half-up; taps clamped to the source.
+static __device__ inline int4 axis_tap(int i, int n_in, long long sig) {
+    const long long t = (long long)(2 * i + 1) * sig - (1LL << SIG_BITS);
+    long long base = t >> (SIG_BITS + 1);                       // floor
+    const long long frac = t - (base << (SIG_BITS + 1));        // [0, 2^41)
+    int a = (int)((frac + (1LL << 32)) >> 33);                  // round(256 frac / 2^41)
+    if (a == 256) { base += 1; a = 0; }
+    const int i0 = (int)min(max(base, 0LL), (long long)(n_in - 1));
+    const int i1 = (int)min(max(base + 1, 0LL), (long long)(n_in - 1));
+    return make_int4(i0, i1, a, 0);
+}
+
+// Frame-pixel edge of level-pixel coordinate v: round(v * sig / 2^40).
+static __device__ inline int box_edge(long long v, long long sig) {
+    return (int)((v * sig + (1LL << (SIG_BITS - 1))) >> SIG_BITS);
+}
+
+}  // namespace hog

@@ -1,0 +1,124 @@
+// Internal definitions shared by the host library and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "libhog355.h"
+
+namespace hog {
+
+constexpr int CELL = 8;        // 8x8-pixel cells
+constexpr int NBINS = 18;      // signed orientation bins
+constexpr int NORIENT = 9;     // unsigned orientations
+constexpr int WIN = 10;        // window side in cells
+constexpr int NFEAT = 31;      // features per cell
+constexpr int FPAD = 32;       // features per cell in the internal layout (31 + zero)
+constexpr int HSTRIDE = 20;    // internal histogram record: 18 bins, energy, zero
+constexpr int MIN_SIDE = 80;
+constexpr int SIG_BITS = 40;   // fractional bits of the fixed-point inverse scale
+constexpr int MAX_LEVELS = 28;
+constexpr int MAX_SIDE = 4096;
+constexpr int MAX_FILTERS = 32;
+constexpr int MAX_DETS = 4096;
+
+// Histogram kernel tile: TCY x TCX complete cells per workgroup, from
+// (TCY+1) x (TCX+1) "quad blocks" of 8x8 pixels.  A quad block spans the
+// pixels between four neighbouring cell centres, so all its pixels vote
+// into the same four cells with weights that depend only on the pixel's
+// offset inside the block.
+constexpr int TCY = 7, TCX = 15;
+constexpr int QBY = TCY + 1, QBX = TCX + 1;     // 8 x 16 quad blocks
+constexpr int TPY = 8 * QBY + 2, TPX = 8 * QBX + 2;  // 66 x 130 level pixels incl. 1-px halo
+constexpr int HIST_THREADS = 256;
+
+constexpr int FEAT_THREADS = 256;
+
+// Window scoring: each wave scores 4 MFMA M-tiles of 16 "anchors"; an
+// anchor is 3 horizontally adjacent windows; a filter group is 5 filters.
+// The 16 MFMA N columns are (filter, shift) = 5 x 3 (+1 unused).
+constexpr int SHIFT = 3;
+constexpr int FGROUP = 5;
+constexpr int KROW = (WIN + SHIFT - 1) * FPAD;   // 384 K values per window row
+constexpr int KK = KROW / 16;                    // 24 chunks of 16 K values
+constexpr int SCORE_THREADS = 256;
+constexpr int ANCHORS_PER_WAVE = 64;
+constexpr int ANCHORS_PER_WG = ANCHORS_PER_WAVE * SCORE_THREADS / 64;
+constexpr int BPACK_PER_GROUP = WIN * KK * 64;   // float4 entries per filter group
+
+constexpr int NMS_THREADS = 1024;
+constexpr int SORT_CAP = 4096;
+
+struct DevLevel {
+    int h, w, cy, cx;
+    int rows, cols, apr, k;       // apr: anchors per window row = ceil(cols / 3)
+    long long sig;                // inverse scale, 40 fractional bits
+    int tap_y, tap_x;             // offsets (int4 units) of the row / column taps
+    int box_r, box_c;             // offsets (int2 units) of the row / column box edges
+    int hist_off;                 // cell offset inside one frame's histogram block
+    int feat_off;                 // float offset inside one frame's feature block
+    int pos_off;                  // window-position offset inside one frame
+    int pk_off;                   // float offset of the packed [cy][cx][31] features (one frame)
+    int sc_off;                   // float offset of the dense scores [nf][rows][cols] (one frame)
+    int th_off, tf_off, ts_off;   // first workgroup of this level in the hist / feat / score grids
+    int nms_klo, nms_khi;         // levels whose boxes can overlap this level's boxes with IoU > 1/2
+    int wmin, wmax, hmin, hmax;   // bounds of this level's box widths / heights (frame px)
+};
+
+struct LevelTable {
+    int n;                        // number of levels
+    int th_total, tf_total, ts_total;
+    int hist_frame;               // cells per frame
+    int feat_frame;               // floats per frame (padded layout)
+    int pos_frame;                // window positions per frame
+    int taps_total, boxes_total;  // geometry table entries
+    int h, w, upsample;
+    DevLevel L[MAX_LEVELS];
+};
+
+static_assert(sizeof(LevelTable) <= 3600, "kernel argument block too large");
+
+// Device-side lookup of the level owning workgroup index `b` for a prefix
+// field (th_off / tf_off / ts_off).
+#define HOG_FIND_LEVEL(T, b, field)                                      \
+    ({ int _k = 0;                                                       \
+       while (_k + 1 < (T).n && (T).L[_k + 1].field <= (b)) ++_k;        \
+       _k; })
+
+// Candidate key: higher value = higher rank.  High word: the score mapped
+// to an unsigned integer with the same order; low word: the bitwise NOT of
+// (filter, level, row, column) so that smaller indices rank higher.
+__host__ __device__ inline unsigned int score_order(float s) {
+    unsigned int u = __builtin_bit_cast(unsigned int, s);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__host__ __device__ inline float score_from_order(unsigned int o) {
+    unsigned int u = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
+    return __builtin_bit_cast(float, u);
+}
+__host__ __device__ inline unsigned int pack_window(int f, int k, int r, int c) {
+    return ((unsigned)f << 27) | ((unsigned)k << 22) | ((unsigned)r << 11) | (unsigned)c;
+}
+
+// Launchers (host functions defined next to their kernels).
+hipError_t launch_setup(const LevelTable& T, int4* taps, int2* boxes,
+                        const float* filters, int nf, float4* bpack,
+                        unsigned long long* poskey_zero, long long poskey_count, hipStream_t s);
+hipError_t launch_hist(const LevelTable& T, const uint8_t* frames, long long fstride, int pitch,
+                       int n, const int4* taps, float* hist, hipStream_t s);
+hipError_t launch_feat(const LevelTable& T, int n, const float* hist, float* feat,
+                       float* packed, hipStream_t s);
+hipError_t launch_score(const LevelTable& T, int n, const float* feat, const float4* bpack,
+                        const float* bias, int nf, float thresh, float* dense,
+                        unsigned long long* poskey, bool atomic_key, hipStream_t s);
+hipError_t launch_nms(const LevelTable& T, int n, const unsigned long long* poskey, int* state,
+                      const int2* boxes, long long iou_num, long long iou_den,
+                      void* dets, int cap, int* n_dets, hipStream_t s);
+hipError_t launch_level_maps(const LevelTable& T, int level, const uint8_t* frame, int pitch,
+                             const int4* taps, float* level_px, uint8_t* bins, hipStream_t s);
+hipError_t launch_orient(const int32_t* gx, const int32_t* gy, long long n, uint8_t* bins,
+                         hipStream_t s);
+hipError_t launch_fill(int* p, int n, int v, hipStream_t s);
+void orientation_table_host(double* c, double* s);
+
+}  // namespace hog

@@ -1,0 +1,208 @@
+// Pyramid resampling, gradients, orientation and cell histograms
+// (Sec. IV-A: image pyramid, gradient computation, histogramisation;
+// Sec. V-A: image-scaling and gradient-histogram kernels), fused into one
+// kernel per tile of cells.
+#include "hog_device.h"
+
+namespace hog {
+
+// Level-pixel tile in LDS, swizzled so that the 64 lanes of a wave, which
+// read the same offset (oy, ox) inside 64 different 8x8 pixel blocks, hit
+// 64 different banks: plane (ty % 8, tx % 8), then (ty / 8, tx / 8).
+constexpr int PL_W = TPX / 8 + 1;                 // 17 block columns
+constexpr int PL_H = TPY / 8 + 1;                 // 9 block rows
+constexpr int PLANE = PL_W * PL_H;                // 153 (odd)
+constexpr int LC_W = TCX + 2, LC_H = TCY + 2;     // local cell grid 17 x 9
+
+__device__ __forceinline__ int swz(int ty, int tx) {
+    return ((ty & 7) * 8 + (tx & 7)) * PLANE + (ty >> 3) * PL_W + (tx >> 3);
+}
+
+// One workgroup = one tile of TCY x TCX cells of one level of one frame.
+//  1. Level pixels of the tile (plus the pixels whose votes reach it and a
+//     one-pixel gradient halo) are resampled from the frame: 8-bit
+//     bilinear weights, exact in integers (value * 2^16).
+//  2. Each lane owns one 8x8 quad block and walks its pixels: central
+//     differences, orientation bin, magnitude, and four votes
+//     mag * wy * wx into the four cells around the block.  Votes are
+//     accumulated as 64-bit fixed point (mag * 2^22 times the integer
+//     weight product out of 256) with LDS integer atomics, so the sums do
+//     not depend on the order of the additions.
+//  3. Complete cells are converted to float (value * 2^-30) and written
+//     with their energy sum_o (h_o + h_{o+9})^2 (Sec. IV-A normalisation,
+//     Sec. V-A energy kernel).
+__global__ __launch_bounds__(HIST_THREADS) void hog_hist_kernel(
+    LevelTable T, const uint8_t* __restrict__ frames, long long fstride, int pitch,
+    const int4* __restrict__ taps, float* __restrict__ hist) {
+    __shared__ int sV[64 * PLANE];
+    __shared__ unsigned long long sH[LC_H * LC_W * NBINS];
+    __shared__ int4 sTy[TPY], sTx[TPX];
+
+    const int tid = threadIdx.x;
+    const int frame = blockIdx.y;
+    const int k = HOG_FIND_LEVEL(T, (int)blockIdx.x, th_off);
+    const DevLevel& L = T.L[k];
+    const int t = blockIdx.x - L.th_off;
+    const int tiles_x = (L.cx + TCX - 1) / TCX;
+    const int i0 = (t / tiles_x) * TCY, j0 = (t % tiles_x) * TCX;
+    const int ybase = 8 * i0 - 5, xbase = 8 * j0 - 5;   // level coords of tile pixel (0, 0)
+    const uint8_t* __restrict__ U = frames + (long long)frame * fstride;
+
+    for (int e = tid; e < LC_H * LC_W * NBINS; e += HIST_THREADS) sH[e] = 0ull;
+    for (int e = tid; e < TPY + TPX; e += HIST_THREADS) {
+        if (e < TPY) {
+            const int y = ybase + e;
+            sTy[e] = (y >= 0 && y < L.h) ? taps[L.tap_y + y] : make_int4(0, 0, 0, -1);
+        } else {
+            const int x = xbase + e - TPY;
+            sTx[e - TPY] = (x >= 0 && x < L.w) ? taps[L.tap_x + x] : make_int4(0, 0, 0, -1);
+        }
+    }
+    __syncthreads();
+
+    // 1. resample
+    for (int e = tid; e < TPY * TPX; e += HIST_THREADS) {
+        const int ty = e / TPX, tx = e - ty * TPX;
+        const int4 a = sTy[ty], b = sTx[tx];
+        int v = 0;
+        if ((a.w | b.w) == 0) {
+            const uint8_t* r0 = U + (long long)a.x * pitch;
+            const int u00 = r0[b.x];
+            const int u01 = b.z ? (int)r0[b.y] : 0;
+            int top = (256 - b.z) * u00 + b.z * u01;
+            int bot = 0;
+            if (a.z) {
+                const uint8_t* r1 = U + (long long)a.y * pitch;
+                bot = (256 - b.z) * (int)r1[b.x] + (b.z ? b.z * (int)r1[b.y] : 0);
+            }
+            v = (256 - a.z) * top + a.z * bot;
+        }
+        sV[swz(ty, tx)] = v;
+    }
+    __syncthreads();
+
+    // 2. gradients, orientation, votes
+    const int wave = tid >> 6, lane = tid & 63;
+    const int qa = (wave & 1) * 4 + (lane >> 4);      // quad-block row 0..7
+    const int qb = lane & 15;                         // quad-block column 0..15
+    const int obase = (wave >> 1) * 32;               // this wave's half of the 64 offsets
+    const int vy = 8 * L.cy, vx = 8 * L.cx;           // voting region
+    unsigned long long* h00 = &sH[(qa * LC_W + qb) * NBINS];
+    for (int oo = 0; oo < 32; ++oo) {
+        const int o = obase + oo;
+        const int oy = o >> 3, ox = o & 7;
+        const int ty = 8 * qa + 1 + oy, tx = 8 * qb + 1 + ox;
+        const int yl = ybase + ty, xl = xbase + tx;
+        const bool in = yl >= 1 && yl < vy && yl <= L.h - 2 && xl >= 1 && xl < vx && xl <= L.w - 2;
+        if (!in) continue;
+        const int gx = sV[swz(ty, tx + 1)] - sV[swz(ty, tx - 1)];
+        const int gy = sV[swz(ty + 1, tx)] - sV[swz(ty - 1, tx)];
+        if ((gx | gy) == 0) continue;
+        const int bin = orient_bin(gx, gy);
+        const float fx = (float)gx, fy = (float)gy;
+        const float mag = __builtin_sqrtf(fmaf(fx, fx, fy * fy));     // in units of 2^-16
+        const unsigned int M = (unsigned int)(mag * 64.0f + 0.5f);      // mag * 2^22
+        const unsigned int wy0 = 15 - 2 * oy, wy1 = 2 * oy + 1;
+        const unsigned int wx0 = 15 - 2 * ox, wx1 = 2 * ox + 1;
+        atomicAdd(h00 + bin, (unsigned long long)M * (wy0 * wx0));
+        atomicAdd(h00 + NBINS + bin, (unsigned long long)M * (wy0 * wx1));
+        atomicAdd(h00 + LC_W * NBINS + bin, (unsigned long long)M * (wy1 * wx0));
+        atomicAdd(h00 + (LC_W + 1) * NBINS + bin, (unsigned long long)M * (wy1 * wx1));
+    }
+    __syncthreads();
+
+    // 3. complete cells -> float histograms + energy
+    if (tid < TCY * TCX) {
+        const int li = tid / TCX, lj = tid - li * TCX;
+        const int gi = i0 + li, gj = j0 + lj;
+        if (gi < L.cy && gj < L.cx) {
+            const unsigned long long* src = &sH[((li + 1) * LC_W + lj + 1) * NBINS];
+            float h[NBINS];
+#pragma unroll
+            for (int b = 0; b < NBINS; ++b) h[b] = (float)((double)src[b] * 0x1p-30);
+            float E = 0.f;
+#pragma unroll
+            for (int o = 0; o < NORIENT; ++o) {
+                const float u = h[o] + h[o + NORIENT];
+                E = fmaf(u, u, E);
+            }
+            float4* dst = reinterpret_cast<float4*>(
+                hist + ((long long)frame * T.hist_frame + L.hist_off + (long long)gi * L.cx + gj) * HSTRIDE);
+            dst[0] = make_float4(h[0], h[1], h[2], h[3]);
+            dst[1] = make_float4(h[4], h[5], h[6], h[7]);
+            dst[2] = make_float4(h[8], h[9], h[10], h[11]);
+            dst[3] = make_float4(h[12], h[13], h[14], h[15]);
+            dst[4] = make_float4(h[16], h[17], E, 0.f);
+        }
+    }
+}
+
+hipError_t launch_hist(const LevelTable& T, const uint8_t* frames, long long fstride, int pitch, int n,
+                       const int4* taps, float* hist, hipStream_t s) {
+    hipLaunchKernelGGL(hog_hist_kernel, dim3(T.th_total, n), dim3(HIST_THREADS), 0, s, T, frames,
+                       fstride, pitch, taps, hist);
+    return hipGetLastError();
+}
+
+// Inspection: level pixel and orientation bin of every pixel of one level,
+// computed per pixel with the same taps and decision as the kernel above.
+__global__ __launch_bounds__(256) void hog_level_maps_kernel(
+    LevelTable T, int level, const uint8_t* __restrict__ U, int pitch, const int4* __restrict__ taps,
+    float* __restrict__ level_px, uint8_t* __restrict__ bins) {
+    const DevLevel& L = T.L[level];
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)L.h * L.w) return;
+    const int y = (int)(e / L.w), x = (int)(e % L.w);
+    auto px = [&](int yy, int xx) -> int {
+        const int4 a = taps[L.tap_y + yy], b = taps[L.tap_x + xx];
+        const uint8_t* r0 = U + (long long)a.x * pitch;
+        const uint8_t* r1 = U + (long long)a.y * pitch;
+        const int top = (256 - b.z) * r0[b.x] + b.z * r0[b.y];
+        const int bot = (256 - b.z) * r1[b.x] + b.z * r1[b.y];
+        return (256 - a.z) * top + a.z * bot;
+    };
+    const int v = px(y, x);
+    if (level_px) level_px[e] = (float)v * 0x1p-16f;
+    if (bins) {
+        int bn = 0;
+        if (y >= 1 && y <= L.h - 2 && x >= 1 && x <= L.w - 2) {
+            const int gx = px(y, x + 1) - px(y, x - 1);
+            const int gy = px(y + 1, x) - px(y - 1, x);
+            if (gx | gy) bn = orient_bin(gx, gy);
+        }
+        bins[e] = (uint8_t)bn;
+    }
+}
+
+hipError_t launch_level_maps(const LevelTable& T, int level, const uint8_t* frame, int pitch,
+                             const int4* taps, float* level_px, uint8_t* bins, hipStream_t s) {
+    const long long n = (long long)T.L[level].h * T.L[level].w;
+    hipLaunchKernelGGL(hog_level_maps_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, T,
+                       level, frame, pitch, taps, level_px, bins);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void hog_orient_kernel(const int32_t* __restrict__ gx,
+                                                          const int32_t* __restrict__ gy, long long n,
+                                                          uint8_t* __restrict__ bins) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int a = gx[e], b = gy[e];
+    bins[e] = (uint8_t)((a | b) ? orient_bin(a, b) : 0);
+}
+
+hipError_t launch_orient(const int32_t* gx, const int32_t* gy, long long n, uint8_t* bins, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(hog_orient_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, gx, gy, n,
+                       bins);
+    return hipGetLastError();
+}
+
+void orientation_table_host(double* c, double* s) {
+    for (int o = 0; o < NORIENT; ++o) {
+        c[o] = dir_cos(o);
+        s[o] = dir_sin(o);
+    }
+}
+
+}  // namespace hog

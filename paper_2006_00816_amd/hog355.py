@@ -1,0 +1,303 @@
+"""Python binding of libhog355 (ctypes).
+
+Argument marshalling only: every step of the detector runs in the HIP
+kernels of libhog355.so.  PyTorch provides device memory and the stream
+(the current torch stream).  There is no fallback: if the library is not
+built, or no GPU is visible, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhog355.so")
+
+HOG_OK = 0
+MAX_DETS = 4096
+
+
+class HogError(RuntimeError):
+    pass
+
+
+class hog_params(ctypes.Structure):
+    _fields_ = [("upsample", ctypes.c_int32), ("thresh", ctypes.c_float), ("iou", ctypes.c_float)]
+
+
+class hog_level(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("h", ctypes.c_int32), ("w", ctypes.c_int32),
+                ("cy", ctypes.c_int32), ("cx", ctypes.c_int32), ("rows", ctypes.c_int32),
+                ("cols", ctypes.c_int32), ("reserved", ctypes.c_int32), ("sig", ctypes.c_int64),
+                ("feat_offset", ctypes.c_int64), ("score_offset", ctypes.c_int64)]
+
+
+DET_DTYPE = np.dtype([("frame", "i4"), ("filter", "i4"), ("level", "i4"), ("row", "i4"), ("col", "i4"),
+                      ("x0", "i4"), ("y0", "i4"), ("x1", "i4"), ("y1", "i4"), ("score", "f4")])
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise HogError(f"{LIB_PATH} is not built (python -m paper_2006_00816_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_size_t
+    f32 = ctypes.c_float
+    sig = {
+        "hog_version": ([], i32),
+        "hog_strerror": ([i32], ctypes.c_char_p),
+        "hog_orientation_table": ([vp, vp], i32),
+        "hog_pyramid": ([i32, i32, i32, i32, vp, i32, vp], i32),
+        "hog_workspace_bytes": ([i32, i32, i32, i32, i32], sz),
+        "hog_features": ([vp, i32, i32, i32, i32, vp, i64, vp, sz, vp], i32),
+        "hog_scores": ([vp, i32, i32, i32, i32, vp, vp, i32, vp, i64, vp, sz, vp], i32),
+        "hog_detect": ([vp, vp, i32, i32, i32, vp, vp, i32, vp, i32, vp, vp, sz, vp], i32),
+        "hog_detect_batch": ([vp, vp, i32, i32, i32, i32, i64, vp, vp, i32, vp, i32, vp, vp, sz, vp], i32),
+        "hog_graph_create": ([vp, vp, vp, i32, i32, i32, i32, i64, vp, vp, i32, vp, i32, vp, vp, sz, vp], i32),
+        "hog_graph_launch": ([vp, vp], i32),
+        "hog_graph_destroy": ([vp], i32),
+        "hog_level_maps": ([vp, i32, i32, i32, i32, i32, vp, vp, vp, vp, sz, vp], i32),
+        "hog_orient_bins": ([vp, vp, i64, vp, vp], i32),
+        "hog_profile_enable": ([i32], i32),
+        "hog_profile_reset": ([], i32),
+        "hog_profile_read": ([ctypes.c_char_p, vp, vp], i32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _ = f32
+    _lib = L
+    return L
+
+
+def _check(st: int, what: str):
+    if st != HOG_OK:
+        raise HogError(f"{what}: {lib().hog_strerror(st).decode()} ({st})")
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    if not t.is_cuda:
+        raise HogError("expected a device tensor")
+    if not t.is_contiguous():
+        raise HogError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------------ host helpers
+def orientation_table():
+    c = (ctypes.c_double * 9)()
+    s = (ctypes.c_double * 9)()
+    _check(lib().hog_orientation_table(c, s), "hog_orientation_table")
+    return np.array(c[:]), np.array(s[:])
+
+
+def pyramid(h: int, w: int, upsample: int = 1, nf: int = 0):
+    arr = (hog_level * 32)()
+    n = ctypes.c_int(0)
+    _check(lib().hog_pyramid(h, w, upsample, nf, arr, 32, ctypes.byref(n)), "hog_pyramid")
+    return [{f: getattr(arr[i], f) for f, _ in hog_level._fields_} for i in range(n.value)]
+
+
+def workspace_bytes(h: int, w: int, upsample: int = 1, n: int = 1, nf: int = 1) -> int:
+    b = lib().hog_workspace_bytes(h, w, upsample, n, nf)
+    if b == 0:
+        raise HogError("hog_workspace_bytes: invalid arguments")
+    return int(b)
+
+
+class Workspace:
+    """A device byte buffer that grows to the largest request seen."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self.buf = torch.empty(0, dtype=torch.uint8, device=device)
+
+    def get(self, nbytes: int) -> torch.Tensor:
+        if self.buf.numel() < nbytes:
+            self.buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return self.buf
+
+
+_default_ws = {}
+
+
+def _ws(ws, nbytes):
+    if ws is None:
+        dev = torch.cuda.current_device()
+        ws = _default_ws.setdefault(dev, Workspace(f"cuda:{dev}"))
+    b = ws.get(nbytes)
+    return ctypes.c_void_p(b.data_ptr()), ctypes.c_size_t(b.numel())
+
+
+def _frame_args(frame: torch.Tensor):
+    if frame.dtype != torch.uint8 or frame.dim() != 2:
+        raise HogError("frame must be a uint8 [h][w] device tensor")
+    h, w = frame.shape
+    return int(h), int(w), int(frame.stride(0))
+
+
+# ---------------------------------------------------------------- calls
+def features(frame: torch.Tensor, upsample: int = 1, ws=None):
+    """31-d features per level: list of (level dict, float32 tensor [cy][cx][31])."""
+    h, w, pitch = _frame_args(frame)
+    levels = pyramid(h, w, upsample, 0)
+    total = sum(l["cy"] * l["cx"] * 31 for l in levels)
+    out = torch.empty(max(total, 1), dtype=torch.float32, device=frame.device)
+    wp, wn = _ws(ws, workspace_bytes(h, w, upsample, 1, 0))
+    _check(lib().hog_features(_ptr(frame), h, w, pitch, upsample, _ptr(out), out.numel(), wp, wn, _stream()),
+           "hog_features")
+    return [(l, out[l["feat_offset"]:l["feat_offset"] + l["cy"] * l["cx"] * 31].view(l["cy"], l["cx"], 31))
+            for l in levels]
+
+
+def scores(frame: torch.Tensor, W: torch.Tensor, b: torch.Tensor, upsample: int = 1, ws=None):
+    """Dense window scores per level: list of (level dict, tensor [nf][rows][cols])."""
+    h, w, pitch = _frame_args(frame)
+    nf = int(W.shape[0])
+    levels = pyramid(h, w, upsample, nf)
+    total = sum(nf * l["rows"] * l["cols"] for l in levels)
+    out = torch.empty(max(total, 1), dtype=torch.float32, device=frame.device)
+    wp, wn = _ws(ws, workspace_bytes(h, w, upsample, 1, nf))
+    _check(lib().hog_scores(_ptr(frame), h, w, pitch, upsample, _ptr(W), _ptr(b), nf, _ptr(out), out.numel(),
+                            wp, wn, _stream()), "hog_scores")
+    return [(l, out[l["score_offset"]:l["score_offset"] + nf * l["rows"] * l["cols"]]
+             .view(nf, l["rows"], l["cols"])) for l in levels]
+
+
+def _params(thresh, iou, upsample):
+    return hog_params(upsample, thresh, iou)
+
+
+def detect_batch_into(frames: torch.Tensor, W: torch.Tensor, b: torch.Tensor, dets: torch.Tensor,
+                      n_dets: torch.Tensor, thresh: float = 0.0, iou: float = 0.5, upsample: int = 1, ws=None):
+    """Enqueue hog_detect_batch into caller-provided outputs: dets int32
+    [n][cap][10] (hog_det records), n_dets int32 [n]."""
+    if frames.dtype != torch.uint8 or frames.dim() != 3:
+        raise HogError("frames must be a uint8 [n][h][w] device tensor")
+    n, h, w = (int(v) for v in frames.shape)
+    cap = int(dets.shape[1])
+    nf = int(W.shape[0])
+    prm = _params(thresh, iou, upsample)
+    wp, wn = _ws(ws, workspace_bytes(h, w, upsample, n, nf))
+    _check(lib().hog_detect_batch(ctypes.byref(prm), _ptr(frames), n, h, w, int(frames.stride(1)),
+                                  int(frames.stride(0)), _ptr(W), _ptr(b), nf, _ptr(dets), cap, _ptr(n_dets),
+                                  wp, wn, _stream()), "hog_detect_batch")
+
+
+def alloc_dets(n: int, cap: int, device="cuda"):
+    return (torch.empty((n, cap, 10), dtype=torch.int32, device=device),
+            torch.empty(n, dtype=torch.int32, device=device))
+
+
+def dets_to_numpy(dets: torch.Tensor, n_dets: torch.Tensor):
+    """Per frame, a structured numpy array of the written detections."""
+    d = dets.cpu().numpy()
+    nd = n_dets.cpu().numpy()
+    out = []
+    for i in range(d.shape[0]):
+        m = min(int(nd[i]), d.shape[1])
+        out.append(np.ascontiguousarray(d[i, :m]).view(DET_DTYPE).reshape(m))
+    return out, nd
+
+
+def detect(frame: torch.Tensor, W, b, thresh=0.0, iou=0.5, upsample=1, cap=MAX_DETS, ws=None):
+    """One frame through hog_detect: (detections, true kept count)."""
+    h, w, pitch = _frame_args(frame)
+    nf = int(W.shape[0])
+    dets, nd = alloc_dets(1, cap, frame.device)
+    prm = _params(thresh, iou, upsample)
+    wp, wn = _ws(ws, workspace_bytes(h, w, upsample, 1, nf))
+    _check(lib().hog_detect(ctypes.byref(prm), _ptr(frame), h, w, pitch, _ptr(W), _ptr(b), nf, _ptr(dets), cap,
+                            _ptr(nd), wp, wn, _stream()), "hog_detect")
+    out, cnt = dets_to_numpy(dets, nd)
+    return out[0], int(cnt[0])
+
+
+def detect_batch(frames: torch.Tensor, W, b, thresh=0.0, iou=0.5, upsample=1, cap=MAX_DETS, ws=None):
+    dets, nd = alloc_dets(int(frames.shape[0]), cap, frames.device)
+    detect_batch_into(frames, W, b, dets, nd, thresh, iou, upsample, ws)
+    return dets_to_numpy(dets, nd)
+
+
+class DetectGraph:
+    """hog_detect_batch captured once as a hipGraph over fixed buffers and
+    replayed; refresh ``frames`` in place between replays."""
+
+    def __init__(self, frames: torch.Tensor, W, b, cap=MAX_DETS, thresh=0.0, iou=0.5, upsample=1):
+        n, h, w = (int(v) for v in frames.shape)
+        nf = int(W.shape[0])
+        self.frames, self.W, self.b = frames, W, b
+        self.dets, self.n_dets = alloc_dets(n, cap, frames.device)
+        self.ws = torch.empty(workspace_bytes(h, w, upsample, n, nf), dtype=torch.uint8, device=frames.device)
+        self.prm = _params(thresh, iou, upsample)
+        self.stream = torch.cuda.Stream(device=frames.device)
+        self.handle = ctypes.c_void_p()
+        torch.cuda.synchronize(frames.device)
+        _check(lib().hog_graph_create(ctypes.byref(self.handle), ctypes.byref(self.prm), _ptr(frames), n, h, w,
+                                      int(frames.stride(1)), int(frames.stride(0)), _ptr(W), _ptr(b), nf,
+                                      _ptr(self.dets), cap, _ptr(self.n_dets), ctypes.c_void_p(self.ws.data_ptr()),
+                                      self.ws.numel(), ctypes.c_void_p(self.stream.cuda_stream)),
+               "hog_graph_create")
+
+    def launch(self):
+        _check(lib().hog_graph_launch(self.handle, _stream()), "hog_graph_launch")
+
+    def close(self):
+        if self.handle:
+            lib().hog_graph_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def level_maps(frame: torch.Tensor, level: int, upsample: int = 1, ws=None):
+    """(level pixels float32 [h_k][w_k], bins uint8 [h_k][w_k], hist float32 [cy][cx][18])."""
+    h, w, pitch = _frame_args(frame)
+    lv = pyramid(h, w, upsample, 0)[level]
+    px = torch.empty((lv["h"], lv["w"]), dtype=torch.float32, device=frame.device)
+    bins = torch.empty((lv["h"], lv["w"]), dtype=torch.uint8, device=frame.device)
+    hist = torch.empty((lv["cy"], lv["cx"], 18), dtype=torch.float32, device=frame.device)
+    wp, wn = _ws(ws, workspace_bytes(h, w, upsample, 1, 0))
+    _check(lib().hog_level_maps(_ptr(frame), h, w, pitch, upsample, level, _ptr(px), _ptr(bins), _ptr(hist),
+                                wp, wn, _stream()), "hog_level_maps")
+    return px, bins, hist
+
+
+def orient_bins(gx: torch.Tensor, gy: torch.Tensor) -> torch.Tensor:
+    """Orientation bins of int32 gradients (units of 2^-16)."""
+    out = torch.empty(gx.shape, dtype=torch.uint8, device=gx.device)
+    _check(lib().hog_orient_bins(_ptr(gx), _ptr(gy), gx.numel(), _ptr(out), _stream()), "hog_orient_bins")
+    return out
+
+
+# ------------------------------------------------------------ profiling
+def profile_enable(on: bool = True):
+    _check(lib().hog_profile_enable(1 if on else 0), "hog_profile_enable")
+
+
+def profile_reset():
+    _check(lib().hog_profile_reset(), "hog_profile_reset")
+
+
+def profile_read(kernel: str):
+    ms = ctypes.c_double(0.0)
+    cnt = ctypes.c_int64(0)
+    _check(lib().hog_profile_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(cnt)), "hog_profile_read")
+    return ms.value, cnt.value

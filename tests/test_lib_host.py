@@ -1,0 +1,108 @@
+"""Host-side checks of libhog355 that need no GPU: every declared symbol is
+exported, the host tables match the oracle, and argument errors are
+reported before any work is enqueued."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import hog as oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "libhog355.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2006_00816_amd import build, hog355
+    if not os.path.exists(hog355.LIB_PATH):
+        build.build()
+    return hog355.lib()
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hog_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_function(L):
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_version_and_strerror(L):
+    assert L.hog_version() >= 100
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert L.hog_strerror(code)
+    assert L.hog_strerror(-99) == b"unknown status"
+
+
+def test_orientation_table_matches_oracle_bitwise(L):
+    from paper_2006_00816_amd import hog355
+    c, s = hog355.orientation_table()
+    oc, os_ = oracle.orientation_table()
+    assert np.array_equal(c.view(np.uint64), oc.view(np.uint64))
+    assert np.array_equal(s.view(np.uint64), os_.view(np.uint64))
+
+
+@pytest.mark.parametrize("h,w,u", [(240, 320, 1), (480, 640, 1), (80, 80, 1), (1080, 1920, 2),
+                                   (97, 331, 1), (4096, 4096, 2), (4096, 81, 1), (100, 120, 2), (79, 500, 1)])
+def test_pyramid_matches_oracle(L, h, w, u):
+    from paper_2006_00816_amd import hog355
+    got = hog355.pyramid(h, w, u, 5)
+    want = oracle.pyramid(h, w, u)
+    assert [(g["h"], g["w"]) for g in got] == [(l.h, l.w) for l in want]
+    assert [g["sig"] for g in got] == [oracle.inverse_scale_fixed(l) for l in want]
+    off = 0
+    for g in got:
+        assert g["feat_offset"] == off
+        off += g["cy"] * g["cx"] * 31
+        assert g["rows"] == g["cy"] - 9 and g["cols"] == g["cx"] - 9
+
+
+def test_workspace_bytes(L):
+    from paper_2006_00816_amd import hog355
+    a = hog355.workspace_bytes(480, 640, 1, 1, 5)
+    b = hog355.workspace_bytes(480, 640, 1, 64, 5)
+    assert 0 < a < b
+    assert L.hog_workspace_bytes(480, 640, 3, 1, 5) == 0       # bad upsample
+    assert L.hog_workspace_bytes(5000, 640, 1, 1, 5) == 0      # too large
+    assert L.hog_workspace_bytes(480, 640, 1, 0, 5) == 0       # no frames
+
+
+def _detect(L, prm=True, frame=1, h=240, w=320, pitch=320, filt=1, bias=1, nf=1, dets=1, cap=16, nd=1,
+            ws=1, ws_bytes=1 << 40, iou=0.5, up=1):
+    from paper_2006_00816_amd import hog355
+    p = hog355.hog_params(up, 0.0, iou)
+    v = lambda x: ctypes.c_void_p(x) if x else None
+    return L.hog_detect(ctypes.byref(p) if prm else None, v(frame), h, w, pitch, v(filt), v(bias), nf, v(dets),
+                        cap, v(nd), v(ws), ws_bytes, None)
+
+
+def test_argument_errors_reported_before_launch(L):
+    # Every call below fails a host-side check; the dummy pointers are
+    # never dereferenced and no GPU is touched.
+    assert _detect(L, prm=False) == -1
+    assert _detect(L, frame=0) == -1
+    assert _detect(L, pitch=100) == -1
+    assert _detect(L, nf=0) == -1
+    assert _detect(L, nf=33) == -2
+    assert _detect(L, cap=0) == -4
+    assert _detect(L, cap=5000) == -4
+    assert _detect(L, iou=1.0) == -1
+    assert _detect(L, h=5000, w=5000, pitch=5000) == -2
+    assert _detect(L, up=3) == -1
+    assert _detect(L, ws_bytes=16) == -3
+    assert _detect(L, ws=0) == -1
+
+
+def test_level_table_limits(L):
+    from paper_2006_00816_amd import hog355
+    lv = hog355.pyramid(4096, 4096, 2, 32)
+    assert len(lv) <= 28
+    assert lv[0]["cx"] <= 1024
