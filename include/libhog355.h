@@ -59,8 +59,10 @@ typedef struct hog_params {
                           (Sec. III-B evaluates on 2x upscaled images) */
     float   thresh;    /* a window is a candidate iff score > thresh (strict) */
     float   iou;       /* greedy NMS drops a box whose IoU with a kept,
-                          better-ranked box exceeds iou (tested on integer
-                          areas as inter > iou * union) */
+                          better-ranked box exceeds iou, 0.5 <= iou < 1
+                          (tested exactly on integer areas as
+                          inter > iou * union, iou taken as its float32
+                          value) */
 } hog_params;
 
 /* One pyramid level.  Level k has scale s_k = upsample * (5/6)^k and size
@@ -181,7 +183,7 @@ int hog_orient_bins(const int32_t* gx, const int32_t* gy, int64_t n,
  * launch of the library's kernels outside graph capture is bracketed by
  * two events on its stream.  hog_profile_read synchronises on the recorded
  * events and returns the summed milliseconds and the launch count of the
- * kernel named `kernel` ("hist", "feat", "score", "nms", "geom").  Not
+ * kernel named `kernel` ("geom", "hist", "feat", "score", "nms_edges", "nms").  Not
  * thread-safe.  Host only. */
 int hog_profile_enable(int on);
 int hog_profile_reset(void);

@@ -18,7 +18,8 @@ struct Plan {
     LevelTable T;
     int n = 0, nf = 0, groups = 0;
     // workspace offsets (bytes)
-    size_t o_taps = 0, o_boxes = 0, o_bpack = 0, o_hist = 0, o_feat = 0, o_key = 0, o_state = 0, total = 0;
+    size_t o_taps = 0, o_boxes = 0, o_bpack = 0, o_hist = 0, o_feat = 0, o_key = 0, o_state = 0, o_list = 0,
+           o_work = 0, total = 0;
     long long packed_floats = 0, dense_floats = 0;
 };
 
@@ -163,7 +164,11 @@ int make_plan(int h, int w, int u, int n, int nf, Plan* P) {
     P->o_key = o;
     o = align256(o + sizeof(unsigned long long) * (size_t)n * std::max(pos, 1LL));
     P->o_state = o;
-    o = align256(o + sizeof(int) * (size_t)n * std::max(pos, 1LL));
+    o = align256(o + sizeof(unsigned) * (size_t)n * ((std::max(pos, 1LL) + 15) / 16));
+    P->o_list = o;
+    o = align256(o + sizeof(unsigned) * NMS_LIST * (size_t)n * std::max(pos, 1LL));
+    P->o_work = o;
+    o = align256(o + sizeof(int) * 2 * (size_t)n * std::max(pos, 1LL));
     P->total = o;
     return HOG_OK;
 }
@@ -249,8 +254,8 @@ int detect_sequence(const Plan& P, const hog_params* prm, const uint8_t* frames,
         return launch_score(T, P.n, at<float>(ws, P.o_feat), at<float4>(ws, P.o_bpack), bias, P.nf, prm->thresh,
                             nullptr, at<unsigned long long>(ws, P.o_key), multi, s);
     }));
-    // iou (a float32 in [2^-10, 1)) as the exact binary fraction num / 2^e,
-    // e <= 34, so that inter * 2^e stays below 2^63
+    // iou (a float32 in [1/2, 1)) as the exact binary fraction num / 2^e,
+    // e <= 24, so that inter * 2^e stays below 2^63
     double v = prm->iou;
     int e = 0;
     while (v != (double)(long long)v) {
@@ -258,9 +263,14 @@ int detect_sequence(const Plan& P, const hog_params* prm, const uint8_t* frames,
         ++e;
     }
     const long long num = (long long)v, den = 1LL << e;
+    HOG_TRY(timed("nms_edges", s, [&] {
+        return launch_nms_edges(T, P.n, at<unsigned long long>(ws, P.o_key), at<int2>(ws, P.o_boxes), num, den,
+                                at<unsigned>(ws, P.o_list), s);
+    }));
     HOG_TRY(timed("nms", s, [&] {
-        return launch_nms(T, P.n, at<unsigned long long>(ws, P.o_key), at<int>(ws, P.o_state),
-                          at<int2>(ws, P.o_boxes), num, den, dets, cap, n_dets, s);
+        return launch_nms(T, P.n, at<unsigned long long>(ws, P.o_key), at<unsigned>(ws, P.o_list),
+                          at<int2>(ws, P.o_boxes), num, den, dets, cap, n_dets, at<unsigned>(ws, P.o_state),
+                          at<int>(ws, P.o_work), s);
     }));
     return HOG_OK;
 }
@@ -272,7 +282,7 @@ int check_detect_args(const hog_params* prm, const void* frames, int pitch, int 
     if (nf < 1) return HOG_E_INVAL;
     if (nf > MAX_FILTERS) return HOG_E_TOO_LARGE;
     if (cap < 1 || cap > MAX_DETS) return HOG_E_CAP;
-    if (!(prm->iou >= 0x1p-10f && prm->iou < 1.f)) return HOG_E_INVAL;
+    if (!(prm->iou >= 0.5f && prm->iou < 1.f)) return HOG_E_INVAL;
     if (prm->thresh != prm->thresh) return HOG_E_INVAL;
     return HOG_OK;
 }

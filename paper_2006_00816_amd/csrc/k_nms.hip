@@ -1,18 +1,27 @@
 // Non-maximum suppression on the GPU (Sec. IV-A: detections of one face
 // are reduced to the best-scoring one; the paper runs this step on the
 // CPU, Sec. V-A).
+//
+// Every window position holds its best candidate key over the filters (a
+// window's other filters have the same box and a lower rank, so they are
+// suppressed by it or by whatever suppresses it).  Greedy NMS in rank order
+// keeps a candidate iff no kept, better-ranked candidate overlaps it with
+// IoU > iou.  Two kernels compute exactly that:
+//  - hog_nms_edges: for every candidate, in parallel over all frames, the
+//    list of better-ranked candidates that overlap it with IoU > iou
+//    (exact integer areas);
+//  - hog_nms_resolve: one workgroup per frame decides candidates in rounds
+//    over a shrinking worklist (DROPPED if a listed neighbour is kept, KEPT
+//    if all are dropped); the best undecided candidate always decides, so
+//    the rounds end, with the result of the sequential greedy pass.  Then
+//    the kept keys are sorted (the top min(cap, 4096) when there are more)
+//    and written out.
 #include "hog_device.h"
 
 namespace hog {
 
-enum : int { UNDECIDED = 0, KEPT = 1, DROPPED = 2 };
+enum : unsigned { UNDECIDED = 0, KEPT = 1, DROPPED = 2 };
 
-__device__ __forceinline__ int ld_state(const int* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_state(int* p, int v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 struct Box {
     int x0, y0, x1, y1;
@@ -23,111 +32,249 @@ __device__ __forceinline__ Box window_box(const DevLevel& L, const int2* boxes, 
     return Box{cx.x, ry.x, cx.y, ry.y};
 }
 
-// Decide one candidate given the states of the better-ranked candidates it
-// overlaps with IoU > iou: DROPPED if one of them is kept, KEPT if all of
-// them are dropped, else UNDECIDED.  The neighbours are enumerated per
-// level from a necessary condition on the horizontal (vertical) overlap:
-// IoU > 1/2 needs 3 I > A + A', and I <= ov_x * min(h, h'), so
-// ov_x > (A + A'_min) / (3 min(h, h'_max)); the exact test is made on
-// integer areas.
-__device__ int decide(const LevelTable& T, const unsigned long long* keys, const int* st, const int2* boxes,
-                      unsigned long long kx, long long inum, long long iden) {
-    const unsigned int pk = ~(unsigned int)(kx & 0xffffffffu);
-    const int k = (pk >> 22) & 31, r = (pk >> 11) & 2047, c = pk & 2047;
+__device__ __forceinline__ long long floordiv(long long a, long long b) {
+    return a >= 0 ? a / b : -((-a + b - 1) / b);
+}
+
+struct Range {
+    int r_lo, r_hi, c_lo, c_hi;
+};
+
+// Windows of level M that can overlap box X with IoU > 1/2 (so also with
+// IoU above any larger threshold).  IoU > 1/2 needs 3 I > A + A', and
+// I <= ov_x * min(h, h'), so the horizontal overlap must exceed
+// t_x = (A + A'_min) / (3 min(h, h'_max)): the window's left edge x0' lies
+// in (X.x0 + t_x - w'_max, X.x1 - t_x), and x0' is within 1/2 px of
+// 8 c' s'^-1.  The bounds are taken in float with one window of slack on
+// each side; every window inside is then tested exactly.
+__device__ __forceinline__ Range neighbour_range(const DevLevel& M, const Box& X, int AX) {
+    const float wX = (float)(X.x1 - X.x0), hX = (float)(X.y1 - X.y0);
+    const float amin = (float)M.wmin * (float)M.hmin;
+    const float tx = ((float)AX + amin) / (3.f * fminf(hX, (float)M.hmax));
+    const float ty = ((float)AX + amin) / (3.f * fminf(wX, (float)M.wmax));
+    const float inv8 = 137438953472.0f / (float)M.sig;   // 2^40 / (8 sig): level cells per frame px
+    Range R;
+    R.c_lo = max((int)floorf(((float)X.x0 + tx - (float)M.wmax - 0.5f) * inv8) - 1, 0);
+    R.c_hi = min((int)ceilf(((float)X.x1 - tx + 0.5f) * inv8) + 1, M.cols - 1);
+    R.r_lo = max((int)floorf(((float)X.y0 + ty - (float)M.hmax - 0.5f) * inv8) - 1, 0);
+    R.r_hi = min((int)ceilf(((float)X.y1 - ty + 0.5f) * inv8) + 1, M.rows - 1);
+    return R;
+}
+
+__device__ __forceinline__ int range_bits(const Range& R) {
+    return (R.r_hi >= R.r_lo && R.c_hi >= R.c_lo) ? (R.r_hi - R.r_lo + 1) * (R.c_hi - R.c_lo + 1) : 0;
+}
+
+// Exact IoU test on integer areas (areas < 2^27): inter / union > num / den.
+__device__ __forceinline__ bool conflicts(const Box& X, int AX, const int2& ry, const int2& cx, long long inum,
+                                          long long iden) {
+    const int iw = min(X.x1, cx.y) - max(X.x0, cx.x);
+    const int ih = min(X.y1, ry.y) - max(X.y0, ry.x);
+    if (iw <= 0 || ih <= 0) return false;
+    const int I = iw * ih;
+    const int U = AX + (cx.y - cx.x) * (ry.y - ry.x) - I;
+    if (inum == 1 && iden == 2) return 2 * I > U;
+    return (long long)I * iden > inum * (long long)U;
+}
+
+__device__ __forceinline__ void decode(unsigned long long key, int& f, int& k, int& r, int& c) {
+    const unsigned int pk = ~(unsigned int)(key & 0xffffffffu);
+    f = pk >> 27;
+    k = (pk >> 22) & 31;
+    r = (pk >> 11) & 2047;
+    c = pk & 2047;
+}
+
+// ------------------------------------------------------------ edges
+// Record per window position: [count, up to NMS_LIST - 1 neighbour
+// positions].  A count above NMS_LIST - 1 means the list was cut short and
+// the candidate is decided by a direct scan instead.
+__global__ __launch_bounds__(256) void hog_nms_edges_kernel(
+    LevelTable T, const unsigned long long* __restrict__ poskey, const int2* __restrict__ boxes, long long inum,
+    long long iden, unsigned* __restrict__ lists) {
+    const int frame = blockIdx.y;
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= T.pos_frame) return;
+    const unsigned long long* keys = poskey + (long long)frame * T.pos_frame;
+    unsigned* out = lists + ((long long)frame * T.pos_frame + p) * NMS_LIST;
+    const unsigned long long kx = keys[p];
+    int cnt = 0;
+    if (kx) {
+        int f, k, r, c;
+        decode(kx, f, k, r, c);
+        const DevLevel& L = T.L[k];
+        const Box X = window_box(L, boxes, r, c);
+        const int AX = (X.x1 - X.x0) * (X.y1 - X.y0);
+        for (int k2 = L.nms_klo; k2 <= L.nms_khi; ++k2) {
+            const DevLevel& M = T.L[k2];
+            const Range R = neighbour_range(M, X, AX);
+            for (int r2 = R.r_lo; r2 <= R.r_hi; ++r2) {
+                const int2 ry = boxes[M.box_r + r2];
+                if (min(X.y1, ry.y) <= max(X.y0, ry.x)) continue;
+                const int base = M.pos_off + r2 * M.cols;
+                for (int c2 = R.c_lo; c2 <= R.c_hi; ++c2) {
+                    if (keys[base + c2] <= kx) continue;          // worse rank, itself, or not a candidate
+                    if (!conflicts(X, AX, ry, boxes[M.box_c + c2], inum, iden)) continue;
+                    if (cnt < NMS_LIST - 1) out[1 + cnt] = (unsigned)(base + c2);
+                    ++cnt;
+                }
+            }
+        }
+    }
+    out[0] = (unsigned)cnt;
+}
+
+// ----------------------------------------------------------- resolve
+// Decision states live in LDS, 2 bits per window position (16 per word);
+// a state only ever changes from UNDECIDED to KEPT or DROPPED, by atomic OR.
+// (Frames with too many positions for LDS keep them in global memory,
+// accessed with device-scope atomics.)
+template <bool G>
+__device__ __forceinline__ unsigned state_of(const unsigned* S, int y) {
+    unsigned w;
+    if (G) w = __hip_atomic_load(S + (y >> 4), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else w = S[y >> 4];
+    return (w >> ((y & 15) * 2)) & 3u;
+}
+
+// Direct scan of the neighbourhood (lists that did not fit).
+template <bool G>
+__device__ unsigned decide_scan(const LevelTable& T, const unsigned long long* keys, const unsigned* S,
+                                const int2* boxes, unsigned long long kx, long long inum, long long iden) {
+    int f, k, r, c;
+    decode(kx, f, k, r, c);
     const DevLevel& L = T.L[k];
     const Box X = window_box(L, boxes, r, c);
-    const long long wX = X.x1 - X.x0, hX = X.y1 - X.y0;
-    const long long AX = wX * hX;
+    const int AX = (X.x1 - X.x0) * (X.y1 - X.y0);
     bool blocked = false;
     for (int k2 = L.nms_klo; k2 <= L.nms_khi; ++k2) {
         const DevLevel& M = T.L[k2];
-        const double inv8 = 0.125 * 1099511627776.0 / (double)M.sig;   // level px per frame px / 8
-        const double amin = (double)M.wmin * M.hmin;
-        const double tx = (AX + amin) / (3.0 * (double)min(hX, (long long)M.hmax)) * (1.0 - 1e-9);
-        const double ty = (AX + amin) / (3.0 * (double)min(wX, (long long)M.wmax)) * (1.0 - 1e-9);
-        // x0' in (X.x0 + tx - wmax', X.x1 - tx), |x0' - 8c' sig'| <= 1/2
-        int c_lo = (int)floor((X.x0 + tx - M.wmax - 0.5) * inv8) - 1;
-        int c_hi = (int)ceil((X.x1 - tx + 0.5) * inv8) + 1;
-        int r_lo = (int)floor((X.y0 + ty - M.hmax - 0.5) * inv8) - 1;
-        int r_hi = (int)ceil((X.y1 - ty + 0.5) * inv8) + 1;
-        c_lo = max(c_lo, 0);
-        r_lo = max(r_lo, 0);
-        c_hi = min(c_hi, M.cols - 1);
-        r_hi = min(r_hi, M.rows - 1);
-        for (int r2 = r_lo; r2 <= r_hi; ++r2) {
+        const Range R = neighbour_range(M, X, AX);
+        for (int r2 = R.r_lo; r2 <= R.r_hi; ++r2) {
             const int2 ry = boxes[M.box_r + r2];
-            const long long ih = (long long)min(X.y1, ry.y) - max(X.y0, ry.x);
-            if (ih <= 0) continue;
-            const long long base = M.pos_off + (long long)r2 * M.cols;
-            for (int c2 = c_lo; c2 <= c_hi; ++c2) {
-                const unsigned long long ky = keys[base + c2];
-                if (ky <= kx) continue;                 // worse rank, or not a candidate
-                const int sy = ld_state(st + base + c2);
+            const int base = M.pos_off + r2 * M.cols;
+            for (int c2 = R.c_lo; c2 <= R.c_hi; ++c2) {
+                if (keys[base + c2] <= kx) continue;
+                const unsigned sy = state_of<G>(S, base + c2);
                 if (sy == DROPPED) continue;
-                const int2 cxy = boxes[M.box_c + c2];
-                const long long iw = (long long)min(X.x1, cxy.y) - max(X.x0, cxy.x);
-                if (iw <= 0) continue;
-                const long long I = iw * ih;
-                const long long U = AX + (long long)(cxy.y - cxy.x) * (ry.y - ry.x) - I;
-                if (I * iden > inum * U) {
-                    if (sy == KEPT) return DROPPED;
-                    blocked = true;
-                }
+                if (!conflicts(X, AX, ry, boxes[M.box_c + c2], inum, iden)) continue;
+                if (sy == KEPT) return DROPPED;
+                blocked = true;
             }
         }
     }
     return blocked ? UNDECIDED : KEPT;
 }
 
-// One workgroup per frame.  Every window position holds its best candidate
-// key over the filters (a window's other filters have the same box and a
-// lower rank, so they are suppressed by it or by whatever suppresses it).
-// Greedy NMS in rank order keeps a candidate iff no kept, better-ranked
-// candidate overlaps it with IoU > iou.  Here every undecided candidate is
-// decided as soon as all its better-ranked overlapping candidates are; the
-// best undecided candidate always decides, so the rounds end, with the
-// same result as the sequential greedy pass.  The kept keys are then
-// sorted (the top min(cap, 4096) when there are more) and written out.
-__global__ __launch_bounds__(NMS_THREADS) void hog_nms_kernel(
-    LevelTable T, const unsigned long long* __restrict__ poskey, int* __restrict__ state,
+// Decision from the neighbour list rec = [count, positions...], read 16
+// entries (four 16-byte loads) at a time.
+template <bool G>
+__device__ __forceinline__ unsigned decide_list(const unsigned* S, const unsigned* rec, int cnt) {
+    bool blocked = false;
+    for (int e = 0; e <= cnt; e += 16) {
+        uint4 q[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) q[j] = *reinterpret_cast<const uint4*>(rec + e + 4 * j);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int i = e + j;
+            const unsigned idx = (j & 3) == 0 ? q[j >> 2].x : (j & 3) == 1 ? q[j >> 2].y
+                               : (j & 3) == 2 ? q[j >> 2].z : q[j >> 2].w;
+            if (i == 0 || i > cnt) continue;
+            const unsigned sy = state_of<G>(S, (int)idx);
+            if (sy == KEPT) return DROPPED;
+            if (sy == UNDECIDED) blocked = true;
+        }
+    }
+    return blocked ? UNDECIDED : KEPT;
+}
+
+// Appends p to a worklist when `take`; one LDS atomic per wave.
+__device__ __forceinline__ void wave_append(bool take, int p, int* list, int* counter) {
+    const unsigned long long m = __ballot(take);
+    if (!m) return;
+    const int lane = threadIdx.x & 63;
+    int base = 0;
+    if (lane == __builtin_ctzll(m)) base = atomicAdd(counter, __popcll(m));
+    base = __shfl(base, __builtin_ctzll(m), 64);
+    if (take) list[base + __popcll(m & ((1ull << lane) - 1ull))] = p;
+}
+
+template <bool G>
+__global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
+    LevelTable T, const unsigned long long* __restrict__ poskey, const unsigned* __restrict__ lists,
     const int2* __restrict__ boxes, long long inum, long long iden, hog_det* __restrict__ dets, int cap,
-    int* __restrict__ n_dets) {
+    int* __restrict__ n_dets, unsigned* __restrict__ gstate, int* __restrict__ work) {
+    extern __shared__ unsigned lstate[];     // 2-bit states (LDS variant)
     __shared__ unsigned long long sk[SORT_CAP];
     __shared__ unsigned int hist[256];
-    __shared__ int s_count;
+    __shared__ int s_count, s_next;
     __shared__ unsigned long long s_prefix, s_mask;
     __shared__ int s_remaining;
 
     const int tid = threadIdx.x;
     const int frame = blockIdx.x;
     const int P = T.pos_frame;
+    const int nw = (P + 15) >> 4;
+    unsigned* S = G ? gstate + (long long)frame * nw : lstate;
     const unsigned long long* keys = poskey + (long long)frame * P;
-    int* st = state + (long long)frame * P;
+    const unsigned* lst = lists + (long long)frame * P * NMS_LIST;
+    int* wl[2] = {work + (long long)frame * 2 * P, work + (long long)frame * 2 * P + P};
 
-    for (int p = tid; p < P; p += NMS_THREADS) st_state(st + p, keys[p] ? UNDECIDED : DROPPED);
+    // initial states and worklist of all candidates
+    if (tid == 0) s_count = 0;
+    __syncthreads();
+    for (int w0 = 0; w0 < nw; w0 += NMS_THREADS) {
+        const int w = w0 + tid;
+        unsigned v = 0;
+        if (w < nw) {
+            for (int j = 0; j < 16; ++j) {
+                const int p = 16 * w + j;
+                if (p >= P || keys[p] == 0ull) v |= DROPPED << (2 * j);
+            }
+            if (G) __hip_atomic_store(S + w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else S[w] = v;
+        }
+    }
+    for (int p0 = 0; p0 < P; p0 += NMS_THREADS) {
+        const int p = p0 + tid;
+        wave_append(p < P && keys[p] != 0ull, p, wl[0], &s_count);
+    }
     __syncthreads();
 
+    int cur = 0;
     for (int round = 0; round <= P; ++round) {
-        int changed = 0, left = 0;
-        for (int p = tid; p < P; p += NMS_THREADS) {
-            if (ld_state(st + p) != UNDECIDED) continue;
-            const int v = decide(T, keys, st, boxes, keys[p], inum, iden);
-            if (v != UNDECIDED) {
-                st_state(st + p, v);
-                changed = 1;
-            } else {
-                left = 1;
+        const int n_in = s_count;
+        if (n_in == 0) break;
+        if (tid == 0) s_next = 0;
+        __syncthreads();
+        const int* in = wl[cur];
+        for (int i0 = 0; i0 < n_in; i0 += NMS_THREADS) {
+            const int i = i0 + tid;
+            bool keep_working = false;
+            int p = 0;
+            if (i < n_in) {
+                p = in[i];
+                const unsigned* rec = lst + (long long)p * NMS_LIST;
+                const int cnt = (int)rec[0];
+                const unsigned v = cnt < NMS_LIST ? decide_list<G>(S, rec, cnt)
+                                                  : decide_scan<G>(T, keys, S, boxes, keys[p], inum, iden);
+                if (v != UNDECIDED) atomicOr(&S[p >> 4], v << ((p & 15) * 2));
+                else keep_working = true;
             }
+            wave_append(keep_working, p, wl[cur ^ 1], &s_next);
         }
-        if (!__syncthreads_or(left)) break;
-        (void)changed;
+        __syncthreads();
+        if (tid == 0) s_count = s_next;
+        cur ^= 1;
+        __syncthreads();
     }
 
     // count the kept candidates
     if (tid == 0) s_count = 0;
     __syncthreads();
     int mine = 0;
-    for (int p = tid; p < P; p += NMS_THREADS) mine += ld_state(st + p) == KEPT;
+    for (int p = tid; p < P; p += NMS_THREADS) mine += state_of<G>(S, p) == KEPT;
     if (mine) atomicAdd(&s_count, mine);
     __syncthreads();
     const int nkept = s_count;
@@ -143,7 +290,7 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_kernel(
             __syncthreads();
             const unsigned long long pre = s_prefix, msk = s_mask;
             for (int p = tid; p < P; p += NMS_THREADS) {
-                if (ld_state(st + p) != KEPT) continue;
+                if (state_of<G>(S, p) != KEPT) continue;
                 const unsigned long long kk = keys[p];
                 if ((kk & msk) == pre) atomicAdd(&hist[(kk >> shift) & 255], 1u);
             }
@@ -163,11 +310,11 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_kernel(
         thr = s_prefix;
     }
 
-    // gather kept keys >= thr into LDS, pad with zeros to a power of two
+    // gather kept keys >= thr, pad with zeros to a power of two
     if (tid == 0) s_count = 0;
     __syncthreads();
     for (int p = tid; p < P; p += NMS_THREADS) {
-        if (ld_state(st + p) != KEPT) continue;
+        if (state_of<G>(S, p) != KEPT) continue;
         const unsigned long long kk = keys[p];
         if (kk < thr) continue;
         const int slot = atomicAdd(&s_count, 1);
@@ -198,8 +345,8 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_kernel(
     const int nout = min(ng, cap);
     for (int e = tid; e < nout; e += NMS_THREADS) {
         const unsigned long long kk = sk[e];
-        const unsigned int pk = ~(unsigned int)(kk & 0xffffffffu);
-        const int f = pk >> 27, k = (pk >> 22) & 31, r = (pk >> 11) & 2047, c = pk & 2047;
+        int f, k, r, c;
+        decode(kk, f, k, r, c);
         const Box b = window_box(T.L[k], boxes, r, c);
         hog_det d;
         d.frame = frame; d.filter = f; d.level = k; d.row = r; d.col = c;
@@ -210,10 +357,27 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_kernel(
     if (tid == 0) n_dets[frame] = nkept;
 }
 
-hipError_t launch_nms(const LevelTable& T, int n, const unsigned long long* poskey, int* state, const int2* boxes,
-                      long long iou_num, long long iou_den, void* dets, int cap, int* n_dets, hipStream_t s) {
-    hipLaunchKernelGGL(hog_nms_kernel, dim3(n), dim3(NMS_THREADS), 0, s, T, poskey, state, boxes, iou_num,
-                       iou_den, (hog_det*)dets, cap, n_dets);
+// Positions whose states fit in LDS next to the sort buffer.
+constexpr int NMS_LDS_STATE_WORDS = (150 * 1024 - SORT_CAP * 8 - 2048) / 4;
+
+hipError_t launch_nms_edges(const LevelTable& T, int n, const unsigned long long* poskey, const int2* boxes,
+                            long long iou_num, long long iou_den, unsigned* lists, hipStream_t s) {
+    hipLaunchKernelGGL(hog_nms_edges_kernel, dim3((T.pos_frame + 255) / 256, n), dim3(256), 0, s, T, poskey, boxes,
+                       iou_num, iou_den, lists);
+    return hipGetLastError();
+}
+
+hipError_t launch_nms(const LevelTable& T, int n, const unsigned long long* poskey, const unsigned* lists,
+                      const int2* boxes, long long iou_num, long long iou_den, void* dets, int cap, int* n_dets,
+                      unsigned* gstate, int* work, hipStream_t s) {
+    const int nw = (T.pos_frame + 15) >> 4;
+    if (nw <= NMS_LDS_STATE_WORDS) {
+        hipLaunchKernelGGL(hog_nms_resolve_kernel<false>, dim3(n), dim3(NMS_THREADS), nw * sizeof(unsigned), s, T,
+                           poskey, lists, boxes, iou_num, iou_den, (hog_det*)dets, cap, n_dets, gstate, work);
+    } else {
+        hipLaunchKernelGGL(hog_nms_resolve_kernel<true>, dim3(n), dim3(NMS_THREADS), 0, s, T, poskey, lists, boxes,
+                           iou_num, iou_den, (hog_det*)dets, cap, n_dets, gstate, work);
+    }
     return hipGetLastError();
 }
 

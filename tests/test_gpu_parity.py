@@ -250,3 +250,18 @@ def test_constant_frame_scores_equal_bias(H):
     got = H.scores(cu(np.full((200, 240), 90, np.uint8)), cu(Wn), cu(bn))
     for lv, S in got:
         assert np.array_equal(S.cpu().numpy(), np.broadcast_to(bn[:, None, None], S.shape))
+
+
+def test_detect_large_frame_nms_states_in_global_memory(H):
+    """4096x4096: more window positions than the NMS keeps in LDS, so the
+    decision states live in global memory.  The filter bias is lowered so
+    that the oracle's NMS over the GPU candidates stays quick."""
+    rng = np.random.default_rng(21)
+    frame = np.clip(np.rint(synth.background(rng, 4096, 4096)), 0, 255).astype(np.uint8)
+    Wn, bn = synth.filters(range(500, 505), bias=-2.2)
+    levels = H.pyramid(4096, 4096, 1, 5)
+    assert sum(l["rows"] * l["cols"] for l in levels) > 16 * 29696
+    dets, n = H.detect(cu(frame), cu(Wn), cu(bn))
+    print(f"4096x4096: {n} kept", flush=True)
+    assert n > 0
+    assert_nms_function(H, frame, Wn, bn, 1, dets, n)

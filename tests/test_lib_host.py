@@ -95,6 +95,7 @@ def test_argument_errors_reported_before_launch(L):
     assert _detect(L, cap=0) == -4
     assert _detect(L, cap=5000) == -4
     assert _detect(L, iou=1.0) == -1
+    assert _detect(L, iou=0.3) == -1
     assert _detect(L, h=5000, w=5000, pitch=5000) == -2
     assert _detect(L, up=3) == -1
     assert _detect(L, ws_bytes=16) == -3
