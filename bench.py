@@ -63,6 +63,7 @@ def main():
     ap.add_argument("--plain-frames", type=int, default=640)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=32)
+    ap.add_argument("--kernel-steps", type=int, default=100, help="eager steps timed per kernel (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the detector shards by frame with no collective on the "
@@ -113,7 +114,7 @@ def main():
     torch.cuda.synchronize()
     hog355.profile_reset()
     hog355.profile_enable(True)
-    ksteps = max(10, min(args.steps, 100))
+    ksteps = min(args.steps, args.kernel_steps)
     for _ in range(ksteps):
         hog355.detect_batch_into(frames, Wt, bt, dets, nd, ws=ws)
     torch.cuda.synchronize()
@@ -127,7 +128,7 @@ def main():
     # ------------------------------------------------------------ plain
     plain_lat = []
     one = frames[0]
-    for _ in range(20):
+    for _ in range(20 if args.plain_frames else 0):
         hog355.detect(one, Wt, bt, ws=ws)
     torch.cuda.synchronize()
     pdets, pnd = hog355.alloc_dets(1, hog355.MAX_DETS)
@@ -138,12 +139,12 @@ def main():
         torch.cuda.synchronize()
         plain_lat.append(1e3 * (time.perf_counter() - t1))
     plain_dt = time.perf_counter() - t0
-    plain_lat = np.array(plain_lat)
+    plain_lat = np.array(plain_lat if plain_lat else [0.0])
 
     # ----------------------------------------------------------- roofline
     win = windows_per_frame(H, W_PX)
     flop_per_frame = 2.0 * 3100 * NF * win
-    achieved = flop_per_frame * CLIP / (kern["score"] * 1e-3) / 1e12
+    achieved = flop_per_frame * CLIP / (max(kern["score"], 1e-9) * 1e-3) / 1e12
     roofline = {"bound": "mfma", "kernel": "hog_score_kernel", "achieved": round(achieved, 2),
                 "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
                 "traffic": None,
@@ -168,7 +169,7 @@ def main():
         "batched": {"fps": round(fps, 1), "p50_ms": round(float(np.percentile(lat, 50)), 4),
                     "p99_ms": round(float(np.percentile(lat, 99)), 4),
                     "latency": "clip submit to completion (every frame of the clip)"},
-        "plain": {"fps": round(args.plain_frames / plain_dt, 1),
+        "plain": {"fps": round(args.plain_frames / max(plain_dt, 1e-9), 1),
                   "p50_ms": round(float(np.percentile(plain_lat, 50)), 4),
                   "p99_ms": round(float(np.percentile(plain_lat, 99)), 4),
                   "latency": "one frame per call, submit to completion"},

@@ -19,7 +19,7 @@ struct Plan {
     int n = 0, nf = 0, groups = 0;
     // workspace offsets (bytes)
     size_t o_taps = 0, o_boxes = 0, o_bpack = 0, o_hist = 0, o_feat = 0, o_key = 0, o_state = 0, o_list = 0,
-           o_work = 0, total = 0;
+           o_work = 0, o_state8 = 0, total = 0;
     long long packed_floats = 0, dense_floats = 0;
 };
 
@@ -53,14 +53,13 @@ int check_frame(int h, int w, int upsample) {
     return HOG_OK;
 }
 
-// Box side bounds of a level: an edge is round(v sig / 2^40), so a side of
-// 80 level px spans floor(80 s^-1) or ceil(80 s^-1) frame px; one more
-// pixel of slack on each side keeps the bounds conservative.
+// Box side bounds of a level: an edge is floor(v sig / 2^40 + 1/2), so a
+// side of 80 level px spans floor(80 sig / 2^40) or one more frame px.
 void box_bounds(long long sig, int* lo, int* hi) {
     const i128 num = (i128)80 * sig;
     const long long fl = (long long)(num >> SIG_BITS);
-    *lo = (int)fl - 1;
-    *hi = (int)fl + 2;
+    *lo = (int)fl;
+    *hi = (int)fl + 1;
 }
 
 int make_plan(int h, int w, int u, int n, int nf, Plan* P) {
@@ -169,6 +168,8 @@ int make_plan(int h, int w, int u, int n, int nf, Plan* P) {
     o = align256(o + sizeof(unsigned) * NMS_LIST * (size_t)n * std::max(pos, 1LL));
     P->o_work = o;
     o = align256(o + sizeof(int) * 2 * (size_t)n * std::max(pos, 1LL));
+    P->o_state8 = o;
+    o = align256(o + (size_t)n * std::max(pos, 1LL));
     P->total = o;
     return HOG_OK;
 }
@@ -265,12 +266,12 @@ int detect_sequence(const Plan& P, const hog_params* prm, const uint8_t* frames,
     const long long num = (long long)v, den = 1LL << e;
     HOG_TRY(timed("nms_edges", s, [&] {
         return launch_nms_edges(T, P.n, at<unsigned long long>(ws, P.o_key), at<int2>(ws, P.o_boxes), num, den,
-                                at<unsigned>(ws, P.o_list), s);
+                                at<unsigned>(ws, P.o_list), at<unsigned char>(ws, P.o_state8), NMS_PAR_ROUNDS, s);
     }));
     HOG_TRY(timed("nms", s, [&] {
         return launch_nms(T, P.n, at<unsigned long long>(ws, P.o_key), at<unsigned>(ws, P.o_list),
                           at<int2>(ws, P.o_boxes), num, den, dets, cap, n_dets, at<unsigned>(ws, P.o_state),
-                          at<int>(ws, P.o_work), s);
+                          at<int>(ws, P.o_work), at<unsigned char>(ws, P.o_state8), s);
     }));
     return HOG_OK;
 }

@@ -49,6 +49,7 @@ constexpr int BPACK_PER_GROUP = WIN * KK * 64;   // float4 entries per filter gr
 constexpr int NMS_THREADS = 1024;
 constexpr int SORT_CAP = 4096;
 constexpr int NMS_LIST = 128;       // neighbour-list record per window position: count + 127 entries
+constexpr int NMS_PAR_ROUNDS = 2;   // decision rounds run in parallel over all frames before the per-frame kernel
 
 struct DevLevel {
     int h, w, cy, cx;
@@ -113,10 +114,11 @@ hipError_t launch_score(const LevelTable& T, int n, const float* feat, const flo
                         const float* bias, int nf, float thresh, float* dense,
                         unsigned long long* poskey, bool atomic_key, hipStream_t s);
 hipError_t launch_nms_edges(const LevelTable& T, int n, const unsigned long long* poskey, const int2* boxes,
-                            long long iou_num, long long iou_den, unsigned* lists, hipStream_t s);
+                            long long iou_num, long long iou_den, unsigned* lists, unsigned char* state8,
+                            int rounds, hipStream_t s);
 hipError_t launch_nms(const LevelTable& T, int n, const unsigned long long* poskey, const unsigned* lists,
                       const int2* boxes, long long iou_num, long long iou_den, void* dets, int cap, int* n_dets,
-                      unsigned* gstate, int* work, hipStream_t s);
+                      unsigned* gstate, int* work, const unsigned char* state8, hipStream_t s);
 hipError_t launch_level_maps(const LevelTable& T, int level, const uint8_t* frame, int pitch,
                              const int4* taps, float* level_px, uint8_t* bins, hipStream_t s);
 hipError_t launch_orient(const int32_t* gx, const int32_t* gy, long long n, uint8_t* bins,

@@ -10,7 +10,8 @@
 //  - hog_nms_edges: for every candidate, in parallel over all frames, the
 //    list of better-ranked candidates that overlap it with IoU > iou
 //    (exact integer areas);
-//  - hog_nms_resolve: one workgroup per frame decides candidates in rounds
+//  - hog_nms_round: a few decision rounds in parallel over all frames;
+//  - hog_nms_resolve: one workgroup per frame decides the rest in rounds
 //    over a shrinking worklist (DROPPED if a listed neighbour is kept, KEPT
 //    if all are dropped); the best undecided candidate always decides, so
 //    the rounds end, with the result of the sequential greedy pass.  Then
@@ -45,8 +46,8 @@ struct Range {
 // I <= ov_x * min(h, h'), so the horizontal overlap must exceed
 // t_x = (A + A'_min) / (3 min(h, h'_max)): the window's left edge x0' lies
 // in (X.x0 + t_x - w'_max, X.x1 - t_x), and x0' is within 1/2 px of
-// 8 c' s'^-1.  The bounds are taken in float with one window of slack on
-// each side; every window inside is then tested exactly.
+// 8 c' s'^-1.  Bounds in float, widened by 1e-2 window to cover rounding;
+// every window inside is then tested exactly.
 __device__ __forceinline__ Range neighbour_range(const DevLevel& M, const Box& X, int AX) {
     const float wX = (float)(X.x1 - X.x0), hX = (float)(X.y1 - X.y0);
     const float amin = (float)M.wmin * (float)M.hmin;
@@ -54,10 +55,10 @@ __device__ __forceinline__ Range neighbour_range(const DevLevel& M, const Box& X
     const float ty = ((float)AX + amin) / (3.f * fminf(wX, (float)M.wmax));
     const float inv8 = 137438953472.0f / (float)M.sig;   // 2^40 / (8 sig): level cells per frame px
     Range R;
-    R.c_lo = max((int)floorf(((float)X.x0 + tx - (float)M.wmax - 0.5f) * inv8) - 1, 0);
-    R.c_hi = min((int)ceilf(((float)X.x1 - tx + 0.5f) * inv8) + 1, M.cols - 1);
-    R.r_lo = max((int)floorf(((float)X.y0 + ty - (float)M.hmax - 0.5f) * inv8) - 1, 0);
-    R.r_hi = min((int)ceilf(((float)X.y1 - ty + 0.5f) * inv8) + 1, M.rows - 1);
+    R.c_lo = max((int)floorf(((float)X.x0 + tx - (float)M.wmax - 0.5f) * inv8 - 1e-2f) + 1, 0);
+    R.c_hi = min((int)ceilf(((float)X.x1 - tx + 0.5f) * inv8 + 1e-2f) - 1, M.cols - 1);
+    R.r_lo = max((int)floorf(((float)X.y0 + ty - (float)M.hmax - 0.5f) * inv8 - 1e-2f) + 1, 0);
+    R.r_hi = min((int)ceilf(((float)X.y1 - ty + 0.5f) * inv8 + 1e-2f) - 1, M.rows - 1);
     return R;
 }
 
@@ -86,17 +87,20 @@ __device__ __forceinline__ void decode(unsigned long long key, int& f, int& k, i
 }
 
 // ------------------------------------------------------------ edges
-// Record per window position: [count, up to NMS_LIST - 1 neighbour
-// positions].  A count above NMS_LIST - 1 means the list was cut short and
-// the candidate is decided by a direct scan instead.
+// List of window position p of a frame, stored transposed so that a
+// wave's lanes read consecutive words: entry e at lists[e * P + p], e = 0
+// the count, e = 1.. the neighbour positions.  A count above NMS_LIST - 1
+// means the list was cut short and the candidate is decided by a direct
+// scan instead.
 __global__ __launch_bounds__(256) void hog_nms_edges_kernel(
     LevelTable T, const unsigned long long* __restrict__ poskey, const int2* __restrict__ boxes, long long inum,
-    long long iden, unsigned* __restrict__ lists) {
+    long long iden, unsigned* __restrict__ lists, unsigned char* __restrict__ state8) {
     const int frame = blockIdx.y;
     const int p = blockIdx.x * 256 + threadIdx.x;
     if (p >= T.pos_frame) return;
     const unsigned long long* keys = poskey + (long long)frame * T.pos_frame;
-    unsigned* out = lists + ((long long)frame * T.pos_frame + p) * NMS_LIST;
+    const int P = T.pos_frame;
+    unsigned* out = lists + (long long)frame * P * NMS_LIST + p;
     const unsigned long long kx = keys[p];
     int cnt = 0;
     if (kx) {
@@ -115,13 +119,45 @@ __global__ __launch_bounds__(256) void hog_nms_edges_kernel(
                 for (int c2 = R.c_lo; c2 <= R.c_hi; ++c2) {
                     if (keys[base + c2] <= kx) continue;          // worse rank, itself, or not a candidate
                     if (!conflicts(X, AX, ry, boxes[M.box_c + c2], inum, iden)) continue;
-                    if (cnt < NMS_LIST - 1) out[1 + cnt] = (unsigned)(base + c2);
+                    if (cnt < NMS_LIST - 1) out[(long long)(1 + cnt) * P] = (unsigned)(base + c2);
                     ++cnt;
                 }
             }
         }
     }
     out[0] = (unsigned)cnt;
+    // first round: a candidate with no better-ranked conflict is kept
+    state8[(long long)frame * T.pos_frame + p] = (unsigned char)(kx == 0ull ? DROPPED : cnt == 0 ? KEPT : UNDECIDED);
+}
+
+// One parallel round over every window position of every frame: an
+// undecided candidate is dropped if a listed neighbour is kept and kept if
+// all are dropped.  Neighbour states read while other threads update them
+// can only be stale towards UNDECIDED, which delays a decision but never
+// changes it.  Candidates whose list overflowed are left to the per-frame
+// kernel.
+__global__ __launch_bounds__(256) void hog_nms_round_kernel(
+    LevelTable T, const unsigned* __restrict__ lists, unsigned char* __restrict__ state8) {
+    const int frame = blockIdx.y;
+    const int P = T.pos_frame;
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= P) return;
+    unsigned char* st = state8 + (long long)frame * P;
+    if (st[p] != UNDECIDED) return;
+    const unsigned* rec = lists + (long long)frame * P * NMS_LIST + p;
+    const int cnt = (int)rec[0];
+    if (cnt >= NMS_LIST) return;
+    bool blocked = false;
+    for (int e = 1; e <= cnt; ++e) {
+        const unsigned idx = rec[(long long)e * P];
+        const unsigned sy = __hip_atomic_load(st + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (sy == KEPT) {
+            __hip_atomic_store(st + p, (unsigned char)DROPPED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+        if (sy == UNDECIDED) blocked = true;
+    }
+    if (!blocked) __hip_atomic_store(st + p, (unsigned char)KEPT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ----------------------------------------------------------- resolve
@@ -166,25 +202,14 @@ __device__ unsigned decide_scan(const LevelTable& T, const unsigned long long* k
     return blocked ? UNDECIDED : KEPT;
 }
 
-// Decision from the neighbour list rec = [count, positions...], read 16
-// entries (four 16-byte loads) at a time.
+// Decision from the (transposed) neighbour list of a position.
 template <bool G>
-__device__ __forceinline__ unsigned decide_list(const unsigned* S, const unsigned* rec, int cnt) {
+__device__ __forceinline__ unsigned decide_list(const unsigned* S, const unsigned* rec, long long stride, int cnt) {
     bool blocked = false;
-    for (int e = 0; e <= cnt; e += 16) {
-        uint4 q[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) q[j] = *reinterpret_cast<const uint4*>(rec + e + 4 * j);
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const int i = e + j;
-            const unsigned idx = (j & 3) == 0 ? q[j >> 2].x : (j & 3) == 1 ? q[j >> 2].y
-                               : (j & 3) == 2 ? q[j >> 2].z : q[j >> 2].w;
-            if (i == 0 || i > cnt) continue;
-            const unsigned sy = state_of<G>(S, (int)idx);
-            if (sy == KEPT) return DROPPED;
-            if (sy == UNDECIDED) blocked = true;
-        }
+    for (int e = 1; e <= cnt; ++e) {
+        const unsigned sy = state_of<G>(S, (int)rec[e * stride]);
+        if (sy == KEPT) return DROPPED;
+        if (sy == UNDECIDED) blocked = true;
     }
     return blocked ? UNDECIDED : KEPT;
 }
@@ -204,7 +229,8 @@ template <bool G>
 __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
     LevelTable T, const unsigned long long* __restrict__ poskey, const unsigned* __restrict__ lists,
     const int2* __restrict__ boxes, long long inum, long long iden, hog_det* __restrict__ dets, int cap,
-    int* __restrict__ n_dets, unsigned* __restrict__ gstate, int* __restrict__ work) {
+    int* __restrict__ n_dets, unsigned* __restrict__ gstate, int* __restrict__ work,
+    const unsigned char* __restrict__ state8) {
     extern __shared__ unsigned lstate[];     // 2-bit states (LDS variant)
     __shared__ unsigned long long sk[SORT_CAP];
     __shared__ unsigned int hist[256];
@@ -218,19 +244,20 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
     const int nw = (P + 15) >> 4;
     unsigned* S = G ? gstate + (long long)frame * nw : lstate;
     const unsigned long long* keys = poskey + (long long)frame * P;
-    const unsigned* lst = lists + (long long)frame * P * NMS_LIST;
+    const unsigned* lst = lists + (long long)frame * P * NMS_LIST;   // transposed: entry e of p at e * P + p
     int* wl[2] = {work + (long long)frame * 2 * P, work + (long long)frame * 2 * P + P};
 
-    // initial states and worklist of all candidates
+    // states left by the parallel rounds, and the worklist of the undecided
+    const unsigned char* st8 = state8 + (long long)frame * P;
     if (tid == 0) s_count = 0;
     __syncthreads();
     for (int w0 = 0; w0 < nw; w0 += NMS_THREADS) {
         const int w = w0 + tid;
-        unsigned v = 0;
         if (w < nw) {
+            unsigned v = 0;
             for (int j = 0; j < 16; ++j) {
                 const int p = 16 * w + j;
-                if (p >= P || keys[p] == 0ull) v |= DROPPED << (2 * j);
+                v |= (p < P ? (unsigned)st8[p] : (unsigned)DROPPED) << (2 * j);
             }
             if (G) __hip_atomic_store(S + w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             else S[w] = v;
@@ -238,7 +265,7 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
     }
     for (int p0 = 0; p0 < P; p0 += NMS_THREADS) {
         const int p = p0 + tid;
-        wave_append(p < P && keys[p] != 0ull, p, wl[0], &s_count);
+        wave_append(p < P && st8[p] == UNDECIDED, p, wl[0], &s_count);
     }
     __syncthreads();
 
@@ -255,9 +282,9 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
             int p = 0;
             if (i < n_in) {
                 p = in[i];
-                const unsigned* rec = lst + (long long)p * NMS_LIST;
+                const unsigned* rec = lst + p;
                 const int cnt = (int)rec[0];
-                const unsigned v = cnt < NMS_LIST ? decide_list<G>(S, rec, cnt)
+                const unsigned v = cnt < NMS_LIST ? decide_list<G>(S, rec, P, cnt)
                                                   : decide_scan<G>(T, keys, S, boxes, keys[p], inum, iden);
                 if (v != UNDECIDED) atomicOr(&S[p >> 4], v << ((p & 15) * 2));
                 else keep_working = true;
@@ -361,22 +388,26 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
 constexpr int NMS_LDS_STATE_WORDS = (150 * 1024 - SORT_CAP * 8 - 2048) / 4;
 
 hipError_t launch_nms_edges(const LevelTable& T, int n, const unsigned long long* poskey, const int2* boxes,
-                            long long iou_num, long long iou_den, unsigned* lists, hipStream_t s) {
-    hipLaunchKernelGGL(hog_nms_edges_kernel, dim3((T.pos_frame + 255) / 256, n), dim3(256), 0, s, T, poskey, boxes,
-                       iou_num, iou_den, lists);
+                            long long iou_num, long long iou_den, unsigned* lists, unsigned char* state8,
+                            int rounds, hipStream_t s) {
+    const dim3 grid((T.pos_frame + 255) / 256, n);
+    hipLaunchKernelGGL(hog_nms_edges_kernel, grid, dim3(256), 0, s, T, poskey, boxes, iou_num, iou_den, lists,
+                       state8);
+    for (int r = 0; r < rounds; ++r)
+        hipLaunchKernelGGL(hog_nms_round_kernel, grid, dim3(256), 0, s, T, lists, state8);
     return hipGetLastError();
 }
 
 hipError_t launch_nms(const LevelTable& T, int n, const unsigned long long* poskey, const unsigned* lists,
                       const int2* boxes, long long iou_num, long long iou_den, void* dets, int cap, int* n_dets,
-                      unsigned* gstate, int* work, hipStream_t s) {
+                      unsigned* gstate, int* work, const unsigned char* state8, hipStream_t s) {
     const int nw = (T.pos_frame + 15) >> 4;
     if (nw <= NMS_LDS_STATE_WORDS) {
         hipLaunchKernelGGL(hog_nms_resolve_kernel<false>, dim3(n), dim3(NMS_THREADS), nw * sizeof(unsigned), s, T,
-                           poskey, lists, boxes, iou_num, iou_den, (hog_det*)dets, cap, n_dets, gstate, work);
+                           poskey, lists, boxes, iou_num, iou_den, (hog_det*)dets, cap, n_dets, gstate, work, state8);
     } else {
         hipLaunchKernelGGL(hog_nms_resolve_kernel<true>, dim3(n), dim3(NMS_THREADS), 0, s, T, poskey, lists, boxes,
-                           iou_num, iou_den, (hog_det*)dets, cap, n_dets, gstate, work);
+                           iou_num, iou_den, (hog_det*)dets, cap, n_dets, gstate, work, state8);
     }
     return hipGetLastError();
 }
