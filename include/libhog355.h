@@ -22,7 +22,7 @@
  *    nothing was enqueued).  HOG_E_HIP means a launch failed.  No
  *    exception crosses the ABI.
  *  - Frames are 8-bit grayscale, row-major, `pitch` bytes per row
- *    (pitch >= w).  Sides are limited to 80 <= h, w <= 4096; smaller
+ *    (w <= pitch <= 65536).  Sides are limited to 80 <= h, w <= 4096; smaller
  *    frames have no pyramid level and yield no detections.
  *  - Filters are float32 [nf][10][10][31] (row, column, channel of the
  *    window), bias float32 [nf].  1 <= nf <= 32.

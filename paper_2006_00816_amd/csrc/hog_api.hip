@@ -279,7 +279,7 @@ int detect_sequence(const Plan& P, const hog_params* prm, const uint8_t* frames,
 int check_detect_args(const hog_params* prm, const void* frames, int pitch, int w, const float* filters,
                       const float* bias, int nf, const hog_det* dets, int cap, const int* n_dets) {
     if (!prm || !frames || !filters || !bias || !dets || !n_dets) return HOG_E_INVAL;
-    if (pitch < w) return HOG_E_INVAL;
+    if (pitch < w || pitch > MAX_PITCH) return HOG_E_INVAL;
     if (nf < 1) return HOG_E_INVAL;
     if (nf > MAX_FILTERS) return HOG_E_TOO_LARGE;
     if (cap < 1 || cap > MAX_DETS) return HOG_E_CAP;
@@ -349,7 +349,7 @@ size_t hog_workspace_bytes(int h, int w, int upsample, int n_frames, int nf) {
 
 int hog_features(const uint8_t* frame, int h, int w, int pitch, int upsample, float* feat, int64_t feat_cap,
                  void* ws, size_t ws_bytes, void* stream) {
-    if (!frame || !feat || pitch < w) return HOG_E_INVAL;
+    if (!frame || !feat || pitch < w || pitch > MAX_PITCH) return HOG_E_INVAL;
     Plan P;
     HOG_TRY(make_plan(h, w, upsample, 1, 0, &P));
     HOG_TRY(check_ws(P, ws, ws_bytes));
@@ -361,7 +361,7 @@ int hog_features(const uint8_t* frame, int h, int w, int pitch, int upsample, fl
 int hog_scores(const uint8_t* frame, int h, int w, int pitch, int upsample, const float* filters,
                const float* bias, int nf, float* scores, int64_t scores_cap, void* ws, size_t ws_bytes,
                void* stream) {
-    if (!frame || !filters || !bias || !scores || pitch < w || nf < 1) return HOG_E_INVAL;
+    if (!frame || !filters || !bias || !scores || pitch < w || pitch > MAX_PITCH || nf < 1) return HOG_E_INVAL;
     Plan P;
     HOG_TRY(make_plan(h, w, upsample, 1, nf, &P));
     HOG_TRY(check_ws(P, ws, ws_bytes));
@@ -447,7 +447,7 @@ int hog_graph_destroy(hog_graph* g) {
 
 int hog_level_maps(const uint8_t* frame, int h, int w, int pitch, int upsample, int level, float* level_px,
                    uint8_t* bins, float* hist, void* ws, size_t ws_bytes, void* stream) {
-    if (!frame || pitch < w) return HOG_E_INVAL;
+    if (!frame || pitch < w || pitch > MAX_PITCH) return HOG_E_INVAL;
     Plan P;
     HOG_TRY(make_plan(h, w, upsample, 1, 0, &P));
     HOG_TRY(check_ws(P, ws, ws_bytes));

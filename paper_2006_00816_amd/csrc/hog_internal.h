@@ -19,6 +19,7 @@ constexpr int MIN_SIDE = 80;
 constexpr int SIG_BITS = 40;   // fractional bits of the fixed-point inverse scale
 constexpr int MAX_LEVELS = 28;
 constexpr int MAX_SIDE = 4096;
+constexpr int MAX_PITCH = 1 << 16;  // bytes per frame row (frame offsets stay 32-bit)
 constexpr int MAX_FILTERS = 32;
 constexpr int MAX_DETS = 4096;
 
@@ -30,7 +31,7 @@ constexpr int MAX_DETS = 4096;
 constexpr int TCY = 7, TCX = 15;
 constexpr int QBY = TCY + 1, QBX = TCX + 1;     // 8 x 16 quad blocks
 constexpr int TPY = 8 * QBY + 2, TPX = 8 * QBX + 2;  // 66 x 130 level pixels incl. 1-px halo
-constexpr int HIST_THREADS = 256;
+constexpr int HIST_THREADS = 512;
 
 constexpr int FEAT_THREADS = 256;
 

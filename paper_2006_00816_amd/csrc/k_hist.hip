@@ -13,21 +13,68 @@ constexpr int PL_W = TPX / 8 + 1;                 // 17 block columns
 constexpr int PL_H = TPY / 8 + 1;                 // 9 block rows
 constexpr int PLANE = PL_W * PL_H;                // 153 (odd)
 constexpr int LC_W = TCX + 2, LC_H = TCY + 2;     // local cell grid 17 x 9
+constexpr int CS = NBINS + 1;                     // u64 words per local cell (odd: spreads LDS banks)
 
 __device__ __forceinline__ int swz(int ty, int tx) {
     return ((ty & 7) * 8 + (tx & 7)) * PLANE + (ty >> 3) * PL_W + (tx >> 3);
+}
+
+// Offset of pixel (ty, tx) relative to its quad block's origin pixel,
+// ty, tx in 0..9, in the swizzled level tile.
+__host__ __device__ constexpr int qoff(int ty, int tx) {
+    return ((ty & 7) * 8 + (tx & 7)) * PLANE + (ty >> 3) * PL_W + (tx >> 3);
+}
+
+// Sixteen pixels (offsets 16Q .. 16Q+15 of an 8x8 quad block) of one lane:
+// central differences, orientation, magnitude and four fixed-point votes.
+// All LDS offsets and weights are compile-time constants.
+template <int Q, bool CHECK>
+__device__ __forceinline__ void quad_votes(const int* __restrict__ sV, int lb, unsigned long long* __restrict__ h00,
+                                           int ylb, int xlb, int ylim, int xlim) {
+#pragma unroll
+    for (int oo = 0; oo < 16; ++oo) {
+        const int o = 16 * Q + oo;
+        const int oy = o >> 3, ox = o & 7;
+        if (CHECK) {
+            const int yl = ylb + oy, xl = xlb + ox;
+            if (yl < 1 || yl > ylim || xl < 1 || xl > xlim) continue;
+        }
+        const int gx = sV[lb + qoff(oy + 1, ox + 2)] - sV[lb + qoff(oy + 1, ox)];
+        const int gy = sV[lb + qoff(oy + 2, ox + 1)] - sV[lb + qoff(oy, ox + 1)];
+        if ((gx | gy) == 0) continue;
+        const int bin = orient_bin(gx, gy);
+        const float fx = (float)gx, fy = (float)gy;
+        const float mag = __builtin_sqrtf(fmaf(fx, fx, fy * fy));     // in units of 2^-16
+        const unsigned long long M = (unsigned int)(mag * 64.0f + 0.5f);   // mag * 2^22
+        atomicAdd(h00 + bin, M * (unsigned)((15 - 2 * oy) * (15 - 2 * ox)));
+        atomicAdd(h00 + CS + bin, M * (unsigned)((15 - 2 * oy) * (2 * ox + 1)));
+        atomicAdd(h00 + LC_W * CS + bin, M * (unsigned)((2 * oy + 1) * (15 - 2 * ox)));
+        atomicAdd(h00 + (LC_W + 1) * CS + bin, M * (unsigned)((2 * oy + 1) * (2 * ox + 1)));
+    }
+}
+
+template <bool CHECK>
+__device__ __forceinline__ void quad_votes_q(int q, const int* sV, int lb, unsigned long long* h00, int ylb, int xlb,
+                                             int ylim, int xlim) {
+    switch (q) {
+        case 0: quad_votes<0, CHECK>(sV, lb, h00, ylb, xlb, ylim, xlim); break;
+        case 1: quad_votes<1, CHECK>(sV, lb, h00, ylb, xlb, ylim, xlim); break;
+        case 2: quad_votes<2, CHECK>(sV, lb, h00, ylb, xlb, ylim, xlim); break;
+        default: quad_votes<3, CHECK>(sV, lb, h00, ylb, xlb, ylim, xlim); break;
+    }
 }
 
 // One workgroup = one tile of TCY x TCX cells of one level of one frame.
 //  1. Level pixels of the tile (plus the pixels whose votes reach it and a
 //     one-pixel gradient halo) are resampled from the frame: 8-bit
 //     bilinear weights, exact in integers (value * 2^16).
-//  2. Each lane owns one 8x8 quad block and walks its pixels: central
-//     differences, orientation bin, magnitude, and four votes
-//     mag * wy * wx into the four cells around the block.  Votes are
-//     accumulated as 64-bit fixed point (mag * 2^22 times the integer
-//     weight product out of 256) with LDS integer atomics, so the sums do
-//     not depend on the order of the additions.
+//  2. Each lane owns one 8x8 quad block (the pixels between four cell
+//     centres, which all vote into the same four cells) and a quarter of
+//     its pixels: central differences, orientation bin, magnitude, and
+//     four votes mag * wy * wx.  Votes are accumulated as 64-bit fixed
+//     point (mag * 2^22 times the integer weight product out of 256) with
+//     LDS integer atomics, so the sums do not depend on the order of the
+//     additions.
 //  3. Complete cells are converted to float (value * 2^-30) and written
 //     with their energy sum_o (h_o + h_{o+9})^2 (Sec. IV-A normalisation,
 //     Sec. V-A energy kernel).
@@ -35,7 +82,7 @@ __global__ __launch_bounds__(HIST_THREADS) void hog_hist_kernel(
     LevelTable T, const uint8_t* __restrict__ frames, long long fstride, int pitch,
     const int4* __restrict__ taps, float* __restrict__ hist) {
     __shared__ int sV[64 * PLANE];
-    __shared__ unsigned long long sH[LC_H * LC_W * NBINS];
+    __shared__ unsigned long long sH[LC_H * LC_W * CS];
     __shared__ int4 sTy[TPY], sTx[TPX];
 
     const int tid = threadIdx.x;
@@ -48,11 +95,16 @@ __global__ __launch_bounds__(HIST_THREADS) void hog_hist_kernel(
     const int ybase = 8 * i0 - 5, xbase = 8 * j0 - 5;   // level coords of tile pixel (0, 0)
     const uint8_t* __restrict__ U = frames + (long long)frame * fstride;
 
-    for (int e = tid; e < LC_H * LC_W * NBINS; e += HIST_THREADS) sH[e] = 0ull;
+    for (int e = tid; e < LC_H * LC_W * CS; e += HIST_THREADS) sH[e] = 0ull;
     for (int e = tid; e < TPY + TPX; e += HIST_THREADS) {
         if (e < TPY) {
             const int y = ybase + e;
-            sTy[e] = (y >= 0 && y < L.h) ? taps[L.tap_y + y] : make_int4(0, 0, 0, -1);
+            int4 a = make_int4(0, 0, 0, -1);
+            if (y >= 0 && y < L.h) {
+                const int4 tp = taps[L.tap_y + y];
+                a = make_int4(tp.x * pitch, tp.y * pitch, tp.z, 0);   // row byte offsets
+            }
+            sTy[e] = a;
         } else {
             const int x = xbase + e - TPY;
             sTx[e - TPY] = (x >= 0 && x < L.w) ? taps[L.tap_x + x] : make_int4(0, 0, 0, -1);
@@ -66,14 +118,13 @@ __global__ __launch_bounds__(HIST_THREADS) void hog_hist_kernel(
         const int4 a = sTy[ty], b = sTx[tx];
         int v = 0;
         if ((a.w | b.w) == 0) {
-            const uint8_t* r0 = U + (long long)a.x * pitch;
-            const int u00 = r0[b.x];
-            const int u01 = b.z ? (int)r0[b.y] : 0;
-            int top = (256 - b.z) * u00 + b.z * u01;
+            const unsigned o00 = (unsigned)(a.x + b.x);
+            int top = (256 - b.z) * (int)U[o00];
+            if (b.z) top += b.z * (int)U[(unsigned)(a.x + b.y)];
             int bot = 0;
             if (a.z) {
-                const uint8_t* r1 = U + (long long)a.y * pitch;
-                bot = (256 - b.z) * (int)r1[b.x] + (b.z ? b.z * (int)r1[b.y] : 0);
+                bot = (256 - b.z) * (int)U[(unsigned)(a.y + b.x)];
+                if (b.z) bot += b.z * (int)U[(unsigned)(a.y + b.y)];
             }
             v = (256 - a.z) * top + a.z * bot;
         }
@@ -85,30 +136,15 @@ __global__ __launch_bounds__(HIST_THREADS) void hog_hist_kernel(
     const int wave = tid >> 6, lane = tid & 63;
     const int qa = (wave & 1) * 4 + (lane >> 4);      // quad-block row 0..7
     const int qb = lane & 15;                         // quad-block column 0..15
-    const int obase = (wave >> 1) * 32;               // this wave's half of the 64 offsets
-    const int vy = 8 * L.cy, vx = 8 * L.cx;           // voting region
-    unsigned long long* h00 = &sH[(qa * LC_W + qb) * NBINS];
-    for (int oo = 0; oo < 32; ++oo) {
-        const int o = obase + oo;
-        const int oy = o >> 3, ox = o & 7;
-        const int ty = 8 * qa + 1 + oy, tx = 8 * qb + 1 + ox;
-        const int yl = ybase + ty, xl = xbase + tx;
-        const bool in = yl >= 1 && yl < vy && yl <= L.h - 2 && xl >= 1 && xl < vx && xl <= L.w - 2;
-        if (!in) continue;
-        const int gx = sV[swz(ty, tx + 1)] - sV[swz(ty, tx - 1)];
-        const int gy = sV[swz(ty + 1, tx)] - sV[swz(ty - 1, tx)];
-        if ((gx | gy) == 0) continue;
-        const int bin = orient_bin(gx, gy);
-        const float fx = (float)gx, fy = (float)gy;
-        const float mag = __builtin_sqrtf(fmaf(fx, fx, fy * fy));     // in units of 2^-16
-        const unsigned int M = (unsigned int)(mag * 64.0f + 0.5f);      // mag * 2^22
-        const unsigned int wy0 = 15 - 2 * oy, wy1 = 2 * oy + 1;
-        const unsigned int wx0 = 15 - 2 * ox, wx1 = 2 * ox + 1;
-        atomicAdd(h00 + bin, (unsigned long long)M * (wy0 * wx0));
-        atomicAdd(h00 + NBINS + bin, (unsigned long long)M * (wy0 * wx1));
-        atomicAdd(h00 + LC_W * NBINS + bin, (unsigned long long)M * (wy1 * wx0));
-        atomicAdd(h00 + (LC_W + 1) * NBINS + bin, (unsigned long long)M * (wy1 * wx1));
-    }
+    const int q = wave >> 1;                          // quarter of the 64 pixel offsets
+    const int lb = qa * PL_W + qb;                    // swizzled base of the quad block
+    unsigned long long* h00 = &sH[(qa * LC_W + qb) * CS];
+    // valid pixels: 1 <= y <= min(8 cy - 1, h - 2), same for x
+    const int ylim = min(8 * L.cy - 1, L.h - 2), xlim = min(8 * L.cx - 1, L.w - 2);
+    const bool inner = ybase + 1 >= 1 && ybase + TPY - 2 <= ylim && xbase + 1 >= 1 && xbase + TPX - 2 <= xlim;
+    const int ylb = ybase + 8 * qa + 1, xlb = xbase + 8 * qb + 1;
+    if (inner) quad_votes_q<false>(q, sV, lb, h00, ylb, xlb, ylim, xlim);
+    else quad_votes_q<true>(q, sV, lb, h00, ylb, xlb, ylim, xlim);
     __syncthreads();
 
     // 3. complete cells -> float histograms + energy
@@ -116,7 +152,7 @@ __global__ __launch_bounds__(HIST_THREADS) void hog_hist_kernel(
         const int li = tid / TCX, lj = tid - li * TCX;
         const int gi = i0 + li, gj = j0 + lj;
         if (gi < L.cy && gj < L.cx) {
-            const unsigned long long* src = &sH[((li + 1) * LC_W + lj + 1) * NBINS];
+            const unsigned long long* src = &sH[((li + 1) * LC_W + lj + 1) * CS];
             float h[NBINS];
 #pragma unroll
             for (int b = 0; b < NBINS; ++b) h[b] = (float)((double)src[b] * 0x1p-30);
