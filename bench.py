@@ -55,6 +55,20 @@ def cpu_baseline(frames, W, b, budget_frames):
                       f"one process per frame on {cores} host cores, {dt:.1f} s wall"}
 
 
+def copy_calibration(mib):
+    """A plain device-to-device copy of known size, to scale the HBM byte
+    counters (FETCH_SIZE, WRITE_SIZE) of the detector's kernels."""
+    import torch
+    torch.cuda.set_device(0)
+    n = mib << 20
+    src = torch.randint(0, 255, (n,), dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n, "copies": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,11 +78,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=32)
     ap.add_argument("--kernel-steps", type=int, default=100, help="eager steps timed per kernel (0: skip)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="only run device-to-device copies of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the detector shards by frame with no collective on the "
               "hot path, and multi-GPU runs are not part of this build", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibration_mib:
+        copy_calibration(args.copy_calibration_mib)
+        return
 
     from paper_2006_00816_amd import synth
 
