@@ -88,6 +88,12 @@ typedef struct hog_det {
     float   score;
 } hog_det;
 
+/* A window: filter f of pyramid level k anchored at cell (row, col) of
+ * frame `frame` of a batch. */
+typedef struct hog_window {
+    int32_t frame, filter, level, row, col;
+} hog_window;
+
 /* Version of the library, as major*10000 + minor*100 + patch.  Host only. */
 int hog_version(void);
 
@@ -178,6 +184,56 @@ int hog_level_maps(const uint8_t* frame, int h, int w, int pitch, int upsample, 
  * n <= 2^31 - 1.  Sec. IV-A: one of eighteen signed directions. */
 int hog_orient_bins(const int32_t* gx, const int32_t* gy, int64_t n,
                     uint8_t* bins, void* stream);
+
+/* Bytes of workspace needed by hog_window_scores, hog_topk_windows and
+ * hog_filter_backward for n_frames frames of h x w, nf filters and up to
+ * n_windows windows.  0 on invalid arguments.  Host only. */
+size_t hog_grad_workspace_bytes(int h, int w, int upsample, int n_frames, int nf, int n_windows);
+
+/* Scores of listed windows (Sec. IV-A, linear classification filter):
+ * scores[i] = bias[f_i] + <filter f_i, 10x10x31 features of window i>.
+ * `windows` (device, n_windows) index frames of the batch as in
+ * hog_detect_batch; the features are computed from the frames in this
+ * call.  Used as the forward pass of filter training. */
+int hog_window_scores(const uint8_t* frames, int n, int h, int w, int pitch, int64_t frame_stride, int upsample,
+                      const float* filters, const float* bias, int nf,
+                      const hog_window* windows, int n_windows, float* scores,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* The k (1..16) best windows of every frame over all filters, levels and
+ * positions, before thresholding and NMS, in rank order (score
+ * descending, then filter, level, row, column ascending).  Outputs
+ * (device): windows [n][k], scores [n][k]. */
+int hog_topk_windows(const uint8_t* frames, int n, int h, int w, int pitch, int64_t frame_stride, int upsample,
+                     const float* filters, const float* bias, int nf, int k,
+                     hog_window* windows, float* scores,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/* Backward pass of window scores.  With upstream gradients dscore[i] for
+ * windows[i] (device arrays of n_windows):
+ *   dfilters[f] += sum_i [f_i = f] dscore[i] * features(window i)   (float32 [nf][10][10][31])
+ *   dbias[f]    += sum_i [f_i = f] dscore[i]                         (float32 [nf], may be NULL)
+ *   dpixels     += sum_i dscore[i] * d score_i / d frame pixels      (float32 [n][h][w], may be NULL)
+ * The features of each window's support (its 10x10 cells and the ring of
+ * cells whose energies normalise them) are recomputed from the frames;
+ * nothing is kept from a forward call.  The pixel gradient runs through
+ * the clip at 0.2, the block normalisation and energies, the bilinear cell
+ * votes, the gradient magnitude (d mag / d g = g / mag, 0 at mag = 0), the
+ * central differences and the pyramid resampling, with orientation bins
+ * and clip decisions held at their forward values.  dfilters and dbias are
+ * summed in a fixed order (deterministic); dpixels with atomic adds. */
+int hog_filter_backward(const uint8_t* frames, int n, int h, int w, int pitch, int64_t frame_stride, int upsample,
+                        const float* filters, int nf,
+                        const hog_window* windows, const float* dscore, int n_windows,
+                        float* dfilters, float* dbias, float* dpixels,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/* Mean hinge loss of scores with labels +-1 plus l2 * ||filters||^2
+ * (bias not regularised): loss (device float[1]) = mean_i max(0, 1 - y_i s_i)
+ * + l2 ||W||^2; dscore[i] = -y_i / n where y_i s_i < 1, else 0; and
+ * dfilters += 2 l2 filters.  n <= 2^30. */
+int hog_hinge_loss(const float* scores, const float* labels, int n, const float* filters, int nf, float l2,
+                   float* loss, float* dscore, float* dfilters, void* stream);
 
 /* Kernel timing with HIP events, for benchmarks.  While enabled, each
  * launch of the library's kernels outside graph capture is bracketed by

@@ -22,6 +22,8 @@ HIPCC_FLAGS = [
     # no packed-FP32 instructions (v_pk_fma_f32 and friends)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
+    # hardware float atomic add for the pixel-gradient scatter
+    "-munsafe-fp-atomics",
 ]
 
 

@@ -19,7 +19,7 @@ struct Plan {
     int n = 0, nf = 0, groups = 0;
     // workspace offsets (bytes)
     size_t o_taps = 0, o_boxes = 0, o_bpack = 0, o_hist = 0, o_feat = 0, o_key = 0, o_state = 0, o_list = 0,
-           o_work = 0, o_state8 = 0, total = 0;
+           o_work = 0, o_state8 = 0, o_dense = 0, o_partial = 0, total = 0;
     long long packed_floats = 0, dense_floats = 0;
 };
 
@@ -62,7 +62,9 @@ void box_bounds(long long sig, int* lo, int* hi) {
     *hi = (int)fl + 1;
 }
 
-int make_plan(int h, int w, int u, int n, int nf, Plan* P) {
+// n_windows > 0 adds the regions of the gradient calls: dense scores of
+// every frame and the per-workgroup partial filter gradients.
+int make_plan(int h, int w, int u, int n, int nf, Plan* P, int n_windows = 0) {
     int st = check_frame(h, w, u);
     if (st) return st;
     if (n < 1 || nf < 0) return HOG_E_INVAL;
@@ -170,6 +172,15 @@ int make_plan(int h, int w, int u, int n, int nf, Plan* P) {
     o = align256(o + sizeof(int) * 2 * (size_t)n * std::max(pos, 1LL));
     P->o_state8 = o;
     o = align256(o + (size_t)n * std::max(pos, 1LL));
+    T.dense_frame = (int)sc;
+    P->o_dense = o;
+    P->o_partial = o;
+    if (n_windows > 0) {
+        o = align256(o + sizeof(float) * (size_t)n * std::max(sc, 1LL));
+        P->o_partial = o;
+        o = align256(o + sizeof(float) * (size_t)backward_groups(n_windows) *
+                             ((size_t)std::max(nf, 1) * WIN * WIN * NFEAT + std::max(nf, 1)));
+    }
     P->total = o;
     return HOG_OK;
 }
@@ -473,6 +484,85 @@ int hog_level_maps(const uint8_t* frame, int h, int w, int pitch, int upsample, 
             return HOG_E_HIP;
     }
     return HOG_OK;
+}
+
+size_t hog_grad_workspace_bytes(int h, int w, int upsample, int n_frames, int nf, int n_windows) {
+    Plan P;
+    if (nf < 1 || make_plan(h, w, upsample, n_frames, nf, &P, std::max(n_windows, 1)) != HOG_OK) return 0;
+    return P.total;
+}
+
+int hog_window_scores(const uint8_t* frames, int n, int h, int w, int pitch, int64_t frame_stride, int upsample,
+                      const float* filters, const float* bias, int nf, const hog_window* windows, int n_windows,
+                      float* scores, void* ws, size_t ws_bytes, void* stream) {
+    if (!frames || !filters || !bias || !windows || !scores || pitch < w || pitch > MAX_PITCH) return HOG_E_INVAL;
+    if (n < 1 || nf < 1 || n_windows < 0 || (n > 1 && frame_stride < (int64_t)pitch * h)) return HOG_E_INVAL;
+    Plan P;
+    HOG_TRY(make_plan(h, w, upsample, n, nf, &P, std::max(n_windows, 1)));
+    HOG_TRY(check_ws(P, ws, ws_bytes));
+    if (P.T.n == 0 || n_windows == 0) return n_windows == 0 ? HOG_OK : HOG_E_INVAL;
+    hipStream_t s = (hipStream_t)stream;
+    HOG_TRY(run_pixels(P, frames, frame_stride, pitch, ws, nullptr, nullptr, s, false));
+    return timed("window_scores", s, [&] {
+        return launch_window_scores(P.T, at<float>(ws, P.o_feat), windows, n_windows, filters, bias, scores, s);
+    });
+}
+
+int hog_topk_windows(const uint8_t* frames, int n, int h, int w, int pitch, int64_t frame_stride, int upsample,
+                     const float* filters, const float* bias, int nf, int k, hog_window* windows, float* scores,
+                     void* ws, size_t ws_bytes, void* stream) {
+    if (!frames || !filters || !bias || !windows || !scores || pitch < w || pitch > MAX_PITCH) return HOG_E_INVAL;
+    if (n < 1 || nf < 1 || k < 1 || k > 16 || (n > 1 && frame_stride < (int64_t)pitch * h)) return HOG_E_INVAL;
+    if (nf > MAX_FILTERS) return HOG_E_TOO_LARGE;
+    Plan P;
+    HOG_TRY(make_plan(h, w, upsample, n, nf, &P, 1));
+    HOG_TRY(check_ws(P, ws, ws_bytes));
+    if (P.T.n == 0) return HOG_E_INVAL;
+    long long total = 0;
+    for (int l = 0; l < P.T.n; ++l) total += (long long)P.T.L[l].rows * P.T.L[l].cols * nf;
+    if (total < k) return HOG_E_INVAL;
+    hipStream_t s = (hipStream_t)stream;
+    HOG_TRY(run_pixels(P, frames, frame_stride, pitch, ws, nullptr, filters, s, false));
+    HOG_TRY(timed("score", s, [&] {
+        return launch_score(P.T, n, at<float>(ws, P.o_feat), at<float4>(ws, P.o_bpack), bias, nf, 0.f,
+                            at<float>(ws, P.o_dense), nullptr, false, s);
+    }));
+    return timed("topk", s, [&] {
+        return launch_topk(P.T, n, at<float>(ws, P.o_dense), P.T.dense_frame, nf, k, windows, scores, s);
+    });
+}
+
+int hog_filter_backward(const uint8_t* frames, int n, int h, int w, int pitch, int64_t frame_stride, int upsample,
+                        const float* filters, int nf, const hog_window* windows, const float* dscore, int n_windows,
+                        float* dfilters, float* dbias, float* dpixels, void* ws, size_t ws_bytes, void* stream) {
+    if (!frames || !filters || !windows || !dscore || !dfilters || pitch < w || pitch > MAX_PITCH) return HOG_E_INVAL;
+    if (n < 1 || nf < 1 || n_windows < 0 || (n > 1 && frame_stride < (int64_t)pitch * h)) return HOG_E_INVAL;
+    if (nf > MAX_FILTERS) return HOG_E_TOO_LARGE;
+    Plan P;
+    HOG_TRY(make_plan(h, w, upsample, n, nf, &P, std::max(n_windows, 1)));
+    HOG_TRY(check_ws(P, ws, ws_bytes));
+    if (n_windows == 0) return HOG_OK;
+    if (P.T.n == 0) return HOG_E_INVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const LevelTable& T = P.T;
+    HOG_TRY(timed("geom", s, [&] {
+        return launch_setup(T, at<int4>(ws, P.o_taps), at<int2>(ws, P.o_boxes), nullptr, 0, nullptr, nullptr, 0, s);
+    }));
+    return timed("backward", s, [&] {
+        return launch_backward(T, frames, frame_stride, pitch, at<int4>(ws, P.o_taps), filters, windows, dscore,
+                               n_windows, nf, at<float>(ws, P.o_partial), dfilters, dbias, dpixels, s);
+    });
+}
+
+int hog_hinge_loss(const float* scores, const float* labels, int n, const float* filters, int nf, float l2,
+                   float* loss, float* dscore, float* dfilters, void* stream) {
+    if (!scores || !labels || !filters || !loss || !dscore || !dfilters || n < 1 || n > (1 << 30) || nf < 1)
+        return HOG_E_INVAL;
+    if (nf > MAX_FILTERS) return HOG_E_TOO_LARGE;
+    hipStream_t s = (hipStream_t)stream;
+    return timed("hinge", s, [&] {
+        return launch_hinge(scores, labels, n, filters, nf * WIN * WIN * NFEAT, l2, loss, dscore, dfilters, s);
+    });
 }
 
 int hog_orient_bins(const int32_t* gx, const int32_t* gy, int64_t n, uint8_t* bins, void* stream) {

@@ -76,6 +76,7 @@ struct LevelTable {
     int pos_frame;                // window positions per frame
     int taps_total, boxes_total;  // geometry table entries
     int h, w, upsample;
+    int dense_frame;              // floats of dense scores per frame: sum over levels of nf * rows * cols
     DevLevel L[MAX_LEVELS];
 };
 
@@ -126,5 +127,16 @@ hipError_t launch_orient(const int32_t* gx, const int32_t* gy, long long n, uint
                          hipStream_t s);
 hipError_t launch_fill(int* p, int n, int v, hipStream_t s);
 void orientation_table_host(double* c, double* s);
+hipError_t launch_window_scores(const LevelTable& T, const float* feat, const hog_window* win, int n_win,
+                                const float* W, const float* bias, float* scores, hipStream_t s);
+hipError_t launch_topk(const LevelTable& T, int n, const float* dense, long long dense_frame, int nf, int K,
+                       hog_window* out, float* out_scores, hipStream_t s);
+hipError_t launch_hinge(const float* S, const float* y, int n, const float* W, int nw, float lam, float* loss,
+                        float* dscore, float* dW, hipStream_t s);
+int backward_groups(int n_win);
+size_t backward_lds_bytes();
+hipError_t launch_backward(const LevelTable& T, const uint8_t* frames, long long fstride, int pitch, const int4* taps,
+                           const float* W, const hog_window* win, const float* dscore, int n_win, int nf,
+                           float* partial, float* dW, float* db, float* dpixels, hipStream_t s);
 
 }  // namespace hog

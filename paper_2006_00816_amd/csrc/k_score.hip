@@ -83,7 +83,7 @@ __global__ __launch_bounds__(SCORE_THREADS) void hog_score_kernel(
             const bool ok = fok && a < nanch && c < L.cols;
             const float s = acc[t][i] + bf;
             if (dense && ok)
-                dense[L.sc_off + ((long long)f * L.rows + r) * L.cols + c] = s;
+                dense[(long long)frame * T.dense_frame + L.sc_off + ((long long)f * L.rows + r) * L.cols + c] = s;
             unsigned long long key = 0ull;
             if (ok && s > thresh)
                 key = ((unsigned long long)score_order(s) << 32) | (unsigned long long)(~pack_window(f, k, r, c));

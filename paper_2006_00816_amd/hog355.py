@@ -66,6 +66,12 @@ def lib():
         "hog_graph_destroy": ([vp], i32),
         "hog_level_maps": ([vp, i32, i32, i32, i32, i32, vp, vp, vp, vp, sz, vp], i32),
         "hog_orient_bins": ([vp, vp, i64, vp, vp], i32),
+        "hog_grad_workspace_bytes": ([i32, i32, i32, i32, i32, i32], sz),
+        "hog_window_scores": ([vp, i32, i32, i32, i32, i64, i32, vp, vp, i32, vp, i32, vp, vp, sz, vp], i32),
+        "hog_topk_windows": ([vp, i32, i32, i32, i32, i64, i32, vp, vp, i32, i32, vp, vp, vp, sz, vp], i32),
+        "hog_filter_backward": ([vp, i32, i32, i32, i32, i64, i32, vp, i32, vp, vp, i32, vp, vp, vp, vp, sz, vp],
+                                i32),
+        "hog_hinge_loss": ([vp, vp, i32, vp, i32, ctypes.c_float, vp, vp, vp, vp], i32),
         "hog_profile_enable": ([i32], i32),
         "hog_profile_reset": ([], i32),
         "hog_profile_read": ([ctypes.c_char_p, vp, vp], i32),
@@ -285,6 +291,104 @@ def orient_bins(gx: torch.Tensor, gy: torch.Tensor) -> torch.Tensor:
     out = torch.empty(gx.shape, dtype=torch.uint8, device=gx.device)
     _check(lib().hog_orient_bins(_ptr(gx), _ptr(gy), gx.numel(), _ptr(out), _stream()), "hog_orient_bins")
     return out
+
+
+# ------------------------------------------------------------ gradients
+def _frames_args(frames: torch.Tensor):
+    if frames.dtype != torch.uint8 or frames.dim() != 3:
+        raise HogError("frames must be a uint8 [n][h][w] device tensor")
+    n, h, w = (int(v) for v in frames.shape)
+    return n, h, w, int(frames.stride(1)), int(frames.stride(0))
+
+
+def grad_workspace_bytes(h, w, upsample, n, nf, n_windows) -> int:
+    b = lib().hog_grad_workspace_bytes(h, w, upsample, n, nf, n_windows)
+    if b == 0:
+        raise HogError("hog_grad_workspace_bytes: invalid arguments")
+    return int(b)
+
+
+def windows_tensor(frame, filt, level, row, col, device="cuda"):
+    """hog_window records as an int32 [n][5] tensor."""
+    cols = [torch.as_tensor(v, dtype=torch.int32).reshape(-1) for v in (frame, filt, level, row, col)]
+    n = max(c.numel() for c in cols)
+    cols = [c.expand(n) if c.numel() == 1 else c for c in cols]
+    return torch.stack(cols, 1).contiguous().to(device)
+
+
+def window_scores(frames: torch.Tensor, W, b, windows: torch.Tensor, upsample: int = 1, ws=None):
+    """Scores of the listed windows (int32 [m][5] hog_window records)."""
+    n, h, w, pitch, stride = _frames_args(frames)
+    m = int(windows.shape[0])
+    nf = int(W.shape[0])
+    out = torch.empty(m, dtype=torch.float32, device=frames.device)
+    wp, wn = _ws(ws, grad_workspace_bytes(h, w, upsample, n, nf, m))
+    _check(lib().hog_window_scores(_ptr(frames), n, h, w, pitch, stride, upsample, _ptr(W), _ptr(b), nf,
+                                   _ptr(windows), m, _ptr(out), wp, wn, _stream()), "hog_window_scores")
+    return out
+
+
+def topk_windows(frames: torch.Tensor, W, b, k: int = 10, upsample: int = 1, ws=None):
+    """The k best windows per frame: (int32 [n][k][5] records, float32 [n][k] scores)."""
+    n, h, w, pitch, stride = _frames_args(frames)
+    nf = int(W.shape[0])
+    win = torch.empty((n, k, 5), dtype=torch.int32, device=frames.device)
+    sc = torch.empty((n, k), dtype=torch.float32, device=frames.device)
+    wp, wn = _ws(ws, grad_workspace_bytes(h, w, upsample, n, nf, 1))
+    _check(lib().hog_topk_windows(_ptr(frames), n, h, w, pitch, stride, upsample, _ptr(W), _ptr(b), nf, k,
+                                  _ptr(win), _ptr(sc), wp, wn, _stream()), "hog_topk_windows")
+    return win, sc
+
+
+def filter_backward(frames: torch.Tensor, W, windows: torch.Tensor, dscore: torch.Tensor, upsample: int = 1,
+                    pixels: bool = False, dW=None, db=None, ws=None):
+    """(dW, db, dpixels or None) for upstream score gradients dscore [m]."""
+    n, h, w, pitch, stride = _frames_args(frames)
+    m = int(windows.shape[0])
+    nf = int(W.shape[0])
+    dW = torch.zeros_like(W) if dW is None else dW
+    db = torch.zeros(nf, dtype=torch.float32, device=frames.device) if db is None else db
+    dpix = torch.zeros((n, h, w), dtype=torch.float32, device=frames.device) if pixels else None
+    wp, wn = _ws(ws, grad_workspace_bytes(h, w, upsample, n, nf, m))
+    _check(lib().hog_filter_backward(_ptr(frames), n, h, w, pitch, stride, upsample, _ptr(W), nf, _ptr(windows),
+                                     _ptr(dscore), m, _ptr(dW), _ptr(db), _ptr(dpix) if pixels else None, wp, wn,
+                                     _stream()), "hog_filter_backward")
+    return dW, db, dpix
+
+
+def hinge_loss(scores: torch.Tensor, labels: torch.Tensor, W: torch.Tensor, l2: float = 1e-4, dW=None):
+    """(loss [1], dscore [n], dW) with dW += 2 l2 W."""
+    n = int(scores.numel())
+    loss = torch.empty(1, dtype=torch.float32, device=scores.device)
+    dscore = torch.empty(n, dtype=torch.float32, device=scores.device)
+    dW = torch.zeros_like(W) if dW is None else dW
+    _check(lib().hog_hinge_loss(_ptr(scores), _ptr(labels), n, _ptr(W), int(W.shape[0]), ctypes.c_float(l2),
+                                _ptr(loss), _ptr(dscore), _ptr(dW), _stream()), "hog_hinge_loss")
+    return loss, dscore, dW
+
+
+class HogScore(torch.autograd.Function):
+    """Window scores as a differentiable function of the filters and bias:
+    forward hog_window_scores, backward hog_filter_backward (features
+    recomputed from the frames)."""
+
+    @staticmethod
+    def forward(ctx, W, b, frames, windows, upsample=1):
+        ctx.save_for_backward(W, frames, windows)
+        ctx.upsample = upsample
+        return window_scores(frames, W.detach().contiguous(), b.detach().contiguous(), windows, upsample)
+
+    @staticmethod
+    def backward(ctx, dscore):
+        W, frames, windows = ctx.saved_tensors
+        dW, db, _ = filter_backward(frames, W.detach().contiguous(), windows, dscore.contiguous().float(),
+                                    ctx.upsample)
+        return dW, db, None, None, None
+
+
+def pixel_gradient(frames: torch.Tensor, W, windows: torch.Tensor, dscore: torch.Tensor, upsample: int = 1):
+    """d(sum_i dscore_i * score_i) / d(frame pixels), float32 [n][h][w]."""
+    return filter_backward(frames, W, windows, dscore, upsample, pixels=True)[2]
 
 
 # ------------------------------------------------------------ profiling
