@@ -78,6 +78,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=32)
     ap.add_argument("--kernel-steps", type=int, default=100, help="eager steps timed per kernel (0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=3.0,
+                    help="seconds of served Poisson stream per rate (0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run device-to-device copies of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -199,6 +201,12 @@ def main():
         "paper_context": {"ms_per_frame": 0.333, "hardware": "NVIDIA Titan X (Pascal), 16 images per launch",
                           "end_to_end_ms_per_frame": 0.533},
     }
+    if args.serve_seconds > 0:
+        # served stream: Poisson arrivals, 40/40/20 % 320x240 / 640x480 / 1280x720
+        from paper_2006_00816_amd import serve
+        pools, Ws, bs = serve.pinned_pools(per_res=64)
+        out["served"] = [serve.served_stream(rate, args.serve_seconds, Ws, bs, pools)[0]
+                         for rate in (500.0, 2000.0, 8000.0)]
     if cpu is not None:
         out["cpu_baseline"] = cpu
     g.close()

@@ -1,0 +1,171 @@
+"""Continuous-batching detection server.
+
+Frames of mixed resolutions arrive as requests (here replayed from
+Poisson arrival times).  The server keeps the filters, the pyramid
+workspaces and the frame buffers resident on the device.  A request is
+admitted into a batch as soon as a slot frees up: a slot is a stream with
+its own pre-sized workspace slab, so admission is by free workspace
+memory.  Each batch takes the waiting frames of one resolution (oldest
+first), copies them host to device asynchronously, runs hog_detect_batch
+and copies the detections back, all on the slot's stream; batches on
+different slots overlap on the GPU while new requests keep arriving.
+Latency is completion time minus arrival time.
+
+    python -m paper_2006_00816_amd.serve --rates 500,2000,8000 --seconds 60
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import dataclasses
+import json
+import time
+
+import numpy as np
+import torch
+
+from . import hog355, synth
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    shape: tuple
+    frame: torch.Tensor          # pinned host uint8 [h][w]
+    arrival: float               # seconds on the server clock
+    done: float = -1.0
+    n_dets: int = 0
+    dets: np.ndarray = None
+
+
+class _Slot:
+    def __init__(self, max_batch, max_bytes, ws_bytes, cap, device):
+        self.stream = torch.cuda.Stream(device=device)
+        self.frames = torch.empty(max_batch * max_bytes, dtype=torch.uint8, device=device)
+        self.ws = hog355.Workspace(device)
+        self.ws.get(ws_bytes)
+        self.dets = torch.empty((max_batch, cap, 10), dtype=torch.int32, device=device)
+        self.n_dets = torch.empty(max_batch, dtype=torch.int32, device=device)
+        self.h_dets = torch.empty((max_batch, cap, 10), dtype=torch.int32).pin_memory()
+        self.h_n = torch.empty(max_batch, dtype=torch.int32).pin_memory()
+        self.event = torch.cuda.Event()
+        self.batch = None
+
+
+class HogServer:
+    def __init__(self, W: torch.Tensor, b: torch.Tensor, shapes, max_batch: int = 16, slots: int = 3,
+                 cap: int = 256, thresh: float = 0.0, iou: float = 0.5, device="cuda"):
+        self.W, self.b = W, b
+        self.max_batch, self.cap, self.thresh, self.iou = max_batch, cap, thresh, iou
+        nf = int(W.shape[0])
+        max_bytes = max(h * w for h, w in shapes)
+        ws_bytes = max(hog355.workspace_bytes(h, w, 1, max_batch, nf) for h, w in shapes)
+        self.slots = [_Slot(max_batch, max_bytes, ws_bytes, cap, device) for _ in range(slots)]
+        self.pending = collections.OrderedDict((tuple(s), collections.deque()) for s in shapes)
+        self.completed = []
+        self.batches = 0
+
+    def submit(self, req: Request):
+        self.pending[req.shape].append(req)
+
+    def _launch(self, slot: _Slot, reqs):
+        h, w = reqs[0].shape
+        n = len(reqs)
+        with torch.cuda.stream(slot.stream):
+            fr = slot.frames[:n * h * w].view(n, h, w)
+            for i, r in enumerate(reqs):
+                fr[i].copy_(r.frame, non_blocking=True)
+            hog355.detect_batch_into(fr, self.W, self.b, slot.dets[:n], slot.n_dets[:n], self.thresh, self.iou,
+                                     1, ws=slot.ws)
+            slot.h_dets[:n].copy_(slot.dets[:n], non_blocking=True)
+            slot.h_n[:n].copy_(slot.n_dets[:n], non_blocking=True)
+            slot.event.record(slot.stream)
+        slot.batch = reqs
+        self.batches += 1
+
+    def pump(self, now_fn) -> int:
+        """Retire finished batches, then fill free slots; returns the number
+        of requests in flight."""
+        for slot in self.slots:
+            if slot.batch is not None and slot.event.query():
+                t = now_fn()
+                for i, r in enumerate(slot.batch):
+                    r.done = t
+                    r.n_dets = int(slot.h_n[i])
+                    m = min(r.n_dets, self.cap)
+                    r.dets = slot.h_dets[i, :m].numpy().copy().view(hog355.DET_DTYPE).reshape(m)
+                    self.completed.append(r)
+                slot.batch = None
+        for slot in self.slots:
+            if slot.batch is not None:
+                continue
+            # the resolution whose oldest waiting request arrived first
+            best = None
+            for shape, q in self.pending.items():
+                if q and (best is None or q[0].arrival < self.pending[best][0].arrival):
+                    best = shape
+            if best is None:
+                break
+            q = self.pending[best]
+            reqs = [q.popleft() for _ in range(min(len(q), self.max_batch))]
+            self._launch(slot, reqs)
+        return sum(len(s.batch) for s in self.slots if s.batch is not None)
+
+
+def run_stream(server: HogServer, frames, shapes, arrivals):
+    """Replay requests at their arrival times (seconds from start) and wait
+    for all of them; returns the completed requests."""
+    t0 = time.perf_counter()
+    now = lambda: time.perf_counter() - t0
+    i = 0
+    n = len(arrivals)
+    while i < n or server.pump(now) or any(server.pending.values()):
+        t = now()
+        while i < n and arrivals[i] <= t:
+            server.submit(Request(i, shapes[i], frames[i], float(arrivals[i])))
+            i += 1
+        server.pump(now)
+    return sorted(server.completed, key=lambda r: r.rid)
+
+
+def served_stream(rate: float, seconds: float, W, b, pools_pinned, seed: int = 2, max_batch: int = 16, slots: int = 3):
+    t, res = synth.poisson_arrivals(seed, rate, seconds)
+    shapes = [tuple(r) for r in res]
+    idx = collections.Counter()
+    frames = []
+    for s in shapes:
+        pool = pools_pinned[s]
+        frames.append(pool[idx[s] % len(pool)])
+        idx[s] += 1
+    server = HogServer(W, b, list(pools_pinned.keys()), max_batch=max_batch, slots=slots)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    done = run_stream(server, frames, shapes, t)
+    wall = time.perf_counter() - t_start
+    lat = np.array([r.done - r.arrival for r in done]) * 1e3
+    return {"rate": rate, "seconds": seconds, "frames": len(done),
+            "fps": len(done) / wall, "p50_ms": float(np.percentile(lat, 50)) if len(lat) else None,
+            "p99_ms": float(np.percentile(lat, 99)) if len(lat) else None,
+            "batches": server.batches, "mean_batch": len(done) / max(server.batches, 1)}, done, frames
+
+
+def pinned_pools(per_res: int = 64, seed: int = 2):
+    pools, W, b = synth.config2_pools(seed, per_res)
+    out = {s: [torch.from_numpy(f).pin_memory() for f in fr] for s, fr in pools.items()}
+    return out, torch.from_numpy(W).cuda(), torch.from_numpy(b).cuda()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--rates", default="500,2000,8000")
+    ap.add_argument("--seconds", type=float, default=60.0)
+    ap.add_argument("--pool", type=int, default=256)
+    args = ap.parse_args()
+    pools, W, b = pinned_pools(args.pool)
+    for rate in (float(r) for r in args.rates.split(",")):
+        stats, _, _ = served_stream(rate, args.seconds, W, b, pools)
+        print(json.dumps(stats), flush=True)
+
+
+if __name__ == "__main__":
+    main()
