@@ -47,6 +47,8 @@ extern "C" {
 #define HOG_E_CAP        -4   /* an output capacity argument is out of range */
 #define HOG_E_HIP        -5   /* a HIP launch or runtime call failed */
 #define HOG_E_NOTIMPL    -6
+#define HOG_E_DEVICE     -7   /* written to n_dets: a bounded device-side wait of the fused kernel
+                                 gave up; that frame's detections are not valid */
 
 #define HOG_MAX_SIDE     4096
 #define HOG_MAX_FILTERS  32
@@ -150,7 +152,11 @@ int hog_detect(const hog_params* prm, const uint8_t* frame, int h, int w, int pi
 /* hog_detect for n frames of one size in one set of launches covering
  * every frame and pyramid level (Sec. V-A, image combinations: an extra
  * grid dimension selects the image).  Frame i starts at
- * frames + i * frame_stride.  dets is [n][cap], n_dets is [n]. */
+ * frames + i * frame_stride.  dets is [n][cap], n_dets is [n].
+ * The schedule is the one hog_tuning_get reports for this shape: either
+ * one kernel per stage, or one persistent kernel that runs the histogram,
+ * feature and scoring work of all frames and levels from a work list.
+ * Both give bit-identical detections. */
 int hog_detect_batch(const hog_params* prm, const uint8_t* frames, int n,
                      int h, int w, int pitch, int64_t frame_stride,
                      const float* filters, const float* bias, int nf,
@@ -169,6 +175,44 @@ int hog_graph_create(hog_graph** out, const hog_params* prm, const uint8_t* fram
                      void* ws, size_t ws_bytes, void* stream);
 int hog_graph_launch(hog_graph* g, void* stream);
 int hog_graph_destroy(hog_graph* g);
+
+/* Schedule of hog_detect_batch for one shape (h, w, upsample, n, nf).
+ * fused = 0: one kernel per stage (histograms, features, scores).
+ * fused = 1: one persistent kernel.  Its work list splits the frames over
+ * `queues` (1..8) atomic ticket queues, each served by `wg_per_queue`
+ * workgroups; in a queue, the feature items of a frame come lag_f slots
+ * and its scoring items lag_s slots after its histogram items
+ * (1 <= lag_f < lag_s), so every item waits only on earlier tickets. */
+typedef struct hog_tuning {
+    int32_t fused;
+    int32_t queues;
+    int32_t wg_per_queue;
+    int32_t lag_f;
+    int32_t lag_s;
+} hog_tuning;
+
+/* The schedule in effect for a shape: the one set by hog_tuning_set or
+ * hog_autotune, else the default.  Returns 1 if set, 0 for the default,
+ * or an error code.  Host only; thread-safe. */
+int hog_tuning_get(int h, int w, int upsample, int n, int nf, hog_tuning* out);
+
+/* Sets (t non-NULL) or clears (t NULL) the schedule of a shape for this
+ * process.  HOG_E_INVAL if t is out of range.  Host only; thread-safe. */
+int hog_tuning_set(int h, int w, int upsample, int n, int nf, const hog_tuning* t);
+
+/* Autotuner: times hog_detect_batch on the given frames under each
+ * candidate schedule (one untimed run, then `reps` timed runs each, with
+ * HIP events on `stream`), keeps the fastest for this shape as with
+ * hog_tuning_set and returns it in `best` with its mean time per call in
+ * `best_ms`.  Arguments as hog_detect_batch; blocks the host until done.
+ * The candidates: the per-stage schedule, and the fused kernel with 8 or
+ * 1 queues, one workgroup per compute unit, and lags (1,2), (1,3), (2,3). */
+int hog_autotune(const hog_params* prm, const uint8_t* frames, int n,
+                 int h, int w, int pitch, int64_t frame_stride,
+                 const float* filters, const float* bias, int nf,
+                 hog_det* dets, int cap, int* n_dets,
+                 void* ws, size_t ws_bytes, int reps,
+                 hog_tuning* best, float* best_ms, void* stream);
 
 /* Inspection of one pyramid level of one frame (test entry point).
  * `level_px` (float32 [h_k][w_k]) receives the resampled level, `bins`

@@ -3,7 +3,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -19,7 +21,7 @@ struct Plan {
     int n = 0, nf = 0, groups = 0;
     // workspace offsets (bytes)
     size_t o_taps = 0, o_boxes = 0, o_bpack = 0, o_hist = 0, o_feat = 0, o_key = 0, o_state = 0, o_list = 0,
-           o_work = 0, o_state8 = 0, o_dense = 0, o_partial = 0, total = 0;
+           o_work = 0, o_state8 = 0, o_sync = 0, o_dense = 0, o_partial = 0, total = 0;
     long long packed_floats = 0, dense_floats = 0;
 };
 
@@ -90,7 +92,6 @@ int make_plan(int h, int w, int u, int n, int nf, Plan* P, int n_windows = 0) {
         L.cx = wk[k] / CELL;
         L.rows = L.cy - WIN + 1;
         L.cols = L.cx - WIN + 1;
-        L.apr = (L.cols + SHIFT - 1) / SHIFT;
         L.sig = sig[k];
         L.tap_y = taps;
         taps += L.h;
@@ -114,8 +115,8 @@ int make_plan(int h, int w, int u, int n, int nf, Plan* P, int n_windows = 0) {
         th += ((L.cy + TCY - 1) / TCY) * ((L.cx + TCX - 1) / TCX);
         L.tf_off = tf;
         tf += (L.cy * (L.cx + 2) + FEAT_THREADS - 1) / FEAT_THREADS;
-        L.ts_off = ts;
-        ts += (L.rows * L.apr + ANCHORS_PER_WG - 1) / ANCHORS_PER_WG;
+        L.row_off = ts;
+        ts += L.rows;
         box_bounds(L.sig, &L.wmin, &L.wmax);
         L.hmin = L.wmin;
         L.hmax = L.wmax;
@@ -140,7 +141,8 @@ int make_plan(int h, int w, int u, int n, int nf, Plan* P, int n_windows = 0) {
     }
     T.th_total = th;
     T.tf_total = tf;
-    T.ts_total = ts;
+    T.rows_total = ts;
+    T.ts_total = (ts + ROWS_PER_ITEM - 1) / ROWS_PER_ITEM;
     T.hist_frame = (int)hist;
     T.feat_frame = (int)feat;
     T.pos_frame = (int)pos;
@@ -172,6 +174,8 @@ int make_plan(int h, int w, int u, int n, int nf, Plan* P, int n_windows = 0) {
     o = align256(o + sizeof(int) * 2 * (size_t)n * std::max(pos, 1LL));
     P->o_state8 = o;
     o = align256(o + (size_t)n * std::max(pos, 1LL));
+    P->o_sync = o;
+    o = align256(o + sizeof(unsigned) * (size_t)fused_sync_words(n));
     T.dense_frame = (int)sc;
     P->o_dense = o;
     P->o_partial = o;
@@ -241,7 +245,7 @@ int run_pixels(const Plan& P, const uint8_t* frames, long long fstride, int pitc
     HOG_TRY(timed("geom", s, [&] {
         return launch_setup(T, at<int4>(ws, P.o_taps), at<int2>(ws, P.o_boxes), filters, P.nf,
                             at<float4>(ws, P.o_bpack), zero_keys ? at<unsigned long long>(ws, P.o_key) : nullptr,
-                            (long long)P.n * T.pos_frame, s);
+                            (long long)P.n * T.pos_frame, nullptr, 0, s);
     }));
     HOG_TRY(timed("hist", s, [&] {
         return launch_hist(T, frames, fstride, pitch, P.n, at<int4>(ws, P.o_taps), at<float>(ws, P.o_hist), s);
@@ -252,20 +256,74 @@ int run_pixels(const Plan& P, const uint8_t* frames, long long fstride, int pitc
     return HOG_OK;
 }
 
+// ------------------------------------------------------------- schedules
+using ShapeKey = std::array<int, 5>;
+std::mutex g_tune_mu;
+std::map<ShapeKey, hog_tuning> g_tune;
+
+int compute_units() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return cus;
+}
+
+bool tuning_valid(const hog_tuning& t) {
+    if (t.fused == 0) return true;
+    return t.fused == 1 && t.queues >= 1 && t.queues <= FUSED_MAX_QUEUES && t.wg_per_queue >= 1 &&
+           t.wg_per_queue <= 65536 && t.lag_f >= 1 && t.lag_s > t.lag_f && t.lag_s <= 64;
+}
+
+hog_tuning default_tuning(int, int, int, int, int) {
+    hog_tuning t{};
+    t.fused = 0;
+    t.queues = 8;
+    t.wg_per_queue = 32;
+    t.lag_f = 1;
+    t.lag_s = 2;
+    return t;
+}
+
+hog_tuning lookup_tuning(int h, int w, int u, int n, int nf, bool* found = nullptr) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find(ShapeKey{h, w, u, n, nf});
+    if (found) *found = it != g_tune.end();
+    return it != g_tune.end() ? it->second : default_tuning(h, w, u, n, nf);
+}
+
 int detect_sequence(const Plan& P, const hog_params* prm, const uint8_t* frames, long long fstride, int pitch,
                     const float* filters, const float* bias, hog_det* dets, int cap, int* n_dets, void* ws,
-                    hipStream_t s) {
+                    const hog_tuning& tune, hipStream_t s) {
     const LevelTable& T = P.T;
     if (T.n == 0) {
         // no pyramid level: zero detections for every frame
         return timed("fill", s, [&] { return launch_fill(n_dets, P.n, 0, s); });
     }
     const bool multi = P.groups > 1;
-    HOG_TRY(run_pixels(P, frames, fstride, pitch, ws, nullptr, filters, s, multi));
-    HOG_TRY(timed("score", s, [&] {
-        return launch_score(T, P.n, at<float>(ws, P.o_feat), at<float4>(ws, P.o_bpack), bias, P.nf, prm->thresh,
-                            nullptr, at<unsigned long long>(ws, P.o_key), multi, s);
-    }));
+    unsigned* sync = at<unsigned>(ws, P.o_sync);
+    if (tune.fused) {
+        FusedCfg cfg;
+        cfg.queues = tune.queues;
+        cfg.wg_per_queue = tune.wg_per_queue;
+        cfg.lag_f = tune.lag_f;
+        cfg.lag_s = tune.lag_s;
+        HOG_TRY(timed("geom", s, [&] {
+            return launch_setup(T, at<int4>(ws, P.o_taps), at<int2>(ws, P.o_boxes), filters, P.nf,
+                                at<float4>(ws, P.o_bpack), multi ? at<unsigned long long>(ws, P.o_key) : nullptr,
+                                (long long)P.n * T.pos_frame, sync, fused_sync_words(P.n), s);
+        }));
+        HOG_TRY(timed("fused", s, [&] {
+            return launch_fused(T, P.n, cfg, frames, fstride, pitch, at<int4>(ws, P.o_taps), at<float>(ws, P.o_hist),
+                                at<float>(ws, P.o_feat), at<float4>(ws, P.o_bpack), bias, P.nf, prm->thresh,
+                                at<unsigned long long>(ws, P.o_key), multi, sync, s);
+        }));
+    } else {
+        HOG_TRY(run_pixels(P, frames, fstride, pitch, ws, nullptr, filters, s, multi));
+        HOG_TRY(timed("score", s, [&] {
+            return launch_score(T, P.n, at<float>(ws, P.o_feat), at<float4>(ws, P.o_bpack), bias, P.nf,
+                                prm->thresh, nullptr, at<unsigned long long>(ws, P.o_key), multi, s);
+        }));
+    }
     // iou (a float32 in [1/2, 1)) as the exact binary fraction num / 2^e,
     // e <= 24, so that inter * 2^e stays below 2^63
     double v = prm->iou;
@@ -282,7 +340,8 @@ int detect_sequence(const Plan& P, const hog_params* prm, const uint8_t* frames,
     HOG_TRY(timed("nms", s, [&] {
         return launch_nms(T, P.n, at<unsigned long long>(ws, P.o_key), at<unsigned>(ws, P.o_list),
                           at<int2>(ws, P.o_boxes), num, den, dets, cap, n_dets, at<unsigned>(ws, P.o_state),
-                          at<int>(ws, P.o_work), at<unsigned char>(ws, P.o_state8), s);
+                          at<int>(ws, P.o_work), at<unsigned char>(ws, P.o_state8),
+                          tune.fused ? sync + FUSED_SYNC_ERR : nullptr, s);
     }));
     return HOG_OK;
 }
@@ -319,6 +378,7 @@ const char* hog_strerror(int st) {
         case HOG_E_CAP: return "output capacity out of range";
         case HOG_E_HIP: return "HIP launch or runtime failure";
         case HOG_E_NOTIMPL: return "not implemented";
+        case HOG_E_DEVICE: return "a bounded device-side wait gave up (detections not valid)";
         default: return "unknown status";
     }
 }
@@ -394,7 +454,8 @@ int hog_detect_batch(const hog_params* prm, const uint8_t* frames, int n, int h,
     Plan P;
     HOG_TRY(make_plan(h, w, prm->upsample, n, nf, &P));
     HOG_TRY(check_ws(P, ws, ws_bytes));
-    return detect_sequence(P, prm, frames, frame_stride, pitch, filters, bias, dets, cap, n_dets, ws,
+    const hog_tuning tune = lookup_tuning(h, w, prm->upsample, n, nf);
+    return detect_sequence(P, prm, frames, frame_stride, pitch, filters, bias, dets, cap, n_dets, ws, tune,
                            (hipStream_t)stream);
 }
 
@@ -426,7 +487,8 @@ int hog_graph_create(hog_graph** out, const hog_params* prm, const uint8_t* fram
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         st = HOG_E_HIP;
     } else {
-        st = detect_sequence(P, prm, frames, frame_stride, pitch, filters, bias, dets, cap, n_dets, ws, cs);
+        const hog_tuning tune = lookup_tuning(h, w, prm->upsample, n, nf);
+        st = detect_sequence(P, prm, frames, frame_stride, pitch, filters, bias, dets, cap, n_dets, ws, tune, cs);
         hipGraph_t graph = nullptr;
         const hipError_t e = hipStreamEndCapture(cs, &graph);
         if (st == HOG_OK && e != hipSuccess) st = HOG_E_HIP;
@@ -456,6 +518,88 @@ int hog_graph_destroy(hog_graph* g) {
     return HOG_OK;
 }
 
+int hog_tuning_get(int h, int w, int upsample, int n, int nf, hog_tuning* out) {
+    if (!out) return HOG_E_INVAL;
+    bool found = false;
+    *out = lookup_tuning(h, w, upsample, n, nf, &found);
+    return found ? 1 : 0;
+}
+
+int hog_tuning_set(int h, int w, int upsample, int n, int nf, const hog_tuning* t) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    if (!t) {
+        g_tune.erase(ShapeKey{h, w, upsample, n, nf});
+        return HOG_OK;
+    }
+    if (!tuning_valid(*t)) return HOG_E_INVAL;
+    g_tune[ShapeKey{h, w, upsample, n, nf}] = *t;
+    return HOG_OK;
+}
+
+int hog_autotune(const hog_params* prm, const uint8_t* frames, int n, int h, int w, int pitch, int64_t frame_stride,
+                 const float* filters, const float* bias, int nf, hog_det* dets, int cap, int* n_dets, void* ws,
+                 size_t ws_bytes, int reps, hog_tuning* best, float* best_ms, void* stream) {
+    HOG_TRY(check_detect_args(prm, frames, pitch, w, filters, bias, nf, dets, cap, n_dets));
+    if (!best || !best_ms || reps < 1 || reps > 1000) return HOG_E_INVAL;
+    if (n < 1 || (n > 1 && frame_stride < (int64_t)pitch * h)) return HOG_E_INVAL;
+    Plan P;
+    HOG_TRY(make_plan(h, w, prm->upsample, n, nf, &P));
+    HOG_TRY(check_ws(P, ws, ws_bytes));
+    const int cus = compute_units();
+    if (cus < 1) return HOG_E_HIP;
+    std::vector<hog_tuning> cand;
+    cand.push_back(default_tuning(h, w, prm->upsample, n, nf));
+    cand.back().fused = 0;
+    const int lags[3][2] = {{1, 2}, {1, 3}, {2, 3}};
+    for (int q : {8, 1}) {
+        for (const auto& lg : lags) {
+            hog_tuning t{};
+            t.fused = 1;
+            t.queues = q;
+            t.wg_per_queue = std::max(1, cus / q);
+            t.lag_f = lg[0];
+            t.lag_s = lg[1];
+            cand.push_back(t);
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return HOG_E_HIP;
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return HOG_E_HIP;
+    }
+    int st = HOG_OK;
+    float best_t = -1.f;
+    hog_tuning pick = cand[0];
+    for (const hog_tuning& t : cand) {
+        st = detect_sequence(P, prm, frames, frame_stride, pitch, filters, bias, dets, cap, n_dets, ws, t, s);
+        if (st != HOG_OK) break;
+        if (hipEventRecord(a, s) != hipSuccess) { st = HOG_E_HIP; break; }
+        for (int i = 0; i < reps && st == HOG_OK; ++i)
+            st = detect_sequence(P, prm, frames, frame_stride, pitch, filters, bias, dets, cap, n_dets, ws, t, s);
+        if (st != HOG_OK) break;
+        float ms = 0.f;
+        if (hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+            hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+            st = HOG_E_HIP;
+            break;
+        }
+        ms /= (float)reps;
+        if (best_t < 0.f || ms < best_t) {
+            best_t = ms;
+            pick = t;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (st != HOG_OK) return st;
+    HOG_TRY(hog_tuning_set(h, w, prm->upsample, n, nf, &pick));
+    *best = pick;
+    *best_ms = best_t;
+    return HOG_OK;
+}
+
 int hog_level_maps(const uint8_t* frame, int h, int w, int pitch, int upsample, int level, float* level_px,
                    uint8_t* bins, float* hist, void* ws, size_t ws_bytes, void* stream) {
     if (!frame || pitch < w || pitch > MAX_PITCH) return HOG_E_INVAL;
@@ -466,7 +610,7 @@ int hog_level_maps(const uint8_t* frame, int h, int w, int pitch, int upsample, 
     hipStream_t s = (hipStream_t)stream;
     const LevelTable& T = P.T;
     HOG_TRY(timed("geom", s, [&] {
-        return launch_setup(T, at<int4>(ws, P.o_taps), at<int2>(ws, P.o_boxes), nullptr, 0, nullptr, nullptr, 0, s);
+        return launch_setup(T, at<int4>(ws, P.o_taps), at<int2>(ws, P.o_boxes), nullptr, 0, nullptr, nullptr, 0, nullptr, 0, s);
     }));
     if (level_px || bins) {
         HOG_TRY(timed("maps", s, [&] {
@@ -546,7 +690,7 @@ int hog_filter_backward(const uint8_t* frames, int n, int h, int w, int pitch, i
     hipStream_t s = (hipStream_t)stream;
     const LevelTable& T = P.T;
     HOG_TRY(timed("geom", s, [&] {
-        return launch_setup(T, at<int4>(ws, P.o_taps), at<int2>(ws, P.o_boxes), nullptr, 0, nullptr, nullptr, 0, s);
+        return launch_setup(T, at<int4>(ws, P.o_taps), at<int2>(ws, P.o_boxes), nullptr, 0, nullptr, nullptr, 0, nullptr, 0, s);
     }));
     return timed("backward", s, [&] {
         return launch_backward(T, frames, frame_stride, pitch, at<int4>(ws, P.o_taps), filters, windows, dscore,

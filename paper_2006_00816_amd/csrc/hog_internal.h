@@ -35,17 +35,35 @@ constexpr int HIST_THREADS = 512;
 
 constexpr int FEAT_THREADS = 256;
 
-// Window scoring: each wave scores 4 MFMA M-tiles of 16 "anchors"; an
-// anchor is 3 horizontally adjacent windows; a filter group is 5 filters.
-// The 16 MFMA N columns are (filter, shift) = 5 x 3 (+1 unused).
-constexpr int SHIFT = 3;
+// Window scoring (see stage_score.h): one wave scores one window row as a
+// matrix product on v_mfma_f32_16x16x4_f32 with M = 16 cell positions,
+// N = (filter f of a group of 5, window column dc) = 50 columns, of which
+// 48 (three N tiles) go to the matrix cores and the last 2 (f = 4,
+// dc = 8, 9) to the vector ALUs, and K = (window row dr, channel) = 320.
 constexpr int FGROUP = 5;
-constexpr int KROW = (WIN + SHIFT - 1) * FPAD;   // 384 K values per window row
-constexpr int KK = KROW / 16;                    // 24 chunks of 16 K values
-constexpr int SCORE_THREADS = 256;
-constexpr int ANCHORS_PER_WAVE = 64;
-constexpr int ANCHORS_PER_WG = ANCHORS_PER_WAVE * SCORE_THREADS / 64;
-constexpr int BPACK_PER_GROUP = WIN * KK * 64;   // float4 entries per filter group
+constexpr int SC_K = WIN * FPAD;                 // 320
+constexpr int SC_KC = SC_K / 16;                 // 20 chunks of 16 K values
+constexpr int SC_NT = 3;                         // N tiles of 16 on the matrix cores
+constexpr int SC_PSTR = 52;                      // floats per row of a wave's partial-product tile
+constexpr int SCORE_THREADS = 1024;
+constexpr int ROWS_PER_ITEM = SCORE_THREADS / 64;   // window rows per scoring workgroup item
+constexpr int BPACK_MFMA = SC_KC * SC_NT * 64;      // float4 B operands of the matrix-core columns
+constexpr int BPACK_XTRA = SC_KC * 4 * 2;           // float4 weights of the two vector-ALU columns
+constexpr int BPACK_PER_GROUP = BPACK_MFMA + BPACK_XTRA;   // 64,000 bytes per filter group
+
+// Fused persistent kernel (k_fused.hip): counters in the workspace, as
+// u32 words: queue tickets [0, 8), error flag [8], then per frame the
+// finished-wave counts of its histogram and feature items.
+constexpr int FUSED_MAX_QUEUES = 8;
+constexpr int FUSED_SYNC_ERR = 8;
+constexpr int FUSED_SYNC_HEAD = 16;
+constexpr unsigned FUSED_SPIN_LIMIT = 1u << 20;   // polls (about a second) before a wait gives up
+
+struct FusedCfg {
+    int queues;          // 1..8; 8 keeps each queue on one XCD
+    int wg_per_queue;    // persistent workgroups per queue
+    int lag_f, lag_s;    // slot lags of the feature and scoring items, 1 <= lag_f < lag_s
+};
 
 constexpr int NMS_THREADS = 1024;
 constexpr int SORT_CAP = 4096;
@@ -54,7 +72,7 @@ constexpr int NMS_PAR_ROUNDS = 2;   // decision rounds run in parallel over all 
 
 struct DevLevel {
     int h, w, cy, cx;
-    int rows, cols, apr, k;       // apr: anchors per window row = ceil(cols / 3)
+    int rows, cols, k, pad0;
     long long sig;                // inverse scale, 40 fractional bits
     int tap_y, tap_x;             // offsets (int4 units) of the row / column taps
     int box_r, box_c;             // offsets (int2 units) of the row / column box edges
@@ -63,14 +81,17 @@ struct DevLevel {
     int pos_off;                  // window-position offset inside one frame
     int pk_off;                   // float offset of the packed [cy][cx][31] features (one frame)
     int sc_off;                   // float offset of the dense scores [nf][rows][cols] (one frame)
-    int th_off, tf_off, ts_off;   // first workgroup of this level in the hist / feat / score grids
+    int th_off, tf_off;           // first workgroup of this level in the hist / feat grids
+    int row_off;                  // first window row of this level in the frame's list of window rows
     int nms_klo, nms_khi;         // levels whose boxes can overlap this level's boxes with IoU > 1/2
     int wmin, wmax, hmin, hmax;   // bounds of this level's box widths / heights (frame px)
 };
 
 struct LevelTable {
     int n;                        // number of levels
-    int th_total, tf_total, ts_total;
+    int th_total, tf_total;       // histogram tiles / feature blocks per frame
+    int rows_total;               // window rows per frame, over all levels
+    int ts_total;                 // scoring items per frame and filter group: ceil(rows_total / ROWS_PER_ITEM)
     int hist_frame;               // cells per frame
     int feat_frame;               // floats per frame (padded layout)
     int pos_frame;                // window positions per frame
@@ -107,11 +128,17 @@ __host__ __device__ inline unsigned int pack_window(int f, int k, int r, int c) 
 // Launchers (host functions defined next to their kernels).
 hipError_t launch_setup(const LevelTable& T, int4* taps, int2* boxes,
                         const float* filters, int nf, float4* bpack,
-                        unsigned long long* poskey_zero, long long poskey_count, hipStream_t s);
+                        unsigned long long* poskey_zero, long long poskey_count, unsigned* sync_zero,
+                        int sync_count, hipStream_t s);
 hipError_t launch_hist(const LevelTable& T, const uint8_t* frames, long long fstride, int pitch,
                        int n, const int4* taps, float* hist, hipStream_t s);
 hipError_t launch_feat(const LevelTable& T, int n, const float* hist, float* feat,
                        float* packed, hipStream_t s);
+int fused_sync_words(int n);
+hipError_t launch_fused(const LevelTable& T, int n, const FusedCfg& cfg, const uint8_t* frames, long long fstride,
+                        int pitch, const int4* taps, float* hist, float* feat, const float4* bpack,
+                        const float* bias, int nf, float thresh, unsigned long long* poskey, bool atomic_key,
+                        unsigned* sync, hipStream_t s);
 hipError_t launch_score(const LevelTable& T, int n, const float* feat, const float4* bpack,
                         const float* bias, int nf, float thresh, float* dense,
                         unsigned long long* poskey, bool atomic_key, hipStream_t s);
@@ -120,7 +147,8 @@ hipError_t launch_nms_edges(const LevelTable& T, int n, const unsigned long long
                             int rounds, hipStream_t s);
 hipError_t launch_nms(const LevelTable& T, int n, const unsigned long long* poskey, const unsigned* lists,
                       const int2* boxes, long long iou_num, long long iou_den, void* dets, int cap, int* n_dets,
-                      unsigned* gstate, int* work, const unsigned char* state8, hipStream_t s);
+                      unsigned* gstate, int* work, const unsigned char* state8, const unsigned* upstream_err,
+                      hipStream_t s);
 hipError_t launch_level_maps(const LevelTable& T, int level, const uint8_t* frame, int pitch,
                              const int4* taps, float* level_px, uint8_t* bins, hipStream_t s);
 hipError_t launch_orient(const int32_t* gx, const int32_t* gy, long long n, uint8_t* bins,

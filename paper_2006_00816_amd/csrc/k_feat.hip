@@ -1,79 +1,12 @@
 // Block normalisation and the 31-d cell features (Sec. IV-A normalisation
 // and feature computation; Sec. V-A feature kernel).
-#include "hog_device.h"
+#include "stage_feat.h"
 
 namespace hog {
 
-// One thread per cell of the padded feature grid [cy][cx + 2] of a level.
-// Each cell is normalised by the four 2x2-cell blocks that contain it,
-// n_k = (B_k + 1e-4)^(-1/2) with B_k the summed energy of the block (zero
-// outside the grid).  With T(v) = min(v, 0.2):
-//   F[b]      = 1/2 sum_k T(h_b n_k)               (18 signed)
-//   F[18 + o] = 1/2 sum_k T((h_o + h_{o+9}) n_k)   (9 unsigned)
-//   F[27 + k] = 1/sqrt(18) sum_b T(h_b n_k)        (4 block energies)
-// The padded layout stores 32 floats per cell (channel 31 = 0) and two
-// zero cells after each row, which the scorer reads past the last column.
-// `packed`, when non-null, also receives [cy][cx][31] at the level's
-// packed offset (single frame).
 __global__ __launch_bounds__(FEAT_THREADS) void hog_feat_kernel(
     LevelTable T, const float* __restrict__ hist, float* __restrict__ feat, float* __restrict__ packed) {
-    const int frame = blockIdx.y;
-    const int k = HOG_FIND_LEVEL(T, (int)blockIdx.x, tf_off);
-    const DevLevel& L = T.L[k];
-    const int pw = L.cx + 2;
-    const int idx = (blockIdx.x - L.tf_off) * FEAT_THREADS + threadIdx.x;
-    if (idx >= L.cy * pw) return;
-    const int i = idx / pw, j = idx - i * pw;
-    float4* out = reinterpret_cast<float4*>(feat + (long long)frame * T.feat_frame + L.feat_off +
-                                            (long long)idx * FPAD);
-    if (j >= L.cx) {
-#pragma unroll
-        for (int q = 0; q < FPAD / 4; ++q) out[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-        return;
-    }
-    const float* H = hist + ((long long)frame * T.hist_frame + L.hist_off) * HSTRIDE;
-    const float4* hc = reinterpret_cast<const float4*>(H + ((long long)i * L.cx + j) * HSTRIDE);
-    float h[20];
-#pragma unroll
-    for (int q = 0; q < 5; ++q) {
-        const float4 v = hc[q];
-        h[4 * q] = v.x; h[4 * q + 1] = v.y; h[4 * q + 2] = v.z; h[4 * q + 3] = v.w;
-    }
-    auto E = [&](int y, int x) -> float {
-        return (y >= 0 && y < L.cy && x >= 0 && x < L.cx) ? H[((long long)y * L.cx + x) * HSTRIDE + NBINS]
-                                                          : 0.f;
-    };
-    const float e0 = h[NBINS];
-    const float eu = E(i - 1, j), ed = E(i + 1, j), el = E(i, j - 1), er = E(i, j + 1);
-    const float eul = E(i - 1, j - 1), eur = E(i - 1, j + 1), edl = E(i + 1, j - 1), edr = E(i + 1, j + 1);
-    float n[4];
-    n[0] = 1.0f / sqrtf(e0 + eu + el + eul + 1e-4f);   // block (-1, -1)
-    n[1] = 1.0f / sqrtf(e0 + eu + er + eur + 1e-4f);   // block (-1, +1)
-    n[2] = 1.0f / sqrtf(e0 + ed + el + edl + 1e-4f);   // block (+1, -1)
-    n[3] = 1.0f / sqrtf(e0 + ed + er + edr + 1e-4f);   // block (+1, +1)
-    float F[FPAD];
-#pragma unroll
-    for (int c = 0; c < FPAD; ++c) F[c] = 0.f;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        float tsum = 0.f;
-#pragma unroll
-        for (int b = 0; b < NBINS; ++b) {
-            const float tv = fminf(h[b] * n[q], 0.2f);
-            F[b] += 0.5f * tv;
-            tsum += tv;
-        }
-#pragma unroll
-        for (int o = 0; o < NORIENT; ++o) F[NBINS + o] += 0.5f * fminf((h[o] + h[o + NORIENT]) * n[q], 0.2f);
-        F[27 + q] = 0.23570226039551584f * tsum;   // 1/sqrt(18)
-    }
-#pragma unroll
-    for (int q = 0; q < FPAD / 4; ++q) out[q] = make_float4(F[4 * q], F[4 * q + 1], F[4 * q + 2], F[4 * q + 3]);
-    if (packed) {
-        float* p = packed + L.pk_off + ((long long)i * L.cx + j) * NFEAT;
-#pragma unroll
-        for (int c = 0; c < NFEAT; ++c) p[c] = F[c];
-    }
+    feat_cell(T, hist, feat, packed, (int)blockIdx.y, (int)blockIdx.x, (int)threadIdx.x);
 }
 
 hipError_t launch_feat(const LevelTable& T, int n, const float* hist, float* feat, float* packed,

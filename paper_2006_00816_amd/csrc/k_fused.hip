@@ -1,0 +1,132 @@
+// One persistent launch for resample -> gradients -> orientation -> cell
+// histograms -> normalisation/31-d features -> window scores of every frame
+// and every pyramid level of a batch (Sec. IV-A steps; Sec. V-A runs them
+// as separate kernels per scale).
+#include "stage_feat.h"
+#include "stage_hist.h"
+#include "stage_score.h"
+
+namespace hog {
+
+union FusedSmem {
+    HistSmem hist[2];        // two histogram tiles side by side (512 threads each)
+    ScoreSmem score;         // one scoring item (16 waves)
+};
+
+// Spin on a counter until it reaches `need` (thread 0), then make the
+// producers' writes visible to the whole workgroup.  The wait is bounded:
+// past `limit` polls the error word is set and the item proceeds, so the
+// kernel always drains.
+__device__ __forceinline__ void wait_count(const unsigned* c, unsigned need, unsigned* err, unsigned limit,
+                                           int tid) {
+    if (tid == 0) {
+        unsigned spins = 0;
+        while (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+            if (++spins > limit) {
+                atomicOr(err, 1u);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(8);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+}
+
+// Each wave publishes its own stores with a release increment.
+__device__ __forceinline__ void wave_done(unsigned* c, int tid) {
+    if ((tid & 63) == 0) __hip_atomic_fetch_add(c, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Work list.  Frames are split over Q queues (frame f in queue f mod Q);
+// workgroup b serves queue b mod Q, so with Q = 8 a queue stays on one XCD
+// (workgroups are dispatched to the 8 XCDs in turn) and a frame's
+// histograms, features and scores stay in one L2.  A queue is a sequence
+// of slots; slot s holds, in this order,
+//   the scoring items of the queue's frame s - lag_s   (ts_total x groups),
+//   the feature items of its frame s - lag_f           (4 blocks of 256 cells each),
+//   the histogram items of its frame s                 (2 tiles each),
+// and workgroups take items in ticket order from the queue's atomic
+// counter.  A feature item waits until its frame's histogram items are
+// done, a scoring item until its frame's feature items are done; with
+// 1 <= lag_f < lag_s those have smaller tickets, so they were taken by
+// running workgroups and every wait ends (no co-residency assumption).
+__global__ __launch_bounds__(SCORE_THREADS) void hog_fused_kernel(
+    LevelTable T, int n, int groups, int Q, int lag_f, int lag_s, const uint8_t* __restrict__ frames,
+    long long fstride, int pitch, const int4* __restrict__ taps, float* __restrict__ hist, float* __restrict__ feat,
+    const float4* __restrict__ bpack, const float* __restrict__ bias, int nf, float thresh,
+    unsigned long long* __restrict__ poskey, int atomic_key, unsigned* __restrict__ sync, unsigned spin_limit) {
+    __shared__ FusedSmem sm;
+    __shared__ int s_ticket;
+    const int tid = threadIdx.x;
+    const int q = (int)(blockIdx.x % (unsigned)Q);
+    const int nq = (n - q + Q - 1) / Q;
+    if (nq <= 0) return;
+    const int nH = (T.th_total + 1) / 2, nF = (T.tf_total + 3) / 4, nS = T.ts_total * groups;
+    const int Z = nS + nF + nH;
+    const long long total = (long long)(nq + lag_s) * Z;
+    unsigned* ticket = sync + q;
+    unsigned* err = sync + FUSED_SYNC_ERR;
+    unsigned* hdone = sync + FUSED_SYNC_HEAD;
+    unsigned* fdone = hdone + n;
+    const unsigned waves = SCORE_THREADS / 64;
+
+    // the two barriers around the ticket also separate one item's LDS use
+    // from the next one's
+    for (;;) {
+        if (tid == 0) s_ticket = (int)atomicAdd(ticket, 1u);
+        __syncthreads();
+        const long long tk = s_ticket;
+        __syncthreads();
+        if (tk >= total) break;
+        const int slot = (int)(tk / Z), o = (int)(tk % Z);
+        if (o < nS) {
+            const int jf = slot - lag_s;
+            if (jf < 0 || jf >= nq) continue;
+            const int frame = q + Q * jf;
+            wait_count(fdone + frame, waves * nF, err, spin_limit, tid);
+            const int grp = o / T.ts_total, it = o % T.ts_total;
+            load_bpack(sm.score, bpack, grp, tid);
+            __syncthreads();
+            score_item(T, frame, grp, it, sm.score, sm.score.P[tid >> 6], feat, nf, bias, thresh, nullptr, poskey,
+                       atomic_key, tid);
+        } else if (o < nS + nF) {
+            const int jf = slot - lag_f;
+            if (jf < 0 || jf >= nq) continue;
+            const int frame = q + Q * jf;
+            wait_count(hdone + frame, waves * nH, err, spin_limit, tid);
+            const int blk = 4 * (o - nS) + (tid >> 8);
+            if (blk < T.tf_total) feat_cell(T, hist, feat, nullptr, frame, blk, tid & 255);
+            wave_done(fdone + frame, tid);
+        } else {
+            const int jf = slot;
+            if (jf >= nq) continue;
+            const int frame = q + Q * jf;
+            int tile = 2 * (o - nS - nF) + (tid >> 9);
+            if (tile >= T.th_total) tile = -1;
+            hist_tile(T, frames, fstride, pitch, taps, hist, frame, tile, tid & 511, sm.hist[tid >> 9]);
+            wave_done(hdone + frame, tid);
+        }
+    }
+}
+
+int fused_sync_words(int n) { return FUSED_SYNC_HEAD + 2 * n; }
+
+hipError_t launch_fused(const LevelTable& T, int n, const FusedCfg& cfg, const uint8_t* frames, long long fstride,
+                        int pitch, const int4* taps, float* hist, float* feat, const float4* bpack,
+                        const float* bias, int nf, float thresh, unsigned long long* poskey, bool atomic_key,
+                        unsigned* sync, hipStream_t s) {
+    const int groups = (nf + FGROUP - 1) / FGROUP;
+    if (cfg.queues < 1 || cfg.queues > FUSED_MAX_QUEUES || cfg.lag_f < 1 || cfg.lag_s <= cfg.lag_f ||
+        cfg.wg_per_queue < 1)
+        return hipErrorInvalidValue;
+    const long long per_slot = (long long)T.ts_total * groups + (T.tf_total + 3) / 4 + (T.th_total + 1) / 2;
+    if (per_slot * ((long long)n + cfg.lag_s) > 0x7fffffffLL) return hipErrorInvalidValue;
+    const int blocks = cfg.queues * cfg.wg_per_queue;
+    hipLaunchKernelGGL(hog_fused_kernel, dim3(blocks), dim3(SCORE_THREADS), 0, s, T, n, groups, cfg.queues,
+                       cfg.lag_f, cfg.lag_s, frames, fstride, pitch, taps, hist, feat, bpack, bias, nf, thresh,
+                       poskey, atomic_key ? 1 : 0, sync, (unsigned)FUSED_SPIN_LIMIT);
+    return hipGetLastError();
+}
+
+}  // namespace hog

@@ -230,7 +230,7 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
     LevelTable T, const unsigned long long* __restrict__ poskey, const unsigned* __restrict__ lists,
     const int2* __restrict__ boxes, long long inum, long long iden, hog_det* __restrict__ dets, int cap,
     int* __restrict__ n_dets, unsigned* __restrict__ gstate, int* __restrict__ work,
-    const unsigned char* __restrict__ state8) {
+    const unsigned char* __restrict__ state8, const unsigned* __restrict__ upstream_err) {
     extern __shared__ unsigned lstate[];     // 2-bit states (LDS variant)
     __shared__ unsigned long long sk[SORT_CAP];
     __shared__ unsigned int hist[256];
@@ -240,6 +240,12 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
 
     const int tid = threadIdx.x;
     const int frame = blockIdx.x;
+    // a bounded wait of the fused kernel gave up: the candidates are not
+    // trustworthy, report the error in place of a count
+    if (upstream_err && *upstream_err) {
+        if (tid == 0) n_dets[frame] = HOG_E_DEVICE;
+        return;
+    }
     const int P = T.pos_frame;
     const int nw = (P + 15) >> 4;
     unsigned* S = G ? gstate + (long long)frame * nw : lstate;
@@ -400,14 +406,15 @@ hipError_t launch_nms_edges(const LevelTable& T, int n, const unsigned long long
 
 hipError_t launch_nms(const LevelTable& T, int n, const unsigned long long* poskey, const unsigned* lists,
                       const int2* boxes, long long iou_num, long long iou_den, void* dets, int cap, int* n_dets,
-                      unsigned* gstate, int* work, const unsigned char* state8, hipStream_t s) {
+                      unsigned* gstate, int* work, const unsigned char* state8, const unsigned* upstream_err,
+                      hipStream_t s) {
     const int nw = (T.pos_frame + 15) >> 4;
     if (nw <= NMS_LDS_STATE_WORDS) {
         hipLaunchKernelGGL(hog_nms_resolve_kernel<false>, dim3(n), dim3(NMS_THREADS), nw * sizeof(unsigned), s, T,
-                           poskey, lists, boxes, iou_num, iou_den, (hog_det*)dets, cap, n_dets, gstate, work, state8);
+                           poskey, lists, boxes, iou_num, iou_den, (hog_det*)dets, cap, n_dets, gstate, work, state8, upstream_err);
     } else {
         hipLaunchKernelGGL(hog_nms_resolve_kernel<true>, dim3(n), dim3(NMS_THREADS), 0, s, T, poskey, lists, boxes,
-                           iou_num, iou_den, (hog_det*)dets, cap, n_dets, gstate, work, state8);
+                           iou_num, iou_den, (hog_det*)dets, cap, n_dets, gstate, work, state8, upstream_err);
     }
     return hipGetLastError();
 }

@@ -7,18 +7,21 @@ namespace hog {
 // Segment 0 (blockIdx.y == 0): resampling taps of every level (rows, then
 // columns; Sec. IV-A pyramid) and the frame-pixel edges of every window row
 // and column (used for boxes and NMS).
-// Segment 1: filters [nf][10][10][31] -> MFMA B operands.  The B matrix of
-// filter group g has K = (window row dr, 384 values j of three adjacent
-// window columns' 12 cells x 32 channels) and N = (filter f in the group,
-// window shift d in 0..2); B[dr][j][f,d] = W_f[dr][j/32 - d][j%32] where
-// that cell exists and the channel is < 31, else 0.  Lane (g4, n) of the
-// 16x16x4 MFMA supplies 4 consecutive K values per 16-wide chunk.
+// Segment 1: filters [nf][10][10][31] -> scorer operands, per group of 5
+// filters.  Column n = 10 f + dc (filter f of the group, window column dc)
+// and K index k = 32 dr + ch (window row dr, channel ch; ch = 31 is zero):
+//  - matrix-core part, columns 0..47: entry [kc][nt][lane] holds the four
+//    K values 16 kc + 4 (lane / 16) + s, s = 0..3, of column
+//    16 nt + lane % 16, for four consecutive MFMAs;
+//  - vector-ALU part, columns 48 and 49 (f = 4, dc = 8, 9): entry
+//    [kc][g][col] holds the K values 16 kc + 4 g + s of that column.
 // Segment 2: zero the per-position candidate keys (when several filter
-// groups merge their keys with atomic max).
+// groups merge their keys with atomic max) and the counters of the fused
+// persistent kernel.
 __global__ __launch_bounds__(256) void hog_setup_kernel(
     LevelTable T, int4* __restrict__ taps, int2* __restrict__ boxes,
     const float* __restrict__ W, int nf, float4* __restrict__ bpack,
-    unsigned long long* __restrict__ keys, long long nkeys) {
+    unsigned long long* __restrict__ keys, long long nkeys, unsigned* __restrict__ sync, int nsync) {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (blockIdx.y == 0) {
         if (e < T.taps_total) {
@@ -51,37 +54,48 @@ __global__ __launch_bounds__(256) void hog_setup_kernel(
         if (e >= (long long)ngroups * BPACK_PER_GROUP) return;
         const int grp = (int)(e / BPACK_PER_GROUP);
         const int rem = (int)(e % BPACK_PER_GROUP);
-        const int dr = rem / (KK * 64);
-        const int kk = (rem / 64) % KK;
-        const int lane = rem % 64;
-        const int g4 = lane >> 4, n = lane & 15;
-        const int d = n % SHIFT, f = grp * FGROUP + n / SHIFT;
+        int n, k0;
+        if (rem < BPACK_MFMA) {
+            const int kc = rem / (SC_NT * 64);
+            const int nt = (rem / 64) % SC_NT;
+            const int lane = rem % 64;
+            n = 16 * nt + (lane & 15);
+            k0 = 16 * kc + 4 * (lane >> 4);
+        } else {
+            const int x = rem - BPACK_MFMA;
+            n = 48 + (x & 1);
+            k0 = 16 * (x >> 3) + 4 * ((x >> 1) & 3);
+        }
+        const int f = grp * FGROUP + n / WIN, dc = n % WIN;
         float v[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            const int j = 16 * kk + 4 * g4 + s - FPAD * d;
-            const int dc = j / FPAD, ch = j % FPAD;
-            const bool ok = n < FGROUP * SHIFT && f < nf && j >= 0 && dc < WIN && ch < NFEAT;
+            const int k = k0 + s;
+            const int dr = k / FPAD, ch = k % FPAD;
+            const bool ok = f < nf && ch < NFEAT;
             v[s] = ok ? W[((f * WIN + dr) * WIN + dc) * NFEAT + ch] : 0.f;
         }
         bpack[e] = make_float4(v[0], v[1], v[2], v[3]);
     } else {
         if (e < nkeys) keys[e] = 0ull;
+        if (e < nsync) sync[e] = 0u;
     }
 }
 
 hipError_t launch_setup(const LevelTable& T, int4* taps, int2* boxes, const float* filters, int nf,
-                        float4* bpack, unsigned long long* poskey_zero, long long poskey_count,
-                        hipStream_t s) {
+                        float4* bpack, unsigned long long* poskey_zero, long long poskey_count, unsigned* sync_zero,
+                        int sync_count, hipStream_t s) {
     const long long geo = (long long)T.taps_total + T.boxes_total;
     const long long pk = filters ? (long long)((nf + FGROUP - 1) / FGROUP) * BPACK_PER_GROUP : 0;
     const long long zk = poskey_zero ? poskey_count : 0;
+    const int zs = sync_zero ? sync_count : 0;
     long long m = geo > pk ? geo : pk;
     if (zk > m) m = zk;
-    const int segs = poskey_zero ? 3 : (filters ? 2 : 1);
+    if (zs > m) m = zs;
+    const int segs = (zk || zs) ? 3 : (filters ? 2 : 1);
     dim3 grid((unsigned)((m + 255) / 256), segs);
     hipLaunchKernelGGL(hog_setup_kernel, grid, dim3(256), 0, s, T, taps, boxes, filters, nf, bpack,
-                       poskey_zero, zk);
+                       poskey_zero, zk, sync_zero, zs);
     return hipGetLastError();
 }
 

@@ -1,0 +1,195 @@
+// Device stage: linear window scoring on the matrix cores (Sec. IV-A
+// linear classification; Sec. V-A classifier and detection kernels).  Used
+// by the per-stage scoring kernel and by the fused persistent kernel.
+#pragma once
+#include "hog_device.h"
+
+namespace hog {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// LDS of one scoring item: the filter group's packed B (62.5 KB) and, per
+// wave, the partial products of one M tile (3.25 KB).
+struct ScoreSmem {
+    float4 B[BPACK_PER_GROUP];
+    float P[ROWS_PER_ITEM][16 * SC_PSTR];
+};
+
+__device__ __forceinline__ void load_bpack(ScoreSmem& sm, const float4* __restrict__ bpack, int grp, int tid) {
+    const float4* __restrict__ g = bpack + (long long)grp * BPACK_PER_GROUP;
+    for (int e = tid; e < BPACK_PER_GROUP; e += SCORE_THREADS) sm.B[e] = g[e];
+}
+
+// Orders a wave's LDS accesses on either side (LDS operations of one wave
+// execute in program order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_lds_order() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// The score of filter f at window (r, c) is bias_f plus the 3100-term dot
+// product of the filter with the window's 10x10x31 features.  For one
+// window row r:
+//   P[x][(f, dc)] = sum over dr, ch of F[r + dr][x][ch] W_f[dr][dc][ch]
+//     (M = cell column x, N = (filter f of a group of 5, window column
+//      dc), K = (dr, ch) = 320 with channel 31 zero),
+//   S_f(r, c) = bias_f + sum over dc = 0..9 of P[c + dc][(f, dc)].
+// Columns 0..16 NT - 1 run on v_mfma_f32_16x16x4_f32: a lane reads 4
+// consecutive channels of one cell as a float4 and feeds them to 4
+// consecutive MFMAs against B packed to match.  With XTRA the columns
+// (f = 4, dc = 8, 9) run on the vector ALUs from the same float4: each lane
+// sums its 4 channels over all K chunks, then the 4 lanes of a cell are
+// added in a fixed tree.
+//
+// The row is walked in M tiles of 16 cells.  Window c = 16 t - 9 + j of
+// lane j takes the terms dc >= 9 - j from tile t and carries, in a
+// register, the terms dc < 9 - j from tile t - 1; the sum runs over dc in
+// increasing order either way.  Outputs: the dense score map (optional)
+// and, per window position, the best candidate key over the group's
+// filters (0 if no filter's score exceeds the threshold), stored or merged
+// with atomic max.
+template <int NT, bool XTRA>
+__device__ __forceinline__ void score_row(const DevLevel& L, int k, int r, const float* __restrict__ Ffr,
+                                          const ScoreSmem& sm, float* __restrict__ ring, int grp, int nf,
+                                          const float* __restrict__ bias, float thresh, float* __restrict__ Dfr,
+                                          unsigned long long* __restrict__ PKfr, int atomic_key, int lane) {
+    const int g4 = lane >> 4, j = lane & 15;
+    const int pitch = (L.cx + 2) * FPAD;
+    const float* __restrict__ Fr = Ffr + L.feat_off + (long long)r * pitch + 4 * g4;
+    const int f0 = grp * FGROUP + g4, f1 = f0 + 4;
+    const bool f0ok = f0 < nf, f1ok = XTRA && g4 == 0;
+    const float b0 = f0ok ? bias[f0] : 0.f, b1 = f1ok ? bias[f1] : 0.f;
+    float* __restrict__ D = Dfr ? Dfr + L.sc_off : nullptr;
+    unsigned long long* __restrict__ PK = PKfr ? PKfr + L.pos_off + (long long)r * L.cols : nullptr;
+    const float4* __restrict__ X = sm.B + BPACK_MFMA + 2 * g4;
+    const int ntiles = (L.cx + 15) >> 4;
+    float carry0 = 0.f, carry1 = 0.f;
+
+    for (int t = 0; t < ntiles; ++t) {
+        floatx4 acc[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+        float x8 = 0.f, x9 = 0.f;
+        // cells past the last window's reach (x >= cx) are never summed
+        const float* __restrict__ a = Fr + min(16 * t + j, L.cx + 1) * FPAD;
+#pragma unroll
+        for (int kc = 0; kc < SC_KC; ++kc) {
+            const float4 av = *reinterpret_cast<const float4*>(a + (kc >> 1) * pitch + 16 * (kc & 1));
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const float4 b = sm.B[(kc * SC_NT + nt) * 64 + lane];
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, b.x, acc[nt], 0, 0, 0);
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, b.y, acc[nt], 0, 0, 0);
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, b.z, acc[nt], 0, 0, 0);
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, b.w, acc[nt], 0, 0, 0);
+            }
+            if (XTRA) {
+                const float4 w8 = X[kc * 8], w9 = X[kc * 8 + 1];
+                x8 = fmaf(av.x, w8.x, x8);
+                x8 = fmaf(av.y, w8.y, x8);
+                x8 = fmaf(av.z, w8.z, x8);
+                x8 = fmaf(av.w, w8.w, x8);
+                x9 = fmaf(av.x, w9.x, x9);
+                x9 = fmaf(av.y, w9.y, x9);
+                x9 = fmaf(av.z, w9.z, x9);
+                x9 = fmaf(av.w, w9.w, x9);
+            }
+        }
+        if (XTRA) {
+            x8 += __shfl_xor(x8, 16, 64);
+            x9 += __shfl_xor(x9, 16, 64);
+            x8 += __shfl_xor(x8, 32, 64);
+            x9 += __shfl_xor(x9, 32, 64);
+        }
+        // lane (g4, j) holds P[16 t + 4 g4 + i][16 nt + j]
+        wave_lds_order();
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ring[(4 * g4 + i) * SC_PSTR + 16 * nt + j] = acc[nt][i];
+        if (XTRA && g4 == 0) {
+            ring[j * SC_PSTR + 48] = x8;
+            ring[j * SC_PSTR + 49] = x9;
+        }
+        wave_lds_order();
+
+        float s0 = carry0, s1 = carry1, n0 = 0.f, n1 = 0.f;
+#pragma unroll
+        for (int dc = 0; dc < WIN; ++dc) {
+            if (dc >= WIN - 1 - j) {
+                const float* p = ring + (j - (WIN - 1) + dc) * SC_PSTR + dc;
+                s0 += p[WIN * g4];
+                if (f1ok) s1 += p[WIN * 4];
+            }
+            if (dc <= WIN - 2 - j) {
+                const float* p = ring + (j + 16 - (WIN - 1) + dc) * SC_PSTR + dc;
+                n0 += p[WIN * g4];
+                if (f1ok) n1 += p[WIN * 4];
+            }
+        }
+        carry0 = n0;
+        carry1 = n1;
+        wave_lds_order();
+
+        const int c = 16 * t - (WIN - 1) + j;
+        const bool cok = c >= 0 && c < L.cols;
+        unsigned long long key = 0ull;
+        if (cok) {
+            s0 += b0;
+            s1 += b1;
+            if (D) {
+                if (f0ok) D[((long long)f0 * L.rows + r) * L.cols + c] = s0;
+                if (f1ok) D[((long long)f1 * L.rows + r) * L.cols + c] = s1;
+            }
+            if (f0ok && s0 > thresh)
+                key = ((unsigned long long)score_order(s0) << 32) | (unsigned long long)(~pack_window(f0, k, r, c));
+            if (f1ok && s1 > thresh) {
+                const unsigned long long k1 =
+                    ((unsigned long long)score_order(s1) << 32) | (unsigned long long)(~pack_window(f1, k, r, c));
+                key = k1 > key ? k1 : key;
+            }
+        }
+        // best over the group's filters of the same window: lanes j, j + 16, j + 32, j + 48
+#pragma unroll
+        for (int sft = 16; sft < 64; sft <<= 1) {
+            const unsigned long long o = __shfl_xor(key, sft, 64);
+            key = o > key ? o : key;
+        }
+        if (PK && cok && g4 == 0) {
+            if (atomic_key) {
+                if (key) atomicMax(PK + c, key);
+            } else {
+                PK[c] = key;
+            }
+        }
+    }
+}
+
+// One scoring item: window rows q = ROWS_PER_ITEM * item + wave of the
+// frame's list of rows (levels in order), filter group grp; sm.B holds the
+// group's B.  Waves past the last row do nothing.
+__device__ __forceinline__ void score_item(const LevelTable& T, int frame, int grp, int item, const ScoreSmem& sm,
+                                           float* __restrict__ ring, const float* __restrict__ feat, int nf,
+                                           const float* __restrict__ bias, float thresh, float* __restrict__ dense,
+                                           unsigned long long* __restrict__ poskey, int atomic_key, int tid) {
+    const int q = item * ROWS_PER_ITEM + (tid >> 6);
+    if (q >= T.rows_total) return;
+    const int k = HOG_FIND_LEVEL(T, q, row_off);
+    const DevLevel& L = T.L[k];
+    const int r = q - L.row_off;
+    const float* Ffr = feat + (long long)frame * T.feat_frame;
+    float* Dfr = dense ? dense + (long long)frame * T.dense_frame : nullptr;
+    unsigned long long* PKfr = poskey ? poskey + (long long)frame * T.pos_frame : nullptr;
+    const int fg = min(FGROUP, nf - grp * FGROUP);
+    const int lane = tid & 63;
+    if (fg == 5)
+        score_row<3, true>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane);
+    else if (fg == 4)
+        score_row<3, false>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane);
+    else if (fg >= 2)
+        score_row<2, false>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane);
+    else
+        score_row<1, false>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane);
+}
+
+}  // namespace hog

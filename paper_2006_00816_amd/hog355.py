@@ -28,6 +28,14 @@ class hog_params(ctypes.Structure):
     _fields_ = [("upsample", ctypes.c_int32), ("thresh", ctypes.c_float), ("iou", ctypes.c_float)]
 
 
+class hog_tuning(ctypes.Structure):
+    _fields_ = [("fused", ctypes.c_int32), ("queues", ctypes.c_int32), ("wg_per_queue", ctypes.c_int32),
+                ("lag_f", ctypes.c_int32), ("lag_s", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 class hog_level(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("h", ctypes.c_int32), ("w", ctypes.c_int32),
                 ("cy", ctypes.c_int32), ("cx", ctypes.c_int32), ("rows", ctypes.c_int32),
@@ -72,6 +80,9 @@ def lib():
         "hog_filter_backward": ([vp, i32, i32, i32, i32, i64, i32, vp, i32, vp, vp, i32, vp, vp, vp, vp, sz, vp],
                                 i32),
         "hog_hinge_loss": ([vp, vp, i32, vp, i32, ctypes.c_float, vp, vp, vp, vp], i32),
+        "hog_tuning_get": ([i32, i32, i32, i32, i32, vp], i32),
+        "hog_tuning_set": ([i32, i32, i32, i32, i32, vp], i32),
+        "hog_autotune": ([vp, vp, i32, i32, i32, i32, i64, vp, vp, i32, vp, i32, vp, vp, sz, i32, vp, vp, vp], i32),
         "hog_profile_enable": ([i32], i32),
         "hog_profile_reset": ([], i32),
         "hog_profile_read": ([ctypes.c_char_p, vp, vp], i32),
@@ -236,6 +247,40 @@ def detect_batch(frames: torch.Tensor, W, b, thresh=0.0, iou=0.5, upsample=1, ca
     dets, nd = alloc_dets(int(frames.shape[0]), cap, frames.device)
     detect_batch_into(frames, W, b, dets, nd, thresh, iou, upsample, ws)
     return dets_to_numpy(dets, nd)
+
+
+def tuning_get(h: int, w: int, upsample: int, n: int, nf: int):
+    """(schedule dict, True if set for this shape / False for the default)."""
+    t = hog_tuning()
+    st = lib().hog_tuning_get(h, w, upsample, n, nf, ctypes.byref(t))
+    if st < 0:
+        _check(st, "hog_tuning_get")
+    return t.as_dict(), st == 1
+
+
+def tuning_set(h: int, w: int, upsample: int, n: int, nf: int, t: dict | None):
+    """Set (dict) or clear (None) the schedule of a shape."""
+    if t is None:
+        _check(lib().hog_tuning_set(h, w, upsample, n, nf, None), "hog_tuning_set")
+        return
+    tt = hog_tuning(**{k: int(v) for k, v in t.items()})
+    _check(lib().hog_tuning_set(h, w, upsample, n, nf, ctypes.byref(tt)), "hog_tuning_set")
+
+
+def autotune(frames: torch.Tensor, W, b, cap=MAX_DETS, thresh=0.0, iou=0.5, upsample=1, reps: int = 5, ws=None):
+    """Time hog_detect_batch under each candidate schedule on these frames;
+    the fastest is kept for the shape.  Returns (schedule dict, ms per call)."""
+    n, h, w = (int(v) for v in frames.shape)
+    nf = int(W.shape[0])
+    dets, nd = alloc_dets(n, cap, frames.device)
+    prm = _params(thresh, iou, upsample)
+    wp, wn = _ws(ws, workspace_bytes(h, w, upsample, n, nf))
+    best = hog_tuning()
+    ms = ctypes.c_float()
+    _check(lib().hog_autotune(ctypes.byref(prm), _ptr(frames), n, h, w, int(frames.stride(1)), int(frames.stride(0)),
+                              _ptr(W), _ptr(b), nf, _ptr(dets), cap, _ptr(nd), wp, wn, reps, ctypes.byref(best),
+                              ctypes.byref(ms), _stream()), "hog_autotune")
+    return best.as_dict(), float(ms.value)
 
 
 class DetectGraph:

@@ -37,7 +37,7 @@ def test_exports_every_declared_function(L):
 
 def test_version_and_strerror(L):
     assert L.hog_version() >= 100
-    for code in (0, -1, -2, -3, -4, -5, -6):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert L.hog_strerror(code)
     assert L.hog_strerror(-99) == b"unknown status"
 
@@ -107,3 +107,23 @@ def test_level_table_limits(L):
     lv = hog355.pyramid(4096, 4096, 2, 32)
     assert len(lv) <= 28
     assert lv[0]["cx"] <= 1024
+
+
+def test_tuning_table_roundtrip_and_validation(L):
+    from paper_2006_00816_amd import hog355
+    shape = (123, 321, 1, 5, 3)
+    t, found = hog355.tuning_get(*shape)
+    assert not found and t["fused"] == 0
+    want = {"fused": 1, "queues": 8, "wg_per_queue": 32, "lag_f": 1, "lag_s": 3}
+    hog355.tuning_set(*shape, want)
+    got, found = hog355.tuning_get(*shape)
+    assert found and got == want
+    # a scoring lag that does not follow the feature lag could wait on a
+    # later ticket: rejected, as are queue counts outside 1..8
+    for bad in ({**want, "lag_s": 1}, {**want, "lag_f": 0}, {**want, "queues": 9}, {**want, "queues": 0},
+                {**want, "wg_per_queue": 0}, {**want, "fused": 2}):
+        with pytest.raises(hog355.HogError):
+            hog355.tuning_set(*shape, bad)
+    assert hog355.tuning_get(*shape)[0] == want
+    hog355.tuning_set(*shape, None)
+    assert not hog355.tuning_get(*shape)[1]
