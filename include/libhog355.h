@@ -177,18 +177,23 @@ int hog_graph_launch(hog_graph* g, void* stream);
 int hog_graph_destroy(hog_graph* g);
 
 /* Schedule of hog_detect_batch for one shape (h, w, upsample, n, nf).
- * fused = 0: one kernel per stage (histograms, features, scores).
- * fused = 1: one persistent kernel.  Its work list splits the frames over
- * `queues` (1..8) atomic ticket queues, each served by `wg_per_queue`
- * workgroups; in a queue, the feature items of a frame come lag_f slots
- * and its scoring items lag_s slots after its histogram items
- * (1 <= lag_f < lag_s), so every item waits only on earlier tickets. */
+ * fused = 0: one kernel per stage (histograms, features, scores, NMS);
+ *   with split = 2..4 the frames run as that many groups on forked
+ *   streams (joined before the call's work ends), so that one group's NMS
+ *   overlaps another group's histograms and scores.
+ * fused = 1: one persistent kernel for histograms, features and scores.
+ *   Its work list splits the frames over `queues` (1..8) atomic ticket
+ *   queues, each served by `wg_per_queue` workgroups; in a queue, the
+ *   feature items of a frame come lag_f slots and its scoring items lag_s
+ *   slots after its histogram items (1 <= lag_f < lag_s), so every item
+ *   waits only on earlier tickets.  split must be 1. */
 typedef struct hog_tuning {
     int32_t fused;
     int32_t queues;
     int32_t wg_per_queue;
     int32_t lag_f;
     int32_t lag_s;
+    int32_t split;
 } hog_tuning;
 
 /* The schedule in effect for a shape: the one set by hog_tuning_set or
@@ -205,8 +210,10 @@ int hog_tuning_set(int h, int w, int upsample, int n, int nf, const hog_tuning* 
  * HIP events on `stream`), keeps the fastest for this shape as with
  * hog_tuning_set and returns it in `best` with its mean time per call in
  * `best_ms`.  Arguments as hog_detect_batch; blocks the host until done.
- * The candidates: the per-stage schedule, and the fused kernel with 8 or
- * 1 queues, one workgroup per compute unit, and lags (1,2), (1,3), (2,3). */
+ * The candidates: the per-stage schedule with split 1, 2 and 4, and the
+ * fused kernel with 8 or 1 queues, one workgroup per compute unit, and
+ * lags (1,2), (1,3), (2,3), (2,4); a candidate that reports an error in
+ * any n_dets entry is skipped. */
 int hog_autotune(const hog_params* prm, const uint8_t* frames, int n,
                  int h, int w, int pitch, int64_t frame_stride,
                  const float* filters, const float* bias, int nf,

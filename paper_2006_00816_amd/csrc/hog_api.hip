@@ -169,7 +169,7 @@ int make_plan(int h, int w, int u, int n, int nf, Plan* P, int n_windows = 0) {
     P->o_state = o;
     o = align256(o + sizeof(unsigned) * (size_t)n * ((std::max(pos, 1LL) + 15) / 16));
     P->o_list = o;
-    o = align256(o + sizeof(unsigned) * NMS_LIST * (size_t)n * std::max(pos, 1LL));
+    o = align256(o + (nms_wide_lists(pos) ? 4 : 2) * (size_t)NMS_LIST * (size_t)n * std::max(pos, 1LL));
     P->o_work = o;
     o = align256(o + sizeof(int) * 2 * (size_t)n * std::max(pos, 1LL));
     P->o_state8 = o;
@@ -268,9 +268,12 @@ int compute_units() {
     return cus;
 }
 
+constexpr int MAX_SPLIT = 4;
+
 bool tuning_valid(const hog_tuning& t) {
+    if (t.split < 1 || t.split > MAX_SPLIT) return false;
     if (t.fused == 0) return true;
-    return t.fused == 1 && t.queues >= 1 && t.queues <= FUSED_MAX_QUEUES && t.wg_per_queue >= 1 &&
+    return t.fused == 1 && t.split == 1 && t.queues >= 1 && t.queues <= FUSED_MAX_QUEUES && t.wg_per_queue >= 1 &&
            t.wg_per_queue <= 65536 && t.lag_f >= 1 && t.lag_s > t.lag_f && t.lag_s <= 64;
 }
 
@@ -281,6 +284,7 @@ hog_tuning default_tuning(int, int, int, int, int) {
     t.wg_per_queue = 32;
     t.lag_f = 1;
     t.lag_s = 2;
+    t.split = 1;
     return t;
 }
 
@@ -289,6 +293,101 @@ hog_tuning lookup_tuning(int h, int w, int u, int n, int nf, bool* found = nullp
     auto it = g_tune.find(ShapeKey{h, w, u, n, nf});
     if (found) *found = it != g_tune.end();
     return it != g_tune.end() ? it->second : default_tuning(h, w, u, n, nf);
+}
+
+// Pointers of the per-frame workspace regions, starting at frame `lo` of
+// the batch.
+struct FrameBufs {
+    const uint8_t* frames;
+    float* hist;
+    float* feat;
+    unsigned long long* keys;
+    unsigned* gstate;
+    void* lists;
+    int* work;
+    unsigned char* state8;
+    hog_det* dets;
+    int* n_dets;
+};
+
+FrameBufs frame_bufs(const Plan& P, void* ws, const uint8_t* frames, long long fstride, hog_det* dets, int cap,
+                     int* n_dets, int lo) {
+    const LevelTable& T = P.T;
+    const long long pos = T.pos_frame;
+    FrameBufs b;
+    b.frames = frames + (long long)lo * fstride;
+    b.hist = at<float>(ws, P.o_hist) + (long long)lo * T.hist_frame * HSTRIDE;
+    b.feat = at<float>(ws, P.o_feat) + (long long)lo * T.feat_frame;
+    b.keys = at<unsigned long long>(ws, P.o_key) + lo * pos;
+    b.gstate = at<unsigned>(ws, P.o_state) + lo * ((pos + 15) / 16);
+    b.lists = at<char>(ws, P.o_list) + lo * pos * NMS_LIST * (nms_wide_lists(pos) ? 4 : 2);
+    b.work = at<int>(ws, P.o_work) + lo * 2 * pos;
+    b.state8 = at<unsigned char>(ws, P.o_state8) + lo * pos;
+    b.dets = dets + (long long)lo * cap;
+    b.n_dets = n_dets + lo;
+    return b;
+}
+
+// Helper streams and events of a host thread for split schedules (default
+// priority), created on first use per device.
+struct SplitRes {
+    int device = -1;
+    hipStream_t st[MAX_SPLIT - 1] = {};
+    hipEvent_t ev[MAX_SPLIT] = {};
+};
+thread_local SplitRes g_split;
+
+int split_resources(SplitRes** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return HOG_E_HIP;
+    SplitRes& r = g_split;
+    if (r.device != dev) {
+        for (int j = 0; j < MAX_SPLIT - 1; ++j)
+            if (hipStreamCreateWithFlags(&r.st[j], hipStreamNonBlocking) != hipSuccess) return HOG_E_HIP;
+        for (int j = 0; j < MAX_SPLIT; ++j)
+            if (hipEventCreateWithFlags(&r.ev[j], hipEventDisableTiming) != hipSuccess) return HOG_E_HIP;
+        r.device = dev;
+    }
+    *out = &r;
+    return HOG_OK;
+}
+
+int nms_chain(const Plan& P, int m, const FrameBufs& b, const hog_params* prm, int cap, const unsigned* upstream,
+              void* ws, hipStream_t s) {
+    const LevelTable& T = P.T;
+    // iou (a float32 in [1/2, 1)) as the exact binary fraction num / 2^e,
+    // e <= 24, so that inter * 2^e stays below 2^63
+    double v = prm->iou;
+    int e = 0;
+    while (v != (double)(long long)v) {
+        v *= 2.0;
+        ++e;
+    }
+    const long long num = (long long)v, den = 1LL << e;
+    HOG_TRY(timed("nms_edges", s, [&] {
+        return launch_nms_edges(T, m, b.keys, at<int2>(ws, P.o_boxes), num, den, b.lists, b.state8, NMS_PAR_ROUNDS,
+                                s);
+    }));
+    return timed("nms", s, [&] {
+        return launch_nms(T, m, b.keys, b.lists, at<int2>(ws, P.o_boxes), num, den, b.dets, cap, b.n_dets, b.gstate,
+                          b.work, b.state8, upstream, fused_need(T, P.nf), s);
+    });
+}
+
+// histograms -> features -> scores -> NMS for frames lo .. lo + m - 1
+int staged_chain(const Plan& P, int m, const FrameBufs& b, long long fstride, int pitch, const hog_params* prm,
+                 const float* bias, int cap, void* ws, hipStream_t s) {
+    const LevelTable& T = P.T;
+    const bool multi = P.groups > 1;
+    HOG_TRY(timed("hist", s, [&] {
+        return launch_hist(T, b.frames, fstride, pitch, m, at<int4>(ws, P.o_taps), b.hist, s);
+    }));
+    HOG_TRY(timed("feat", s, [&] { return launch_feat(T, m, b.hist, b.feat, nullptr, s); }));
+    HOG_TRY(timed("score", s, [&] {
+        return launch_score(T, m, b.feat, at<float4>(ws, P.o_bpack), bias, P.nf, prm->thresh, nullptr, b.keys, multi,
+                            s);
+    }));
+    return nms_chain(P, m, b, prm, cap, nullptr, ws, s);
 }
 
 int detect_sequence(const Plan& P, const hog_params* prm, const uint8_t* frames, long long fstride, int pitch,
@@ -301,49 +400,48 @@ int detect_sequence(const Plan& P, const hog_params* prm, const uint8_t* frames,
     }
     const bool multi = P.groups > 1;
     unsigned* sync = at<unsigned>(ws, P.o_sync);
+    HOG_TRY(timed("geom", s, [&] {
+        return launch_setup(T, at<int4>(ws, P.o_taps), at<int2>(ws, P.o_boxes), filters, P.nf,
+                            at<float4>(ws, P.o_bpack), multi ? at<unsigned long long>(ws, P.o_key) : nullptr,
+                            (long long)P.n * T.pos_frame, tune.fused ? sync : nullptr,
+                            tune.fused ? fused_sync_words(P.n) : 0, s);
+    }));
     if (tune.fused) {
         FusedCfg cfg;
         cfg.queues = tune.queues;
         cfg.wg_per_queue = tune.wg_per_queue;
         cfg.lag_f = tune.lag_f;
         cfg.lag_s = tune.lag_s;
-        HOG_TRY(timed("geom", s, [&] {
-            return launch_setup(T, at<int4>(ws, P.o_taps), at<int2>(ws, P.o_boxes), filters, P.nf,
-                                at<float4>(ws, P.o_bpack), multi ? at<unsigned long long>(ws, P.o_key) : nullptr,
-                                (long long)P.n * T.pos_frame, sync, fused_sync_words(P.n), s);
-        }));
         HOG_TRY(timed("fused", s, [&] {
             return launch_fused(T, P.n, cfg, frames, fstride, pitch, at<int4>(ws, P.o_taps), at<float>(ws, P.o_hist),
                                 at<float>(ws, P.o_feat), at<float4>(ws, P.o_bpack), bias, P.nf, prm->thresh,
                                 at<unsigned long long>(ws, P.o_key), multi, sync, s);
         }));
-    } else {
-        HOG_TRY(run_pixels(P, frames, fstride, pitch, ws, nullptr, filters, s, multi));
-        HOG_TRY(timed("score", s, [&] {
-            return launch_score(T, P.n, at<float>(ws, P.o_feat), at<float4>(ws, P.o_bpack), bias, P.nf,
-                                prm->thresh, nullptr, at<unsigned long long>(ws, P.o_key), multi, s);
-        }));
+        return nms_chain(P, P.n, frame_bufs(P, ws, frames, fstride, dets, cap, n_dets, 0), prm, cap, sync, ws, s);
     }
-    // iou (a float32 in [1/2, 1)) as the exact binary fraction num / 2^e,
-    // e <= 24, so that inter * 2^e stays below 2^63
-    double v = prm->iou;
-    int e = 0;
-    while (v != (double)(long long)v) {
-        v *= 2.0;
-        ++e;
+    const int parts = std::min(std::max(tune.split, 1), P.n);
+    if (parts == 1)
+        return staged_chain(P, P.n, frame_bufs(P, ws, frames, fstride, dets, cap, n_dets, 0), fstride, pitch, prm,
+                            bias, cap, ws, s);
+    // the frames in `parts` groups on forked streams: one group's NMS
+    // overlaps another's histograms and scores
+    SplitRes* r = nullptr;
+    HOG_TRY(split_resources(&r));
+    if (hipEventRecord(r->ev[0], s) != hipSuccess) return HOG_E_HIP;
+    for (int j = 1; j < parts; ++j)
+        if (hipStreamWaitEvent(r->st[j - 1], r->ev[0], 0) != hipSuccess) return HOG_E_HIP;
+    int st = HOG_OK;
+    for (int j = 0; j < parts && st == HOG_OK; ++j) {
+        const int lo = (int)((long long)j * P.n / parts), hi = (int)((long long)(j + 1) * P.n / parts);
+        st = staged_chain(P, hi - lo, frame_bufs(P, ws, frames, fstride, dets, cap, n_dets, lo), fstride, pitch,
+                          prm, bias, cap, ws, j == 0 ? s : r->st[j - 1]);
     }
-    const long long num = (long long)v, den = 1LL << e;
-    HOG_TRY(timed("nms_edges", s, [&] {
-        return launch_nms_edges(T, P.n, at<unsigned long long>(ws, P.o_key), at<int2>(ws, P.o_boxes), num, den,
-                                at<unsigned>(ws, P.o_list), at<unsigned char>(ws, P.o_state8), NMS_PAR_ROUNDS, s);
-    }));
-    HOG_TRY(timed("nms", s, [&] {
-        return launch_nms(T, P.n, at<unsigned long long>(ws, P.o_key), at<unsigned>(ws, P.o_list),
-                          at<int2>(ws, P.o_boxes), num, den, dets, cap, n_dets, at<unsigned>(ws, P.o_state),
-                          at<int>(ws, P.o_work), at<unsigned char>(ws, P.o_state8),
-                          tune.fused ? sync + FUSED_SYNC_ERR : nullptr, s);
-    }));
-    return HOG_OK;
+    // join (also after an error, so that no forked stream is left behind a capture)
+    for (int j = 1; j < parts; ++j) {
+        if (hipEventRecord(r->ev[j], r->st[j - 1]) != hipSuccess) return HOG_E_HIP;
+        if (hipStreamWaitEvent(s, r->ev[j], 0) != hipSuccess) return HOG_E_HIP;
+    }
+    return st;
 }
 
 int check_detect_args(const hog_params* prm, const void* frames, int pitch, int w, const float* filters,
@@ -548,9 +646,12 @@ int hog_autotune(const hog_params* prm, const uint8_t* frames, int n, int h, int
     const int cus = compute_units();
     if (cus < 1) return HOG_E_HIP;
     std::vector<hog_tuning> cand;
-    cand.push_back(default_tuning(h, w, prm->upsample, n, nf));
-    cand.back().fused = 0;
-    const int lags[3][2] = {{1, 2}, {1, 3}, {2, 3}};
+    for (int sp : {1, 2, 4}) {
+        if (sp > n) break;
+        cand.push_back(default_tuning(h, w, prm->upsample, n, nf));
+        cand.back().split = sp;
+    }
+    const int lags[4][2] = {{1, 2}, {1, 3}, {2, 3}, {2, 4}};
     for (int q : {8, 1}) {
         for (const auto& lg : lags) {
             hog_tuning t{};
@@ -559,6 +660,7 @@ int hog_autotune(const hog_params* prm, const uint8_t* frames, int n, int h, int
             t.wg_per_queue = std::max(1, cus / q);
             t.lag_f = lg[0];
             t.lag_s = lg[1];
+            t.split = 1;
             cand.push_back(t);
         }
     }
@@ -586,6 +688,13 @@ int hog_autotune(const hog_params* prm, const uint8_t* frames, int n, int h, int
             break;
         }
         ms /= (float)reps;
+        // a schedule that reports an error for any frame is not a candidate
+        std::vector<int> counts((size_t)n);
+        if (hipMemcpy(counts.data(), n_dets, sizeof(int) * (size_t)n, hipMemcpyDeviceToHost) != hipSuccess) {
+            st = HOG_E_HIP;
+            break;
+        }
+        if (std::any_of(counts.begin(), counts.end(), [](int c) { return c < 0; })) continue;
         if (best_t < 0.f || ms < best_t) {
             best_t = ms;
             pick = t;

@@ -53,7 +53,7 @@ constexpr int BPACK_PER_GROUP = BPACK_MFMA + BPACK_XTRA;   // 64,000 bytes per f
 
 // Fused persistent kernel (k_fused.hip): counters in the workspace, as
 // u32 words: queue tickets [0, 8), error flag [8], then per frame the
-// finished-wave counts of its histogram and feature items.
+// finished-wave counts of its histogram, feature and scoring items.
 constexpr int FUSED_MAX_QUEUES = 8;
 constexpr int FUSED_SYNC_ERR = 8;
 constexpr int FUSED_SYNC_HEAD = 16;
@@ -68,7 +68,7 @@ struct FusedCfg {
 constexpr int NMS_THREADS = 1024;
 constexpr int SORT_CAP = 4096;
 constexpr int NMS_LIST = 128;       // neighbour-list record per window position: count + 127 entries
-constexpr int NMS_PAR_ROUNDS = 2;   // decision rounds run in parallel over all frames before the per-frame kernel
+constexpr int NMS_PAR_ROUNDS = 3;   // decision rounds run in parallel over all frames before the per-frame kernel
 
 struct DevLevel {
     int h, w, cy, cx;
@@ -135,6 +135,10 @@ hipError_t launch_hist(const LevelTable& T, const uint8_t* frames, long long fst
 hipError_t launch_feat(const LevelTable& T, int n, const float* hist, float* feat,
                        float* packed, hipStream_t s);
 int fused_sync_words(int n);
+struct FusedNeed {
+    unsigned hist, feat, score;   // finished-wave counts of a complete frame
+};
+FusedNeed fused_need(const LevelTable& T, int nf);
 hipError_t launch_fused(const LevelTable& T, int n, const FusedCfg& cfg, const uint8_t* frames, long long fstride,
                         int pitch, const int4* taps, float* hist, float* feat, const float4* bpack,
                         const float* bias, int nf, float thresh, unsigned long long* poskey, bool atomic_key,
@@ -142,13 +146,16 @@ hipError_t launch_fused(const LevelTable& T, int n, const FusedCfg& cfg, const u
 hipError_t launch_score(const LevelTable& T, int n, const float* feat, const float4* bpack,
                         const float* bias, int nf, float thresh, float* dense,
                         unsigned long long* poskey, bool atomic_key, hipStream_t s);
+// NMS records hold 32-bit position indices when a frame has 65536 window
+// positions or more, else 16-bit ones.
+inline bool nms_wide_lists(long long positions) { return positions > 65535; }
 hipError_t launch_nms_edges(const LevelTable& T, int n, const unsigned long long* poskey, const int2* boxes,
-                            long long iou_num, long long iou_den, unsigned* lists, unsigned char* state8,
-                            int rounds, hipStream_t s);
-hipError_t launch_nms(const LevelTable& T, int n, const unsigned long long* poskey, const unsigned* lists,
+                            long long iou_num, long long iou_den, void* lists, unsigned char* state8, int rounds,
+                            hipStream_t s);
+hipError_t launch_nms(const LevelTable& T, int n, const unsigned long long* poskey, const void* lists,
                       const int2* boxes, long long iou_num, long long iou_den, void* dets, int cap, int* n_dets,
-                      unsigned* gstate, int* work, const unsigned char* state8, const unsigned* upstream_err,
-                      hipStream_t s);
+                      unsigned* gstate, int* work, const unsigned char* state8, const unsigned* upstream,
+                      FusedNeed need, hipStream_t s);
 hipError_t launch_level_maps(const LevelTable& T, int level, const uint8_t* frame, int pitch,
                              const int4* taps, float* level_px, uint8_t* bins, hipStream_t s);
 hipError_t launch_orient(const int32_t* gx, const int32_t* gy, long long n, uint8_t* bins,

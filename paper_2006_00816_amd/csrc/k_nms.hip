@@ -9,7 +9,8 @@
 // IoU > iou.  Two kernels compute exactly that:
 //  - hog_nms_edges: for every candidate, in parallel over all frames, the
 //    list of better-ranked candidates that overlap it with IoU > iou
-//    (exact integer areas);
+//    (exact integer areas), as a record of position indices (16-bit when
+//    a frame has fewer than 65536 window positions, else 32-bit);
 //  - hog_nms_round: a few decision rounds in parallel over all frames;
 //  - hog_nms_resolve: one workgroup per frame decides the rest in rounds
 //    over a shrinking worklist (DROPPED if a listed neighbour is kept, KEPT
@@ -86,21 +87,73 @@ __device__ __forceinline__ void decode(unsigned long long key, int& f, int& k, i
     c = pk & 2047;
 }
 
-// ------------------------------------------------------------ edges
-// List of window position p of a frame, stored transposed so that a
-// wave's lanes read consecutive words: entry e at lists[e * P + p], e = 0
-// the count, e = 1.. the neighbour positions.  A count above NMS_LIST - 1
+// ------------------------------------------------------------ records
+// The record of window position p of a frame: NMS_LIST entries of type E
+// at lists + (frame * P + p) * NMS_LIST; entry 0 is the count, entries
+// 1.. the conflicting better-ranked positions.  A count above NMS_LIST - 1
 // means the list was cut short and the candidate is decided by a direct
-// scan instead.
+// scan instead.  Records are read and written in 64-byte chunks (4 x 16 B).
+template <typename E>
+struct Rec {
+    static constexpr int CH = 64 / (int)sizeof(E);   // entries per chunk
+    uint4 c[4];
+    __device__ __forceinline__ void load(const E* rec, int chunk) {
+        const uint4* r4 = reinterpret_cast<const uint4*>(rec) + 4 * chunk;
+        c[0] = r4[0];
+        c[1] = r4[1];
+        c[2] = r4[2];
+        c[3] = r4[3];
+    }
+    // entry j of the loaded chunk (j a compile-time constant after unrolling)
+    __device__ __forceinline__ unsigned at(int j) const {
+        if (sizeof(E) == 2) {
+            const int w = j >> 1;
+            const uint4 q = c[w >> 2];
+            const unsigned x = (w & 3) == 0 ? q.x : (w & 3) == 1 ? q.y : (w & 3) == 2 ? q.z : q.w;
+            return (j & 1) ? x >> 16 : x & 0xffffu;
+        } else {
+            const uint4 q = c[j >> 2];
+            return (j & 3) == 0 ? q.x : (j & 3) == 1 ? q.y : (j & 3) == 2 ? q.z : q.w;
+        }
+    }
+};
+
+// Per-thread staging of one 64-byte chunk in LDS, as 16 words; word w of
+// thread t at stage[w][t], so a wave's accesses fall in different banks.
+template <typename E>
+__device__ __forceinline__ void stage_put(unsigned (*stage)[256], int t, int slot, unsigned v) {
+    if (sizeof(E) == 2) {
+        unsigned& wd = stage[slot >> 1][t];
+        wd = (slot & 1) ? (wd & 0xffffu) | (v << 16) : (wd & 0xffff0000u) | (v & 0xffffu);
+    } else {
+        stage[slot][t] = v;
+    }
+}
+
+__device__ __forceinline__ void stage_flush(unsigned (*stage)[256], int t, void* dst) {
+    uint4* d = reinterpret_cast<uint4*>(dst);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        d[q] = make_uint4(stage[4 * q][t], stage[4 * q + 1][t], stage[4 * q + 2][t], stage[4 * q + 3][t]);
+}
+
+// ------------------------------------------------------------ edges
+// One thread per window position of every frame: the record of the
+// position, and its first-round state (a candidate with no better-ranked
+// conflict is kept).
+template <typename E>
 __global__ __launch_bounds__(256) void hog_nms_edges_kernel(
     LevelTable T, const unsigned long long* __restrict__ poskey, const int2* __restrict__ boxes, long long inum,
-    long long iden, unsigned* __restrict__ lists, unsigned char* __restrict__ state8) {
+    long long iden, E* __restrict__ lists, unsigned char* __restrict__ state8) {
+    constexpr int CH = Rec<E>::CH;
+    __shared__ unsigned st0[16][256], st1[16][256];   // chunk 0 (holds the count) and the current chunk
     const int frame = blockIdx.y;
-    const int p = blockIdx.x * 256 + threadIdx.x;
+    const int t = threadIdx.x;
+    const int p = blockIdx.x * 256 + t;
     if (p >= T.pos_frame) return;
     const unsigned long long* keys = poskey + (long long)frame * T.pos_frame;
     const int P = T.pos_frame;
-    unsigned* out = lists + (long long)frame * P * NMS_LIST + p;
+    E* rec = lists + ((long long)frame * P + p) * NMS_LIST;
     const unsigned long long kx = keys[p];
     int cnt = 0;
     if (kx) {
@@ -119,14 +172,22 @@ __global__ __launch_bounds__(256) void hog_nms_edges_kernel(
                 for (int c2 = R.c_lo; c2 <= R.c_hi; ++c2) {
                     if (keys[base + c2] <= kx) continue;          // worse rank, itself, or not a candidate
                     if (!conflicts(X, AX, ry, boxes[M.box_c + c2], inum, iden)) continue;
-                    if (cnt < NMS_LIST - 1) out[(long long)(1 + cnt) * P] = (unsigned)(base + c2);
+                    const int e = 1 + cnt;
+                    if (e < CH) {
+                        stage_put<E>(st0, t, e, (unsigned)(base + c2));
+                    } else if (e < NMS_LIST) {
+                        stage_put<E>(st1, t, e % CH, (unsigned)(base + c2));
+                        if (e % CH == CH - 1) stage_flush(st1, t, rec + (e / CH) * CH);
+                    }
                     ++cnt;
                 }
             }
         }
     }
-    out[0] = (unsigned)cnt;
-    // first round: a candidate with no better-ranked conflict is kept
+    stage_put<E>(st0, t, 0, (unsigned)min(cnt, 65535));
+    stage_flush(st0, t, rec);
+    const int last = min(cnt, NMS_LIST - 1);
+    if (last >= CH && last % CH != CH - 1) stage_flush(st1, t, rec + (last / CH) * CH);
     state8[(long long)frame * T.pos_frame + p] = (unsigned char)(kx == 0ull ? DROPPED : cnt == 0 ? KEPT : UNDECIDED);
 }
 
@@ -136,26 +197,41 @@ __global__ __launch_bounds__(256) void hog_nms_edges_kernel(
 // can only be stale towards UNDECIDED, which delays a decision but never
 // changes it.  Candidates whose list overflowed are left to the per-frame
 // kernel.
+template <typename E>
 __global__ __launch_bounds__(256) void hog_nms_round_kernel(
-    LevelTable T, const unsigned* __restrict__ lists, unsigned char* __restrict__ state8) {
+    LevelTable T, const E* __restrict__ lists, unsigned char* __restrict__ state8) {
+    constexpr int CH = Rec<E>::CH;
     const int frame = blockIdx.y;
     const int P = T.pos_frame;
     const int p = blockIdx.x * 256 + threadIdx.x;
     if (p >= P) return;
     unsigned char* st = state8 + (long long)frame * P;
     if (st[p] != UNDECIDED) return;
-    const unsigned* rec = lists + (long long)frame * P * NMS_LIST + p;
-    const int cnt = (int)rec[0];
+    const E* rec = lists + ((long long)frame * P + p) * NMS_LIST;
+    Rec<E> R;
+    R.load(rec, 0);
+    const int cnt = (int)R.at(0);
     if (cnt >= NMS_LIST) return;
     bool blocked = false;
-    for (int e = 1; e <= cnt; ++e) {
-        const unsigned idx = rec[(long long)e * P];
-        const unsigned sy = __hip_atomic_load(st + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (sy == KEPT) {
-            __hip_atomic_store(st + p, (unsigned char)DROPPED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return;
+    for (int ch = 0; ch * CH <= cnt; ++ch) {
+        if (ch) R.load(rec, ch);
+        unsigned char sy[CH];
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            const int e = ch * CH + j;
+            const bool in = e >= 1 && e <= cnt;
+            const unsigned char w =
+                __hip_atomic_load(st + (in ? R.at(j) : (unsigned)p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            sy[j] = in ? w : (unsigned char)DROPPED;
         }
-        if (sy == UNDECIDED) blocked = true;
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            if (sy[j] == KEPT) {
+                __hip_atomic_store(st + p, (unsigned char)DROPPED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return;
+            }
+            if (sy[j] == UNDECIDED) blocked = true;
+        }
     }
     if (!blocked) __hip_atomic_store(st + p, (unsigned char)KEPT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -202,37 +278,69 @@ __device__ unsigned decide_scan(const LevelTable& T, const unsigned long long* k
     return blocked ? UNDECIDED : KEPT;
 }
 
-// Decision from the (transposed) neighbour list of a position.
-template <bool G>
-__device__ __forceinline__ unsigned decide_list(const unsigned* S, const unsigned* rec, long long stride, int cnt) {
+// Decision from a position's record whose first chunk is loaded in R.
+template <typename E, bool G>
+__device__ __forceinline__ unsigned decide_rec(const unsigned* S, const E* rec, Rec<E>& R, int cnt) {
+    constexpr int CH = Rec<E>::CH;
     bool blocked = false;
-    for (int e = 1; e <= cnt; ++e) {
-        const unsigned sy = state_of<G>(S, (int)rec[e * stride]);
-        if (sy == KEPT) return DROPPED;
-        if (sy == UNDECIDED) blocked = true;
+    for (int ch = 0; ch * CH <= cnt; ++ch) {
+        if (ch) R.load(rec, ch);
+        // all state reads of the chunk in flight together, then the checks
+        // (16 at a time; unconditional reads, entries past the count
+        // redirected to position 0, so that the compiler does not
+        // serialise them)
+#pragma unroll
+        for (int h = 0; h < CH; h += 16) {
+            unsigned sy[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int e = ch * CH + h + j;
+                const bool in = e >= 1 && e <= cnt;
+                const unsigned w = state_of<G>(S, in ? (int)R.at(h + j) : 0);
+                sy[j] = in ? w : (unsigned)DROPPED;
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                if (sy[j] == KEPT) return DROPPED;
+                if (sy[j] == UNDECIDED) blocked = true;
+            }
+        }
     }
     return blocked ? UNDECIDED : KEPT;
 }
 
 // Appends p to a worklist when `take`; one LDS atomic per wave.
-__device__ __forceinline__ void wave_append(bool take, int p, int* list, int* counter) {
+template <typename W>
+__device__ __forceinline__ void wave_append(bool take, int p, W* list, int* counter) {
     const unsigned long long m = __ballot(take);
     if (!m) return;
     const int lane = threadIdx.x & 63;
     int base = 0;
     if (lane == __builtin_ctzll(m)) base = atomicAdd(counter, __popcll(m));
     base = __shfl(base, __builtin_ctzll(m), 64);
-    if (take) list[base + __popcll(m & ((1ull << lane) - 1ull))] = p;
+    if (take) list[base + __popcll(m & ((1ull << lane) - 1ull))] = (W)p;
 }
 
-template <bool G>
+constexpr int RESOLVE_BATCH = 2;   // worklist items per thread whose records are loaded together
+
+// Record cache of the per-frame kernel: once the worklist is short enough,
+// the records of its candidates are copied into LDS and the remaining
+// rounds read only LDS.  Layout of the dynamic LDS after the states:
+// RC_CHUNKS 64-byte chunks (also the sort buffer afterwards), then per
+// cached candidate its position and first chunk, then two worklists of
+// cached-candidate indices.
+constexpr int RC_MAXI = 2048;
+constexpr int RC_CHUNKS = 1536;
+constexpr int RC_BYTES = RC_CHUNKS * 64 + RC_MAXI * (4 + 2 + 2 + 2);
+static_assert(RC_CHUNKS * 64 >= SORT_CAP * 8, "sort buffer aliases the chunk cache");
+
+template <typename E, bool G>
 __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
-    LevelTable T, const unsigned long long* __restrict__ poskey, const unsigned* __restrict__ lists,
+    LevelTable T, const unsigned long long* __restrict__ poskey, const E* __restrict__ lists,
     const int2* __restrict__ boxes, long long inum, long long iden, hog_det* __restrict__ dets, int cap,
     int* __restrict__ n_dets, unsigned* __restrict__ gstate, int* __restrict__ work,
-    const unsigned char* __restrict__ state8, const unsigned* __restrict__ upstream_err) {
-    extern __shared__ unsigned lstate[];     // 2-bit states (LDS variant)
-    __shared__ unsigned long long sk[SORT_CAP];
+    const unsigned char* __restrict__ state8, const unsigned* __restrict__ upstream, FusedNeed need, int n) {
+    extern __shared__ __align__(16) unsigned dyn[];   // [2-bit states (LDS variant)] + record cache
     __shared__ unsigned int hist[256];
     __shared__ int s_count, s_next;
     __shared__ unsigned long long s_prefix, s_mask;
@@ -240,17 +348,29 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
 
     const int tid = threadIdx.x;
     const int frame = blockIdx.x;
-    // a bounded wait of the fused kernel gave up: the candidates are not
-    // trustworthy, report the error in place of a count
-    if (upstream_err && *upstream_err) {
-        if (tid == 0) n_dets[frame] = HOG_E_DEVICE;
-        return;
+    // after the fused kernel: if one of its bounded waits gave up, or this
+    // frame's items did not all finish, the candidates are not
+    // trustworthy; report the error in place of a count
+    if (upstream) {
+        const unsigned* cnt = upstream + FUSED_SYNC_HEAD;
+        if (upstream[FUSED_SYNC_ERR] || cnt[frame] != need.hist || cnt[n + frame] != need.feat ||
+            cnt[2 * n + frame] != need.score) {
+            if (tid == 0) n_dets[frame] = HOG_E_DEVICE;
+            return;
+        }
     }
     const int P = T.pos_frame;
     const int nw = (P + 15) >> 4;
-    unsigned* S = G ? gstate + (long long)frame * nw : lstate;
+    const int sw = G ? 0 : (nw + 3) & ~3;          // state words in LDS, 16-byte multiple
+    unsigned* S = G ? gstate + (long long)frame * nw : dyn;
+    uint4* rc_chunks = reinterpret_cast<uint4*>(dyn + sw);
+    unsigned long long* sk = reinterpret_cast<unsigned long long*>(rc_chunks);
+    int* rc_pos = reinterpret_cast<int*>(rc_chunks + 4 * RC_CHUNKS);
+    unsigned short* rc_first = reinterpret_cast<unsigned short*>(rc_pos + RC_MAXI);
+    unsigned short* rc_wl[2] = {rc_first + RC_MAXI, rc_first + 2 * RC_MAXI};
+    __shared__ int s_chunks;
     const unsigned long long* keys = poskey + (long long)frame * P;
-    const unsigned* lst = lists + (long long)frame * P * NMS_LIST;   // transposed: entry e of p at e * P + p
+    const E* lst = lists + (long long)frame * P * NMS_LIST;
     int* wl[2] = {work + (long long)frame * 2 * P, work + (long long)frame * 2 * P + P};
 
     // states left by the parallel rounds, and the worklist of the undecided
@@ -275,27 +395,95 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
     }
     __syncthreads();
 
+    constexpr int CH = Rec<E>::CH;
     int cur = 0;
+    bool cached = false;
     for (int round = 0; round <= P; ++round) {
         const int n_in = s_count;
         if (n_in == 0) break;
+        if (!cached && n_in <= RC_MAXI) {
+            // try to cache the records of the worklist: count their chunks
+            if (tid == 0) s_chunks = 0;
+            __syncthreads();
+            const int* in = wl[cur];
+            for (int i = tid; i < n_in; i += NMS_THREADS) {
+                const int p = in[i];
+                const int cnt = (int)lst[(long long)p * NMS_LIST];
+                rc_pos[i] = p;
+                // overflowed lists (decided by a scan) take no chunks: 0xffff
+                rc_first[i] = cnt < NMS_LIST ? (unsigned short)min(atomicAdd(&s_chunks, cnt / CH + 1), 65534)
+                                             : (unsigned short)0xffff;
+            }
+            __syncthreads();
+            if (s_chunks <= RC_CHUNKS) {
+                for (int i = tid; i < n_in; i += NMS_THREADS) {
+                    rc_wl[0][i] = (unsigned short)i;
+                    if (rc_first[i] == 0xffff) continue;
+                    const E* rec = lst + (long long)rc_pos[i] * NMS_LIST;
+                    const int cnt = (int)rec[0];
+                    const uint4* src = reinterpret_cast<const uint4*>(rec);
+                    uint4* dst = rc_chunks + 4 * (int)rc_first[i];
+                    for (int q = 0; q < 4 * (cnt / CH + 1); ++q) dst[q] = src[q];
+                }
+                cached = true;
+                cur = 0;
+                __syncthreads();
+            }
+        }
         if (tid == 0) s_next = 0;
         __syncthreads();
-        const int* in = wl[cur];
-        for (int i0 = 0; i0 < n_in; i0 += NMS_THREADS) {
-            const int i = i0 + tid;
-            bool keep_working = false;
-            int p = 0;
-            if (i < n_in) {
-                p = in[i];
-                const unsigned* rec = lst + p;
-                const int cnt = (int)rec[0];
-                const unsigned v = cnt < NMS_LIST ? decide_list<G>(S, rec, P, cnt)
-                                                  : decide_scan<G>(T, keys, S, boxes, keys[p], inum, iden);
-                if (v != UNDECIDED) atomicOr(&S[p >> 4], v << ((p & 15) * 2));
-                else keep_working = true;
+        if (cached) {
+            const unsigned short* in = rc_wl[cur];
+            for (int i0 = 0; i0 < n_in; i0 += NMS_THREADS) {
+                const int i = i0 + tid;
+                bool keep_working = false;
+                int it = 0;
+                if (i < n_in) {
+                    it = in[i];
+                    const int p = rc_pos[it];
+                    const int first = rc_first[it];
+                    unsigned v;
+                    if (first != 0xffff) {
+                        const E* rec = reinterpret_cast<const E*>(rc_chunks + 4 * first);
+                        Rec<E> R;
+                        R.load(rec, 0);
+                        v = decide_rec<E, G>(S, rec, R, (int)R.at(0));
+                    } else {
+                        v = decide_scan<G>(T, keys, S, boxes, keys[p], inum, iden);
+                    }
+                    if (v != UNDECIDED) atomicOr(&S[p >> 4], v << ((p & 15) * 2));
+                    else keep_working = true;
+                }
+                wave_append(keep_working, it, rc_wl[cur ^ 1], &s_next);
             }
-            wave_append(keep_working, p, wl[cur ^ 1], &s_next);
+        } else {
+            const int* in = wl[cur];
+            for (int i0 = 0; i0 < n_in; i0 += RESOLVE_BATCH * NMS_THREADS) {
+                int pp[RESOLVE_BATCH];
+                Rec<E> R[RESOLVE_BATCH];
+#pragma unroll
+                for (int b = 0; b < RESOLVE_BATCH; ++b) {
+                    const int i = i0 + b * NMS_THREADS + tid;
+                    pp[b] = i < n_in ? in[i] : -1;
+                }
+#pragma unroll
+                for (int b = 0; b < RESOLVE_BATCH; ++b)
+                    if (pp[b] >= 0) R[b].load(lst + (long long)pp[b] * NMS_LIST, 0);
+#pragma unroll
+                for (int b = 0; b < RESOLVE_BATCH; ++b) {
+                    bool keep_working = false;
+                    const int p = pp[b];
+                    if (p >= 0) {
+                        const int cnt = (int)R[b].at(0);
+                        const unsigned v = cnt < NMS_LIST
+                                               ? decide_rec<E, G>(S, lst + (long long)p * NMS_LIST, R[b], cnt)
+                                               : decide_scan<G>(T, keys, S, boxes, keys[p], inum, iden);
+                        if (v != UNDECIDED) atomicOr(&S[p >> 4], v << ((p & 15) * 2));
+                        else keep_working = true;
+                    }
+                    wave_append(keep_working, p, wl[cur ^ 1], &s_next);
+                }
+            }
         }
         __syncthreads();
         if (tid == 0) s_count = s_next;
@@ -391,31 +579,60 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
 }
 
 // Positions whose states fit in LDS next to the sort buffer.
-constexpr int NMS_LDS_STATE_WORDS = (150 * 1024 - SORT_CAP * 8 - 2048) / 4;
+constexpr int NMS_LDS_STATE_WORDS = (160 * 1024 - RC_BYTES - 2048) / 4;
 
 hipError_t launch_nms_edges(const LevelTable& T, int n, const unsigned long long* poskey, const int2* boxes,
-                            long long iou_num, long long iou_den, unsigned* lists, unsigned char* state8,
-                            int rounds, hipStream_t s) {
+                            long long iou_num, long long iou_den, void* lists, unsigned char* state8, int rounds,
+                            hipStream_t s) {
     const dim3 grid((T.pos_frame + 255) / 256, n);
-    hipLaunchKernelGGL(hog_nms_edges_kernel, grid, dim3(256), 0, s, T, poskey, boxes, iou_num, iou_den, lists,
-                       state8);
-    for (int r = 0; r < rounds; ++r)
-        hipLaunchKernelGGL(hog_nms_round_kernel, grid, dim3(256), 0, s, T, lists, state8);
+    if (nms_wide_lists(T.pos_frame)) {
+        hipLaunchKernelGGL(hog_nms_edges_kernel<unsigned>, grid, dim3(256), 0, s, T, poskey, boxes, iou_num, iou_den,
+                           (unsigned*)lists, state8);
+        for (int r = 0; r < rounds; ++r)
+            hipLaunchKernelGGL(hog_nms_round_kernel<unsigned>, grid, dim3(256), 0, s, T, (const unsigned*)lists,
+                               state8);
+    } else {
+        hipLaunchKernelGGL(hog_nms_edges_kernel<unsigned short>, grid, dim3(256), 0, s, T, poskey, boxes, iou_num,
+                           iou_den, (unsigned short*)lists, state8);
+        for (int r = 0; r < rounds; ++r)
+            hipLaunchKernelGGL(hog_nms_round_kernel<unsigned short>, grid, dim3(256), 0, s, T,
+                               (const unsigned short*)lists, state8);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_nms(const LevelTable& T, int n, const unsigned long long* poskey, const unsigned* lists,
-                      const int2* boxes, long long iou_num, long long iou_den, void* dets, int cap, int* n_dets,
-                      unsigned* gstate, int* work, const unsigned char* state8, const unsigned* upstream_err,
-                      hipStream_t s) {
+template <typename E>
+void launch_resolve(const LevelTable& T, int n, const unsigned long long* poskey, const void* lists,
+                    const int2* boxes, long long iou_num, long long iou_den, void* dets, int cap, int* n_dets,
+                    unsigned* gstate, int* work, const unsigned char* state8, const unsigned* upstream,
+                    FusedNeed need, hipStream_t s) {
     const int nw = (T.pos_frame + 15) >> 4;
     if (nw <= NMS_LDS_STATE_WORDS) {
-        hipLaunchKernelGGL(hog_nms_resolve_kernel<false>, dim3(n), dim3(NMS_THREADS), nw * sizeof(unsigned), s, T,
-                           poskey, lists, boxes, iou_num, iou_den, (hog_det*)dets, cap, n_dets, gstate, work, state8, upstream_err);
+        const size_t lds = sizeof(unsigned) * (size_t)((nw + 3) & ~3) + RC_BYTES;
+        (void)hipFuncSetAttribute((const void*)hog_nms_resolve_kernel<E, false>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL((hog_nms_resolve_kernel<E, false>), dim3(n), dim3(NMS_THREADS), lds, s, T, poskey,
+                           (const E*)lists, boxes, iou_num, iou_den, (hog_det*)dets, cap, n_dets, gstate, work,
+                           state8, upstream, need, n);
     } else {
-        hipLaunchKernelGGL(hog_nms_resolve_kernel<true>, dim3(n), dim3(NMS_THREADS), 0, s, T, poskey, lists, boxes,
-                           iou_num, iou_den, (hog_det*)dets, cap, n_dets, gstate, work, state8, upstream_err);
+        (void)hipFuncSetAttribute((const void*)hog_nms_resolve_kernel<E, true>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, RC_BYTES);
+        hipLaunchKernelGGL((hog_nms_resolve_kernel<E, true>), dim3(n), dim3(NMS_THREADS), RC_BYTES, s, T, poskey,
+                           (const E*)lists, boxes, iou_num, iou_den, (hog_det*)dets, cap, n_dets, gstate, work,
+                           state8, upstream, need, n);
     }
+}
+
+hipError_t launch_nms(const LevelTable& T, int n, const unsigned long long* poskey, const void* lists,
+                      const int2* boxes, long long iou_num, long long iou_den, void* dets, int cap, int* n_dets,
+                      unsigned* gstate, int* work, const unsigned char* state8, const unsigned* upstream,
+                      FusedNeed need, hipStream_t s) {
+    if (nms_wide_lists(T.pos_frame))
+        launch_resolve<unsigned>(T, n, poskey, lists, boxes, iou_num, iou_den, dets, cap, n_dets, gstate, work,
+                                 state8, upstream, need, s);
+    else
+        launch_resolve<unsigned short>(T, n, poskey, lists, boxes, iou_num, iou_den, dets, cap, n_dets, gstate,
+                                       work, state8, upstream, need, s);
     return hipGetLastError();
 }
 

@@ -1,8 +1,9 @@
-"""The fused persistent kernel (histograms, features and scores of every
-frame and level from one work list) gives the same detections, bit for
-bit, as the per-stage kernels, for several work-list settings, batch sizes
-that do not fill the queues evenly, several filter groups, 2x upsampling,
-and graph replay; the autotuner picks a valid schedule that keeps them."""
+"""Schedules of hog_detect_batch give the same detections, bit for bit:
+the fused persistent kernel (histograms, features and scores of every
+frame and level from one work list) for several work-list settings, batch
+sizes that do not fill the queues evenly, several filter groups, 2x
+upsampling and graph replay; the per-stage kernels with the frames split
+into groups on forked streams; and the autotuner's pick."""
 import numpy as np
 import pytest
 import torch
@@ -13,7 +14,7 @@ from test_gpu_parity import H, cu  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 
-STAGED = {"fused": 0, "queues": 8, "wg_per_queue": 32, "lag_f": 1, "lag_s": 2}
+STAGED = {"fused": 0, "queues": 8, "wg_per_queue": 32, "lag_f": 1, "lag_s": 2, "split": 1}
 
 
 def _run(H, fr, W, b, tuning, upsample=1):
@@ -40,7 +41,7 @@ def test_fused_equals_staged_clip(H, queues, wg, lag_f, lag_s):
     fr, W, b = cu(wl.frames), cu(wl.W), cu(wl.b)
     print(f"fused q={queues} wg={wg} lags=({lag_f},{lag_s}) n=13", flush=True)
     ref = _run(H, fr, W, b, STAGED)
-    got = _run(H, fr, W, b, {"fused": 1, "queues": queues, "wg_per_queue": wg, "lag_f": lag_f, "lag_s": lag_s})
+    got = _run(H, fr, W, b, {"fused": 1, "queues": queues, "wg_per_queue": wg, "lag_f": lag_f, "lag_s": lag_s, "split": 1})
     _assert_same(got, ref, 13)
     assert sum(ref[1]) > 0
 
@@ -61,15 +62,44 @@ def test_fused_equals_staged_shapes(H, nf, shape, upsample, n):
     W, b = cu(W), cu(b)
     print(f"fused nf={nf} {h}x{w} u={upsample} n={n}", flush=True)
     ref = _run(H, fr, W, b, STAGED, upsample)
-    got = _run(H, fr, W, b, {"fused": 1, "queues": 8, "wg_per_queue": 32, "lag_f": 1, "lag_s": 2}, upsample)
+    got = _run(H, fr, W, b, {"fused": 1, "queues": 8, "wg_per_queue": 32, "lag_f": 1, "lag_s": 2, "split": 1}, upsample)
     _assert_same(got, ref, n)
+
+
+@pytest.mark.parametrize("split,n", [(2, 13), (3, 13), (4, 5), (4, 3)])
+def test_split_equals_staged(H, split, n):
+    wl = synth.config1(seed=24, n=n)
+    fr, W, b = cu(wl.frames), cu(wl.W), cu(wl.b)
+    print(f"split={split} n={n}", flush=True)
+    ref = _run(H, fr, W, b, STAGED)
+    got = _run(H, fr, W, b, {**STAGED, "split": split})
+    _assert_same(got, ref, n)
+
+
+def test_split_graph_replay(H):
+    wl = synth.config1(seed=25, n=16)
+    fr, W, b = cu(wl.frames), cu(wl.W), cu(wl.b)
+    ref = _run(H, fr, W, b, STAGED)
+    H.tuning_set(480, 640, 1, 16, 5, {**STAGED, "split": 2})
+    try:
+        g = H.DetectGraph(fr, W, b)
+        other = cu(synth.config0(5).frames[0])
+        for rep in range(3):
+            g.launch()
+            torch.cuda.synchronize()
+            _assert_same(H.dets_to_numpy(g.dets, g.n_dets), ref, 16)
+            H.scores(other, W, b)
+            torch.cuda.synchronize()
+        g.close()
+    finally:
+        H.tuning_set(480, 640, 1, 16, 5, None)
 
 
 def test_fused_graph_replay(H):
     wl = synth.config1(seed=22, n=16)
     fr, W, b = cu(wl.frames), cu(wl.W), cu(wl.b)
     ref = _run(H, fr, W, b, STAGED)
-    H.tuning_set(480, 640, 1, 16, 5, {"fused": 1, "queues": 8, "wg_per_queue": 32, "lag_f": 1, "lag_s": 2})
+    H.tuning_set(480, 640, 1, 16, 5, {"fused": 1, "queues": 8, "wg_per_queue": 32, "lag_f": 1, "lag_s": 2, "split": 1})
     try:
         g = H.DetectGraph(fr, W, b)
         other = cu(synth.config0(5).frames[0])
