@@ -270,15 +270,20 @@ int compute_units() {
 
 constexpr int MAX_SPLIT = 4;
 
+constexpr int MAX_NMS_ROUNDS = 16;
+
 bool tuning_valid(const hog_tuning& t) {
     if (t.split < 1 || t.split > MAX_SPLIT) return false;
+    if (t.nms_rounds < 0 || t.nms_rounds > MAX_NMS_ROUNDS) return false;
     if (t.fused == 0) return true;
     return t.fused == 1 && t.split == 1 && t.queues >= 1 && t.queues <= FUSED_MAX_QUEUES && t.wg_per_queue >= 1 &&
            t.wg_per_queue <= 65536 && t.lag_f >= 1 && t.lag_s > t.lag_f && t.lag_s <= 64;
 }
 
-hog_tuning default_tuning(int, int, int, int, int) {
+hog_tuning default_tuning(int, int, int, int n, int) {
     hog_tuning t{};
+    // parallel NMS rounds: small batches leave most of the GPU to them
+    t.nms_rounds = n <= 2 ? 8 : n <= 8 ? 5 : 3;
     t.fused = 0;
     t.queues = 8;
     t.wg_per_queue = 32;
@@ -353,7 +358,7 @@ int split_resources(SplitRes** out) {
 }
 
 int nms_chain(const Plan& P, int m, const FrameBufs& b, const hog_params* prm, int cap, const unsigned* upstream,
-              void* ws, hipStream_t s) {
+              int rounds, void* ws, hipStream_t s) {
     const LevelTable& T = P.T;
     // iou (a float32 in [1/2, 1)) as the exact binary fraction num / 2^e,
     // e <= 24, so that inter * 2^e stays below 2^63
@@ -365,8 +370,7 @@ int nms_chain(const Plan& P, int m, const FrameBufs& b, const hog_params* prm, i
     }
     const long long num = (long long)v, den = 1LL << e;
     HOG_TRY(timed("nms_edges", s, [&] {
-        return launch_nms_edges(T, m, b.keys, at<int2>(ws, P.o_boxes), num, den, b.lists, b.state8, NMS_PAR_ROUNDS,
-                                s);
+        return launch_nms_edges(T, m, b.keys, at<int2>(ws, P.o_boxes), num, den, b.lists, b.state8, rounds, s);
     }));
     return timed("nms", s, [&] {
         return launch_nms(T, m, b.keys, b.lists, at<int2>(ws, P.o_boxes), num, den, b.dets, cap, b.n_dets, b.gstate,
@@ -376,7 +380,7 @@ int nms_chain(const Plan& P, int m, const FrameBufs& b, const hog_params* prm, i
 
 // histograms -> features -> scores -> NMS for frames lo .. lo + m - 1
 int staged_chain(const Plan& P, int m, const FrameBufs& b, long long fstride, int pitch, const hog_params* prm,
-                 const float* bias, int cap, void* ws, hipStream_t s) {
+                 const float* bias, int cap, int rounds, void* ws, hipStream_t s) {
     const LevelTable& T = P.T;
     const bool multi = P.groups > 1;
     HOG_TRY(timed("hist", s, [&] {
@@ -387,7 +391,7 @@ int staged_chain(const Plan& P, int m, const FrameBufs& b, long long fstride, in
         return launch_score(T, m, b.feat, at<float4>(ws, P.o_bpack), bias, P.nf, prm->thresh, nullptr, b.keys, multi,
                             s);
     }));
-    return nms_chain(P, m, b, prm, cap, nullptr, ws, s);
+    return nms_chain(P, m, b, prm, cap, nullptr, rounds, ws, s);
 }
 
 int detect_sequence(const Plan& P, const hog_params* prm, const uint8_t* frames, long long fstride, int pitch,
@@ -417,12 +421,13 @@ int detect_sequence(const Plan& P, const hog_params* prm, const uint8_t* frames,
                                 at<float>(ws, P.o_feat), at<float4>(ws, P.o_bpack), bias, P.nf, prm->thresh,
                                 at<unsigned long long>(ws, P.o_key), multi, sync, s);
         }));
-        return nms_chain(P, P.n, frame_bufs(P, ws, frames, fstride, dets, cap, n_dets, 0), prm, cap, sync, ws, s);
+        return nms_chain(P, P.n, frame_bufs(P, ws, frames, fstride, dets, cap, n_dets, 0), prm, cap, sync,
+                         tune.nms_rounds, ws, s);
     }
     const int parts = std::min(std::max(tune.split, 1), P.n);
     if (parts == 1)
         return staged_chain(P, P.n, frame_bufs(P, ws, frames, fstride, dets, cap, n_dets, 0), fstride, pitch, prm,
-                            bias, cap, ws, s);
+                            bias, cap, tune.nms_rounds, ws, s);
     // the frames in `parts` groups on forked streams: one group's NMS
     // overlaps another's histograms and scores
     SplitRes* r = nullptr;
@@ -434,7 +439,7 @@ int detect_sequence(const Plan& P, const hog_params* prm, const uint8_t* frames,
     for (int j = 0; j < parts && st == HOG_OK; ++j) {
         const int lo = (int)((long long)j * P.n / parts), hi = (int)((long long)(j + 1) * P.n / parts);
         st = staged_chain(P, hi - lo, frame_bufs(P, ws, frames, fstride, dets, cap, n_dets, lo), fstride, pitch,
-                          prm, bias, cap, ws, j == 0 ? s : r->st[j - 1]);
+                          prm, bias, cap, tune.nms_rounds, ws, j == 0 ? s : r->st[j - 1]);
     }
     // join (also after an error, so that no forked stream is left behind a capture)
     for (int j = 1; j < parts; ++j) {
@@ -648,8 +653,11 @@ int hog_autotune(const hog_params* prm, const uint8_t* frames, int n, int h, int
     std::vector<hog_tuning> cand;
     for (int sp : {1, 2, 4}) {
         if (sp > n) break;
-        cand.push_back(default_tuning(h, w, prm->upsample, n, nf));
-        cand.back().split = sp;
+        for (int nr : {2, 4, 8}) {
+            cand.push_back(default_tuning(h, w, prm->upsample, n, nf));
+            cand.back().split = sp;
+            cand.back().nms_rounds = nr;
+        }
     }
     const int lags[4][2] = {{1, 2}, {1, 3}, {2, 3}, {2, 4}};
     for (int q : {8, 1}) {
@@ -661,6 +669,7 @@ int hog_autotune(const hog_params* prm, const uint8_t* frames, int n, int h, int
             t.lag_f = lg[0];
             t.lag_s = lg[1];
             t.split = 1;
+            t.nms_rounds = default_tuning(h, w, prm->upsample, n, nf).nms_rounds;
             cand.push_back(t);
         }
     }

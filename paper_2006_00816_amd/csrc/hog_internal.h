@@ -68,7 +68,6 @@ struct FusedCfg {
 constexpr int NMS_THREADS = 1024;
 constexpr int SORT_CAP = 4096;
 constexpr int NMS_LIST = 128;       // neighbour-list record per window position: count + 127 entries
-constexpr int NMS_PAR_ROUNDS = 3;   // decision rounds run in parallel over all frames before the per-frame kernel
 
 struct DevLevel {
     int h, w, cy, cx;

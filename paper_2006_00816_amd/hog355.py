@@ -30,7 +30,8 @@ class hog_params(ctypes.Structure):
 
 class hog_tuning(ctypes.Structure):
     _fields_ = [("fused", ctypes.c_int32), ("queues", ctypes.c_int32), ("wg_per_queue", ctypes.c_int32),
-                ("lag_f", ctypes.c_int32), ("lag_s", ctypes.c_int32), ("split", ctypes.c_int32)]
+                ("lag_f", ctypes.c_int32), ("lag_s", ctypes.c_int32), ("split", ctypes.c_int32),
+                ("nms_rounds", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -263,7 +264,7 @@ def tuning_set(h: int, w: int, upsample: int, n: int, nf: int, t: dict | None):
     if t is None:
         _check(lib().hog_tuning_set(h, w, upsample, n, nf, None), "hog_tuning_set")
         return
-    tt = hog_tuning(**{"split": 1, **{k: int(v) for k, v in t.items()}})
+    tt = hog_tuning(**{"split": 1, "nms_rounds": 3, **{k: int(v) for k, v in t.items()}})
     _check(lib().hog_tuning_set(h, w, upsample, n, nf, ctypes.byref(tt)), "hog_tuning_set")
 
 
@@ -281,6 +282,43 @@ def autotune(frames: torch.Tensor, W, b, cap=MAX_DETS, thresh=0.0, iou=0.5, upsa
                               _ptr(W), _ptr(b), nf, _ptr(dets), cap, _ptr(nd), wp, wn, reps, ctypes.byref(best),
                               ctypes.byref(ms), _stream()), "hog_autotune")
     return best.as_dict(), float(ms.value)
+
+
+class BoundGraph:
+    """hog_detect_batch over caller-owned buffers (frames uint8 [n][h][w],
+    dets int32 [n][cap][10], n_dets int32 [n], workspace tensor) captured
+    once as a hipGraph on ``stream``; launch() replays it on a stream."""
+
+    def __init__(self, frames: torch.Tensor, W, b, dets: torch.Tensor, n_dets: torch.Tensor, ws: torch.Tensor,
+                 thresh=0.0, iou=0.5, upsample=1, stream=None):
+        n, h, w = (int(v) for v in frames.shape)
+        nf = int(W.shape[0])
+        need = workspace_bytes(h, w, upsample, n, nf)
+        if ws.numel() < need:
+            raise HogError(f"workspace of {ws.numel()} bytes, {need} needed")
+        self.keep = (frames, W, b, dets, n_dets, ws)
+        self.prm = _params(thresh, iou, upsample)
+        self.handle = ctypes.c_void_p()
+        st = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().hog_graph_create(ctypes.byref(self.handle), ctypes.byref(self.prm), _ptr(frames), n, h, w,
+                                      int(frames.stride(1)), int(frames.stride(0)), _ptr(W), _ptr(b), nf, _ptr(dets),
+                                      int(dets.shape[1]), _ptr(n_dets), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                      ctypes.c_void_p(st.cuda_stream)), "hog_graph_create")
+
+    def launch(self, stream=None):
+        st = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().hog_graph_launch(self.handle, ctypes.c_void_p(st.cuda_stream)), "hog_graph_launch")
+
+    def close(self):
+        if self.handle:
+            lib().hog_graph_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class DetectGraph:
