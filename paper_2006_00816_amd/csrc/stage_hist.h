@@ -125,24 +125,36 @@ __device__ __forceinline__ void hist_tile(const LevelTable& T, const uint8_t* __
     }
     __syncthreads();
 
-    // 1. resample
+    // 1. resample, RS pixels per thread at a time with all their frame
+    // loads in flight together (taps are clamped to the frame, so every
+    // load is in bounds; a zero weight or a pixel outside the level
+    // discards the value)
     if (on) {
-        for (int e = tid; e < TPY * TPX; e += HIST_THREADS) {
-            const int ty = e / TPX, tx = e - ty * TPX;
-            const int4 a = sTy[ty], b = sTx[tx];
-            int v = 0;
-            if ((a.w | b.w) == 0) {
-                const unsigned o00 = (unsigned)(a.x + b.x);
-                int top = (256 - b.z) * (int)U[o00];
-                if (b.z) top += b.z * (int)U[(unsigned)(a.x + b.y)];
-                int bot = 0;
-                if (a.z) {
-                    bot = (256 - b.z) * (int)U[(unsigned)(a.y + b.x)];
-                    if (b.z) bot += b.z * (int)U[(unsigned)(a.y + b.y)];
-                }
-                v = (256 - a.z) * top + a.z * bot;
+        constexpr int RS = 6;
+        for (int e0 = tid; e0 < TPY * TPX; e0 += RS * HIST_THREADS) {
+            int ty[RS], tx[RS], ay[RS], bx[RS], inside[RS];
+            int u00[RS], u01[RS], u10[RS], u11[RS];
+#pragma unroll
+            for (int r = 0; r < RS; ++r) {
+                const int e = min(e0 + r * HIST_THREADS, TPY * TPX - 1);
+                ty[r] = e / TPX;
+                tx[r] = e - ty[r] * TPX;
+                const int4 a = sTy[ty[r]], b = sTx[tx[r]];
+                ay[r] = a.z;
+                bx[r] = b.z;
+                inside[r] = (a.w | b.w) == 0;
+                u00[r] = U[(unsigned)(a.x + b.x)];
+                u01[r] = U[(unsigned)(a.x + b.y)];
+                u10[r] = U[(unsigned)(a.y + b.x)];
+                u11[r] = U[(unsigned)(a.y + b.y)];
             }
-            sV[swz(ty, tx)] = v;
+#pragma unroll
+            for (int r = 0; r < RS; ++r) {
+                const int top = (256 - bx[r]) * u00[r] + bx[r] * u01[r];
+                const int bot = (256 - bx[r]) * u10[r] + bx[r] * u11[r];
+                const int v = inside[r] ? (256 - ay[r]) * top + ay[r] * bot : 0;
+                if (e0 + r * HIST_THREADS < TPY * TPX) sV[swz(ty[r], tx[r])] = v;
+            }
         }
     }
     __syncthreads();
