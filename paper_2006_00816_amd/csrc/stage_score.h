@@ -70,29 +70,41 @@ __device__ __forceinline__ void score_row(const DevLevel& L, int k, int r, const
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
         float x8 = 0.f, x9 = 0.f;
-        // cells past the last window's reach (x >= cx) are never summed
+        // cells past the last window's reach (x >= cx) are never summed.
+        // The operand of K chunk kc + 2 is loaded while chunk kc computes;
+        // the MFMAs of one chunk alternate between the N tiles so that
+        // consecutive ones are independent.
         const float* __restrict__ a = Fr + min(16 * t + j, L.cx + 1) * FPAD;
+        auto load_a = [&](int kc) {
+            return *reinterpret_cast<const float4*>(a + (kc >> 1) * pitch + 16 * (kc & 1));
+        };
+        float4 av[SC_KC];
+        av[0] = load_a(0);
+        av[1] = load_a(1);
 #pragma unroll
         for (int kc = 0; kc < SC_KC; ++kc) {
-            const float4 av = *reinterpret_cast<const float4*>(a + (kc >> 1) * pitch + 16 * (kc & 1));
+            if (kc + 2 < SC_KC) av[kc + 2] = load_a(kc + 2);
+            float4 b[NT];
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const float4 b = sm.B[(kc * SC_NT + nt) * 64 + lane];
-                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, b.x, acc[nt], 0, 0, 0);
-                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, b.y, acc[nt], 0, 0, 0);
-                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, b.z, acc[nt], 0, 0, 0);
-                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, b.w, acc[nt], 0, 0, 0);
-            }
+            for (int nt = 0; nt < NT; ++nt) b[nt] = sm.B[(kc * SC_NT + nt) * 64 + lane];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kc].x, b[nt].x, acc[nt], 0, 0, 0);
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kc].y, b[nt].y, acc[nt], 0, 0, 0);
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kc].z, b[nt].z, acc[nt], 0, 0, 0);
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kc].w, b[nt].w, acc[nt], 0, 0, 0);
             if (XTRA) {
                 const float4 w8 = X[kc * 8], w9 = X[kc * 8 + 1];
-                x8 = fmaf(av.x, w8.x, x8);
-                x8 = fmaf(av.y, w8.y, x8);
-                x8 = fmaf(av.z, w8.z, x8);
-                x8 = fmaf(av.w, w8.w, x8);
-                x9 = fmaf(av.x, w9.x, x9);
-                x9 = fmaf(av.y, w9.y, x9);
-                x9 = fmaf(av.z, w9.z, x9);
-                x9 = fmaf(av.w, w9.w, x9);
+                x8 = fmaf(av[kc].x, w8.x, x8);
+                x8 = fmaf(av[kc].y, w8.y, x8);
+                x8 = fmaf(av[kc].z, w8.z, x8);
+                x8 = fmaf(av[kc].w, w8.w, x8);
+                x9 = fmaf(av[kc].x, w9.x, x9);
+                x9 = fmaf(av[kc].y, w9.y, x9);
+                x9 = fmaf(av[kc].z, w9.z, x9);
+                x9 = fmaf(av[kc].w, w9.w, x9);
             }
         }
         if (XTRA) {
