@@ -169,17 +169,32 @@ __global__ __launch_bounds__(256) void hog_nms_edges_kernel(
                 const int2 ry = boxes[M.box_r + r2];
                 if (min(X.y1, ry.y) <= max(X.y0, ry.x)) continue;
                 const int base = M.pos_off + r2 * M.cols;
-                for (int c2 = R.c_lo; c2 <= R.c_hi; ++c2) {
-                    if (keys[base + c2] <= kx) continue;          // worse rank, itself, or not a candidate
-                    if (!conflicts(X, AX, ry, boxes[M.box_c + c2], inum, iden)) continue;
-                    const int e = 1 + cnt;
-                    if (e < CH) {
-                        stage_put<E>(st0, t, e, (unsigned)(base + c2));
-                    } else if (e < NMS_LIST) {
-                        stage_put<E>(st1, t, e % CH, (unsigned)(base + c2));
-                        if (e % CH == CH - 1) stage_flush(st1, t, rec + (e / CH) * CH);
+                // 8 columns at a time, their key and box loads in flight
+                // together (columns past the range re-read the last one)
+                for (int c0 = R.c_lo; c0 <= R.c_hi; c0 += 8) {
+                    unsigned long long kk[8];
+                    int2 bc[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const int c2 = min(c0 + q, R.c_hi);
+                        kk[q] = keys[base + c2];
+                        bc[q] = boxes[M.box_c + c2];
                     }
-                    ++cnt;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const int c2 = c0 + q;
+                        if (c2 > R.c_hi) break;
+                        if (kk[q] <= kx) continue;          // worse rank, itself, or not a candidate
+                        if (!conflicts(X, AX, ry, bc[q], inum, iden)) continue;
+                        const int e = 1 + cnt;
+                        if (e < CH) {
+                            stage_put<E>(st0, t, e, (unsigned)(base + c2));
+                        } else if (e < NMS_LIST) {
+                            stage_put<E>(st1, t, e % CH, (unsigned)(base + c2));
+                            if (e % CH == CH - 1) stage_flush(st1, t, rec + (e / CH) * CH);
+                        }
+                        ++cnt;
+                    }
                 }
             }
         }
