@@ -26,6 +26,26 @@ FP32_PEAK_TFLOPS = 157.3     # MI355X dense FP32 matrix peak
 HBM_PEAK_GBS = 8000.0
 
 
+def score_traffic():
+    """HBM bytes per launch of the scoring kernel from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, calibrated by a
+    plain copy), if the scorer sources are still the ones profiled; else
+    None."""
+    import hashlib
+    src = b"".join(open(os.path.join(ROOT, "paper_2006_00816_amd", "csrc", f), "rb").read()
+                   for f in ("hog_internal.h", "stage_score.h", "k_score.hip"))
+    sha = hashlib.sha256(src).hexdigest()[:16]
+    path = os.path.join(ROOT, "profiles", "kernels_64x640x480_staged.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("score_traffic "):
+            kv = dict(t.split("=", 1) for t in line.split()[1:])
+            if kv.get("sha256_16") == sha:
+                return int(kv["fetch_bytes"]) + int(kv["write_bytes"])
+    return None
+
+
 def windows_per_frame(h, w):
     from paper_2006_00816_amd import hog355
     return sum(l["rows"] * l["cols"] for l in hog355.pyramid(h, w, 1, NF))
@@ -273,8 +293,15 @@ def main():
     achieved = flop_per_frame * CLIP / (max(staged_kern["score"], 1e-9) * 1e-3) / 1e12
     roofline = {"bound": "mfma", "kernel": "hog_score_kernel", "achieved": round(achieved, 2),
                 "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-                "traffic": None,
+                "traffic": score_traffic(),
                 "flop_per_launch": flop_per_frame * CLIP, "avg_launch_ms": round(staged_kern["score"], 5)}
+    # the whole path against the FP32 and HBM rooflines: algorithmic scoring
+    # FLOP, and the bytes a frame must cross (frame in, detections out)
+    det_bytes = 40.0 * float(np.mean(n_kept))
+    path = {"fp32_tflops": round(flop_per_frame * fps / 1e12, 3),
+            "fp32_frac": round(flop_per_frame * fps / 1e12 / FP32_PEAK_TFLOPS, 4),
+            "hbm_gbs": round((H * W_PX + det_bytes) * fps / 1e9, 2),
+            "hbm_frac": round((H * W_PX + det_bytes) * fps / 1e9 / HBM_PEAK_GBS, 5)}
 
     out = {
         "metric": METRIC,
@@ -304,6 +331,7 @@ def main():
         "staged_kernels_avg_ms_per_64_frames": {k: round(v, 5) for k, v in staged_kern.items()},
         "kept_per_frame_mean": float(np.mean(n_kept)),
         "roofline": roofline,
+        "roofline_path": path,
         "paper_context": {"ms_per_frame": 0.333, "hardware": "NVIDIA Titan X (Pascal), 16 images per launch",
                           "end_to_end_ms_per_frame": 0.533},
     }
