@@ -205,8 +205,8 @@ def main():
     torch.cuda.synchronize()
 
     # ---------------------------------------------------------- schedule
-    staged = {"fused": 0, "queues": 8, "wg_per_queue": 32, "lag_f": 1, "lag_s": 2, "split": 1, "nms_rounds": 3}
-    fused = {"fused": 1, "queues": 8, "wg_per_queue": 32, "lag_f": 1, "lag_s": 2, "split": 1, "nms_rounds": 3}
+    staged = {"fused": 0, "queues": 8, "wg_per_queue": 32, "lag_f": 1, "lag_s": 2, "split": 1, "nms_rounds": 3, "score_rows": 0}
+    fused = {"fused": 1, "queues": 8, "wg_per_queue": 32, "lag_f": 1, "lag_s": 2, "split": 1, "nms_rounds": 3, "score_rows": 0}
     tune_ms = None
     if args.schedule == "auto":
         tuning, tune_ms = hog355.autotune(frames, Wt, bt, reps=5)

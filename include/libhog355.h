@@ -189,7 +189,9 @@ int hog_graph_destroy(hog_graph* g);
  *   waits only on earlier tickets.  split must be 1.
  * nms_rounds (0..16): NMS decision rounds run over all window positions of
  *   all frames of a group before the per-frame NMS kernel decides the rest
- *   (any value gives the same detections). */
+ *   (any value gives the same detections).
+ * score_rows (per-stage schedule): window rows per scoring workgroup, 4 or
+ *   16; 0 picks 4 when the batch has fewer 16-row items than compute units. */
 typedef struct hog_tuning {
     int32_t fused;
     int32_t queues;
@@ -198,6 +200,7 @@ typedef struct hog_tuning {
     int32_t lag_s;
     int32_t split;
     int32_t nms_rounds;
+    int32_t score_rows;
 } hog_tuning;
 
 /* The schedule in effect for a shape: the one set by hog_tuning_set or
@@ -214,8 +217,8 @@ int hog_tuning_set(int h, int w, int upsample, int n, int nf, const hog_tuning* 
  * HIP events on `stream`), keeps the fastest for this shape as with
  * hog_tuning_set and returns it in `best` with its mean time per call in
  * `best_ms`.  Arguments as hog_detect_batch; blocks the host until done.
- * The candidates: the per-stage schedule with split 1, 2 and 4 and 2, 4
- * or 8 NMS rounds, and the fused kernel with 8 or 1 queues, one workgroup per compute unit, and
+ * The candidates: the per-stage schedule with split 1, 2 and 4, 2, 4 or 8
+ * NMS rounds and scoring items of 4 or 16 rows, and the fused kernel with 8 or 1 queues, one workgroup per compute unit, and
  * lags (1,2), (1,3), (2,3), (2,4); a candidate that reports an error in
  * any n_dets entry is skipped. */
 int hog_autotune(const hog_params* prm, const uint8_t* frames, int n,

@@ -275,6 +275,7 @@ constexpr int MAX_NMS_ROUNDS = 16;
 bool tuning_valid(const hog_tuning& t) {
     if (t.split < 1 || t.split > MAX_SPLIT) return false;
     if (t.nms_rounds < 0 || t.nms_rounds > MAX_NMS_ROUNDS) return false;
+    if (t.score_rows != 0 && t.score_rows != SCORE_SMALL_ROWS && t.score_rows != ROWS_PER_ITEM) return false;
     if (t.fused == 0) return true;
     return t.fused == 1 && t.split == 1 && t.queues >= 1 && t.queues <= FUSED_MAX_QUEUES && t.wg_per_queue >= 1 &&
            t.wg_per_queue <= 65536 && t.lag_f >= 1 && t.lag_s > t.lag_f && t.lag_s <= 64;
@@ -284,6 +285,7 @@ hog_tuning default_tuning(int, int, int, int n, int) {
     hog_tuning t{};
     // parallel NMS rounds: small batches leave most of the GPU to them
     t.nms_rounds = n <= 2 ? 8 : n <= 8 ? 5 : 3;
+    t.score_rows = 0;   // by batch size: small items when the batch does not fill the GPU
     t.fused = 0;
     t.queues = 8;
     t.wg_per_queue = 32;
@@ -380,7 +382,7 @@ int nms_chain(const Plan& P, int m, const FrameBufs& b, const hog_params* prm, i
 
 // histograms -> features -> scores -> NMS for frames lo .. lo + m - 1
 int staged_chain(const Plan& P, int m, const FrameBufs& b, long long fstride, int pitch, const hog_params* prm,
-                 const float* bias, int cap, int rounds, void* ws, hipStream_t s) {
+                 const float* bias, int cap, int rounds, int score_rows, void* ws, hipStream_t s) {
     const LevelTable& T = P.T;
     const bool multi = P.groups > 1;
     HOG_TRY(timed("hist", s, [&] {
@@ -388,8 +390,9 @@ int staged_chain(const Plan& P, int m, const FrameBufs& b, long long fstride, in
     }));
     HOG_TRY(timed("feat", s, [&] { return launch_feat(T, m, b.hist, b.feat, nullptr, s); }));
     HOG_TRY(timed("score", s, [&] {
+        const int rows = score_rows ? score_rows : score_rows_auto(T, m, P.nf, compute_units());
         return launch_score(T, m, b.feat, at<float4>(ws, P.o_bpack), bias, P.nf, prm->thresh, nullptr, b.keys, multi,
-                            s);
+                            rows, s);
     }));
     return nms_chain(P, m, b, prm, cap, nullptr, rounds, ws, s);
 }
@@ -427,7 +430,7 @@ int detect_sequence(const Plan& P, const hog_params* prm, const uint8_t* frames,
     const int parts = std::min(std::max(tune.split, 1), P.n);
     if (parts == 1)
         return staged_chain(P, P.n, frame_bufs(P, ws, frames, fstride, dets, cap, n_dets, 0), fstride, pitch, prm,
-                            bias, cap, tune.nms_rounds, ws, s);
+                            bias, cap, tune.nms_rounds, tune.score_rows, ws, s);
     // the frames in `parts` groups on forked streams: one group's NMS
     // overlaps another's histograms and scores
     SplitRes* r = nullptr;
@@ -439,7 +442,7 @@ int detect_sequence(const Plan& P, const hog_params* prm, const uint8_t* frames,
     for (int j = 0; j < parts && st == HOG_OK; ++j) {
         const int lo = (int)((long long)j * P.n / parts), hi = (int)((long long)(j + 1) * P.n / parts);
         st = staged_chain(P, hi - lo, frame_bufs(P, ws, frames, fstride, dets, cap, n_dets, lo), fstride, pitch,
-                          prm, bias, cap, tune.nms_rounds, ws, j == 0 ? s : r->st[j - 1]);
+                          prm, bias, cap, tune.nms_rounds, tune.score_rows, ws, j == 0 ? s : r->st[j - 1]);
     }
     // join (also after an error, so that no forked stream is left behind a capture)
     for (int j = 1; j < parts; ++j) {
@@ -545,7 +548,7 @@ int hog_scores(const uint8_t* frame, int h, int w, int pitch, int upsample, cons
     HOG_TRY(run_pixels(P, frame, 0, pitch, ws, nullptr, filters, s, false));
     return timed("score", s, [&] {
         return launch_score(P.T, 1, at<float>(ws, P.o_feat), at<float4>(ws, P.o_bpack), bias, nf, 0.f, scores,
-                            nullptr, false, s);
+                            nullptr, false, score_rows_auto(P.T, 1, nf, compute_units()), s);
     });
 }
 
@@ -654,9 +657,12 @@ int hog_autotune(const hog_params* prm, const uint8_t* frames, int n, int h, int
     for (int sp : {1, 2, 4}) {
         if (sp > n) break;
         for (int nr : {2, 4, 8}) {
-            cand.push_back(default_tuning(h, w, prm->upsample, n, nf));
-            cand.back().split = sp;
-            cand.back().nms_rounds = nr;
+            for (int rows : {SCORE_SMALL_ROWS, ROWS_PER_ITEM}) {
+                cand.push_back(default_tuning(h, w, prm->upsample, n, nf));
+                cand.back().split = sp;
+                cand.back().nms_rounds = nr;
+                cand.back().score_rows = rows;
+            }
         }
     }
     const int lags[4][2] = {{1, 2}, {1, 3}, {2, 3}, {2, 4}};
@@ -787,7 +793,7 @@ int hog_topk_windows(const uint8_t* frames, int n, int h, int w, int pitch, int6
     HOG_TRY(run_pixels(P, frames, frame_stride, pitch, ws, nullptr, filters, s, false));
     HOG_TRY(timed("score", s, [&] {
         return launch_score(P.T, n, at<float>(ws, P.o_feat), at<float4>(ws, P.o_bpack), bias, nf, 0.f,
-                            at<float>(ws, P.o_dense), nullptr, false, s);
+                            at<float>(ws, P.o_dense), nullptr, false, score_rows_auto(P.T, n, nf, compute_units()), s);
     }));
     return timed("topk", s, [&] {
         return launch_topk(P.T, n, at<float>(ws, P.o_dense), P.T.dense_frame, nf, k, windows, scores, s);

@@ -47,6 +47,7 @@ constexpr int SC_NT = 3;                         // N tiles of 16 on the matrix 
 constexpr int SC_PSTR = 52;                      // floats per row of a wave's partial-product tile
 constexpr int SCORE_THREADS = 1024;
 constexpr int ROWS_PER_ITEM = SCORE_THREADS / 64;   // window rows per scoring workgroup item
+constexpr int SCORE_SMALL_ROWS = 4;                 // rows per item for batches too small to fill the GPU
 constexpr int BPACK_MFMA = SC_KC * SC_NT * 64;      // float4 B operands of the matrix-core columns
 constexpr int BPACK_XTRA = SC_KC * 4 * 2;           // float4 weights of the two vector-ALU columns
 constexpr int BPACK_PER_GROUP = BPACK_MFMA + BPACK_XTRA;   // 64,000 bytes per filter group
@@ -142,9 +143,10 @@ hipError_t launch_fused(const LevelTable& T, int n, const FusedCfg& cfg, const u
                         int pitch, const int4* taps, float* hist, float* feat, const float4* bpack,
                         const float* bias, int nf, float thresh, unsigned long long* poskey, bool atomic_key,
                         unsigned* sync, hipStream_t s);
+int score_rows_auto(const LevelTable& T, int n, int nf, int cus);
 hipError_t launch_score(const LevelTable& T, int n, const float* feat, const float4* bpack,
                         const float* bias, int nf, float thresh, float* dense,
-                        unsigned long long* poskey, bool atomic_key, hipStream_t s);
+                        unsigned long long* poskey, bool atomic_key, int rows, hipStream_t s);
 // NMS records hold 32-bit position indices when a frame has 65536 window
 // positions or more, else 16-bit ones.
 inline bool nms_wide_lists(long long positions) { return positions > 65535; }

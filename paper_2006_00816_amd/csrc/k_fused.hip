@@ -113,9 +113,9 @@ __global__ __launch_bounds__(SCORE_THREADS) void hog_fused_kernel(
             const int frame = q + Q * jf;
             wait_count<LOCAL>(fdone + frame, waves * nF, err, spin_limit, tid);
             const int grp = o / T.ts_total, it = o % T.ts_total;
-            load_bpack(sm.score, bpack, grp, tid);
+            load_bpack<ROWS_PER_ITEM>(sm.score, bpack, grp, tid);
             __syncthreads();
-            score_item(T, frame, grp, it, sm.score, sm.score.P[tid >> 6], feat, nf, bias, thresh, nullptr, poskey,
+            score_item<ROWS_PER_ITEM>(T, frame, grp, it, sm.score, sm.score.P[tid >> 6], feat, nf, bias, thresh, nullptr, poskey,
                        atomic_key, tid);
             wave_done<LOCAL>(sdone + frame, tid);
         } else if (o < nS + nF) {

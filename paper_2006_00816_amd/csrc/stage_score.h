@@ -8,16 +8,21 @@ namespace hog {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-// LDS of one scoring item: the filter group's packed B (62.5 KB) and, per
-// wave, the partial products of one M tile (3.25 KB).
-struct ScoreSmem {
+// LDS of one scoring item of ROWS window rows (one wave each): the filter
+// group's packed B (62.5 KB) and, per wave, the partial products of one M
+// tile (3.25 KB).
+template <int ROWS>
+struct ScoreSmemT {
     float4 B[BPACK_PER_GROUP];
-    float P[ROWS_PER_ITEM][16 * SC_PSTR];
+    float P[ROWS][16 * SC_PSTR];
 };
+using ScoreSmem = ScoreSmemT<ROWS_PER_ITEM>;
 
-__device__ __forceinline__ void load_bpack(ScoreSmem& sm, const float4* __restrict__ bpack, int grp, int tid) {
+template <int ROWS>
+__device__ __forceinline__ void load_bpack(ScoreSmemT<ROWS>& sm, const float4* __restrict__ bpack, int grp,
+                                           int tid) {
     const float4* __restrict__ g = bpack + (long long)grp * BPACK_PER_GROUP;
-    for (int e = tid; e < BPACK_PER_GROUP; e += SCORE_THREADS) sm.B[e] = g[e];
+    for (int e = tid; e < BPACK_PER_GROUP; e += ROWS * 64) sm.B[e] = g[e];
 }
 
 // Orders a wave's LDS accesses on either side (LDS operations of one wave
@@ -48,9 +53,9 @@ __device__ __forceinline__ void wave_lds_order() {
 // and, per window position, the best candidate key over the group's
 // filters (0 if no filter's score exceeds the threshold), stored or merged
 // with atomic max.
-template <int NT, bool XTRA>
+template <int NT, bool XTRA, int ROWS>
 __device__ __forceinline__ void score_row(const DevLevel& L, int k, int r, const float* __restrict__ Ffr,
-                                          const ScoreSmem& sm, float* __restrict__ ring, int grp, int nf,
+                                          const ScoreSmemT<ROWS>& sm, float* __restrict__ ring, int grp, int nf,
                                           const float* __restrict__ bias, float thresh, float* __restrict__ Dfr,
                                           unsigned long long* __restrict__ PKfr, int atomic_key, int lane) {
     const int g4 = lane >> 4, j = lane & 15;
@@ -177,14 +182,16 @@ __device__ __forceinline__ void score_row(const DevLevel& L, int k, int r, const
     }
 }
 
-// One scoring item: window rows q = ROWS_PER_ITEM * item + wave of the
-// frame's list of rows (levels in order), filter group grp; sm.B holds the
-// group's B.  Waves past the last row do nothing.
-__device__ __forceinline__ void score_item(const LevelTable& T, int frame, int grp, int item, const ScoreSmem& sm,
+// One scoring item: window rows q = ROWS * item + wave of the frame's list
+// of rows (levels in order), filter group grp; sm.B holds the group's B.
+// Waves past the last row do nothing.
+template <int ROWS>
+__device__ __forceinline__ void score_item(const LevelTable& T, int frame, int grp, int item,
+                                           const ScoreSmemT<ROWS>& sm,
                                            float* __restrict__ ring, const float* __restrict__ feat, int nf,
                                            const float* __restrict__ bias, float thresh, float* __restrict__ dense,
                                            unsigned long long* __restrict__ poskey, int atomic_key, int tid) {
-    const int q = item * ROWS_PER_ITEM + (tid >> 6);
+    const int q = item * ROWS + (tid >> 6);
     if (q >= T.rows_total) return;
     const int k = HOG_FIND_LEVEL(T, q, row_off);
     const DevLevel& L = T.L[k];
@@ -195,13 +202,13 @@ __device__ __forceinline__ void score_item(const LevelTable& T, int frame, int g
     const int fg = min(FGROUP, nf - grp * FGROUP);
     const int lane = tid & 63;
     if (fg == 5)
-        score_row<3, true>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane);
+        score_row<3, true, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane);
     else if (fg == 4)
-        score_row<3, false>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane);
+        score_row<3, false, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane);
     else if (fg >= 2)
-        score_row<2, false>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane);
+        score_row<2, false, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane);
     else
-        score_row<1, false>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane);
+        score_row<1, false, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane);
 }
 
 }  // namespace hog

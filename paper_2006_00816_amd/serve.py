@@ -56,7 +56,7 @@ class _Slot:
 
 
 class HogServer:
-    def __init__(self, W: torch.Tensor, b: torch.Tensor, shapes, max_batch: int = 16, slots: int = 3,
+    def __init__(self, W: torch.Tensor, b: torch.Tensor, shapes, max_batch: int = 16, slots: int = 4,
                  cap: int = 256, thresh: float = 0.0, iou: float = 0.5, device="cuda"):
         self.W, self.b = W, b
         self.max_batch, self.cap, self.thresh, self.iou = max_batch, cap, thresh, iou
@@ -145,7 +145,7 @@ def run_stream(server: HogServer, frames, shapes, arrivals):
     return sorted(server.completed, key=lambda r: r.rid)
 
 
-def served_stream(rate: float, seconds: float, W, b, pools_pinned, seed: int = 2, max_batch: int = 16, slots: int = 3):
+def served_stream(rate: float, seconds: float, W, b, pools_pinned, seed: int = 2, max_batch: int = 16, slots: int = 4):
     t, res = synth.poisson_arrivals(seed, rate, seconds)
     shapes = [tuple(r) for r in res]
     idx = collections.Counter()

@@ -14,7 +14,7 @@ from test_gpu_parity import H, cu  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 
-STAGED = {"fused": 0, "queues": 8, "wg_per_queue": 32, "lag_f": 1, "lag_s": 2, "split": 1, "nms_rounds": 3}
+STAGED = {"fused": 0, "queues": 8, "wg_per_queue": 32, "lag_f": 1, "lag_s": 2, "split": 1, "nms_rounds": 3, "score_rows": 0}
 
 
 def _run(H, fr, W, b, tuning, upsample=1):
@@ -41,7 +41,7 @@ def test_fused_equals_staged_clip(H, queues, wg, lag_f, lag_s):
     fr, W, b = cu(wl.frames), cu(wl.W), cu(wl.b)
     print(f"fused q={queues} wg={wg} lags=({lag_f},{lag_s}) n=13", flush=True)
     ref = _run(H, fr, W, b, STAGED)
-    got = _run(H, fr, W, b, {"fused": 1, "queues": queues, "wg_per_queue": wg, "lag_f": lag_f, "lag_s": lag_s, "split": 1, "nms_rounds": 3})
+    got = _run(H, fr, W, b, {"fused": 1, "queues": queues, "wg_per_queue": wg, "lag_f": lag_f, "lag_s": lag_s, "split": 1, "nms_rounds": 3, "score_rows": 0})
     _assert_same(got, ref, 13)
     assert sum(ref[1]) > 0
 
@@ -62,17 +62,18 @@ def test_fused_equals_staged_shapes(H, nf, shape, upsample, n):
     W, b = cu(W), cu(b)
     print(f"fused nf={nf} {h}x{w} u={upsample} n={n}", flush=True)
     ref = _run(H, fr, W, b, STAGED, upsample)
-    got = _run(H, fr, W, b, {"fused": 1, "queues": 8, "wg_per_queue": 32, "lag_f": 1, "lag_s": 2, "split": 1, "nms_rounds": 3}, upsample)
+    got = _run(H, fr, W, b, {"fused": 1, "queues": 8, "wg_per_queue": 32, "lag_f": 1, "lag_s": 2, "split": 1, "nms_rounds": 3, "score_rows": 0}, upsample)
     _assert_same(got, ref, n)
 
 
-@pytest.mark.parametrize("split,n,rounds", [(2, 13, 3), (3, 13, 0), (4, 5, 8), (4, 3, 16), (1, 6, 0), (1, 6, 16)])
-def test_split_and_rounds_equal_staged(H, split, n, rounds):
+@pytest.mark.parametrize("split,n,rounds,rows", [(2, 13, 3, 16), (3, 13, 0, 4), (4, 5, 8, 16), (4, 3, 16, 4),
+                                                (1, 6, 0, 4), (1, 6, 16, 16), (1, 1, 3, 4)])
+def test_split_rounds_rows_equal_staged(H, split, n, rounds, rows):
     wl = synth.config1(seed=24, n=n)
     fr, W, b = cu(wl.frames), cu(wl.W), cu(wl.b)
-    print(f"split={split} n={n} nms_rounds={rounds}", flush=True)
-    ref = _run(H, fr, W, b, STAGED)
-    got = _run(H, fr, W, b, {**STAGED, "split": split, "nms_rounds": rounds})
+    print(f"split={split} n={n} nms_rounds={rounds} score_rows={rows}", flush=True)
+    ref = _run(H, fr, W, b, {**STAGED, "score_rows": 16})
+    got = _run(H, fr, W, b, {**STAGED, "split": split, "nms_rounds": rounds, "score_rows": rows})
     _assert_same(got, ref, n)
 
 
@@ -99,7 +100,7 @@ def test_fused_graph_replay(H):
     wl = synth.config1(seed=22, n=16)
     fr, W, b = cu(wl.frames), cu(wl.W), cu(wl.b)
     ref = _run(H, fr, W, b, STAGED)
-    H.tuning_set(480, 640, 1, 16, 5, {"fused": 1, "queues": 8, "wg_per_queue": 32, "lag_f": 1, "lag_s": 2, "split": 1, "nms_rounds": 3})
+    H.tuning_set(480, 640, 1, 16, 5, {"fused": 1, "queues": 8, "wg_per_queue": 32, "lag_f": 1, "lag_s": 2, "split": 1, "nms_rounds": 3, "score_rows": 0})
     try:
         g = H.DetectGraph(fr, W, b)
         other = cu(synth.config0(5).frames[0])
