@@ -21,6 +21,7 @@ from __future__ import annotations
 import argparse
 import collections
 import dataclasses
+import gc
 import json
 import time
 
@@ -73,11 +74,19 @@ class HogServer:
                     fr = slot.frames[:n * h * w].view(n, h, w)
                     slot.graphs[(h, w, n)] = hog355.BoundGraph(fr, W, b, slot.dets[:n], slot.n_dets[:n], slot.ws,
                                                                thresh, iou, 1, slot.stream)
-        # one replay of every graph (on blank frames) before serving, so
-        # that no request pays for a first launch
+        # one replay of every graph (on blank frames) and one pass of every
+        # copy and event on each slot's stream before serving, so that no
+        # request pays for a first use
+        blank = torch.zeros(max_bytes, dtype=torch.uint8).pin_memory()
         for slot in self.slots:
-            for g in slot.graphs.values():
-                g.launch(slot.stream)
+            with torch.cuda.stream(slot.stream):
+                slot.frames[:max_bytes].copy_(blank, non_blocking=True)
+                for g in slot.graphs.values():
+                    g.launch(slot.stream)
+                slot.h_dets.copy_(slot.dets, non_blocking=True)
+                slot.h_n.copy_(slot.n_dets, non_blocking=True)
+                slot.event.record(slot.stream)
+            slot.event.query()
         torch.cuda.synchronize()
         self.pending = collections.OrderedDict((tuple(s), collections.deque()) for s in shapes)
         self.completed = []
@@ -131,17 +140,26 @@ class HogServer:
 
 def run_stream(server: HogServer, frames, shapes, arrivals):
     """Replay requests at their arrival times (seconds from start) and wait
-    for all of them; returns the completed requests."""
-    t0 = time.perf_counter()
-    now = lambda: time.perf_counter() - t0
-    i = 0
-    n = len(arrivals)
-    while i < n or server.pump(now) or any(server.pending.values()):
-        t = now()
-        while i < n and arrivals[i] <= t:
-            server.submit(Request(i, shapes[i], frames[i], float(arrivals[i])))
-            i += 1
-        server.pump(now)
+    for all of them; returns the completed requests.  The garbage
+    collector is paused while serving (a full collection over the request
+    objects stalls the loop for tens of milliseconds)."""
+    gc.collect()
+    paused = gc.isenabled()
+    gc.disable()
+    try:
+        t0 = time.perf_counter()
+        now = lambda: time.perf_counter() - t0
+        i = 0
+        n = len(arrivals)
+        while i < n or server.pump(now) or any(server.pending.values()):
+            t = now()
+            while i < n and arrivals[i] <= t:
+                server.submit(Request(i, shapes[i], frames[i], float(arrivals[i])))
+                i += 1
+            server.pump(now)
+    finally:
+        if paused:
+            gc.enable()
     return sorted(server.completed, key=lambda r: r.rid)
 
 
