@@ -40,16 +40,27 @@ __host__ __device__ constexpr int qoff(int ty, int tx) {
 template <int Q, bool CHECK>
 __device__ __forceinline__ void quad_votes(const int* __restrict__ sV, int lb, unsigned long long* __restrict__ h00,
                                            int ylb, int xlb, int ylim, int xlim) {
+    // the two pixel rows 2Q, 2Q + 1 of the quad block and their central
+    // differences need level rows 2Q .. 2Q + 3 (tile coordinates, one-pixel
+    // halo), columns 0 .. 9 of the middle two and 1 .. 8 of the outer two:
+    // 36 LDS reads for 16 pixels, all issued before the first use
+    int V[4][10];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < 10; ++c)
+            V[i][c] = ((i == 0 || i == 3) && (c == 0 || c == 9)) ? 0 : sV[lb + qoff(2 * Q + i, c)];
 #pragma unroll
     for (int oo = 0; oo < 16; ++oo) {
         const int o = 16 * Q + oo;
         const int oy = o >> 3, ox = o & 7;
+        const int di = oy - 2 * Q;
         if (CHECK) {
             const int yl = ylb + oy, xl = xlb + ox;
             if (yl < 1 || yl > ylim || xl < 1 || xl > xlim) continue;
         }
-        const int gx = sV[lb + qoff(oy + 1, ox + 2)] - sV[lb + qoff(oy + 1, ox)];
-        const int gy = sV[lb + qoff(oy + 2, ox + 1)] - sV[lb + qoff(oy, ox + 1)];
+        const int gx = V[di + 1][ox + 2] - V[di + 1][ox];
+        const int gy = V[di + 2][ox + 1] - V[di][ox + 1];
         if ((gx | gy) == 0) continue;
         const int bin = orient_bin(gx, gy);
         const float fx = (float)gx, fy = (float)gy;
