@@ -158,3 +158,33 @@ def test_pixel_gradient_matches_finite_differences(H):
         if checked == 64:
             break
     assert checked == 64
+
+
+def test_config4_frame_topk_and_pixel_gradient(H):
+    """One 1920x1080 frame of the large-batch workload on the pyramid from
+    2x (19 levels, 32-bit NMS records): top-10 windows and the pixel
+    gradient of their summed scores against the oracle at every pixel."""
+    wl = synth.config4(seed=4, n=1)
+    frame, W, b, u = wl.frames[0], wl.W, wl.b, 2
+    print("config-4 frame 1920x1080 u=2", flush=True)
+    win, sc = H.topk_windows(cu(frame[None]), cu(W), cu(b), 10, u)
+    ow = oracle.top_windows(frame, W, b, 12, u)
+    got = [tuple(x) for x in win.cpu().numpy()[0][:, 1:].tolist()]
+    want = [(int(r["f"]), int(r["k"]), int(r["r"]), int(r["c"])) for r in ow[:10]]
+    s = ow["score"]
+    near = [i for i in range(11) if abs(s[i] - s[i + 1]) < 1e-4]
+    amb = set(near) | set(i + 1 for i in near)
+    for i in range(10):
+        if got[i] != want[i]:
+            assert i in amb, (i, got, want)
+    assert np.allclose(sc.cpu().numpy()[0], s[:10], rtol=1e-5, atol=2e-5)
+    recs = win.cpu().numpy()[0]
+    w10 = np.zeros(10, oracle.CAND_DTYPE)
+    w10["f"], w10["k"], w10["r"], w10["c"] = recs[:, 1], recs[:, 2], recs[:, 3], recs[:, 4]
+    dpix = H.pixel_gradient(cu(frame[None]), cu(W), win.reshape(-1, 5).contiguous(),
+                            torch.ones(10, device="cuda"), u)[0].cpu().numpy().astype(np.float64)
+    g, _ = oracle.topk_pixel_grad(frame, W, b, 10, u, windows=w10)
+    scale = np.abs(g).max()
+    assert scale > 0
+    err = np.abs(dpix - g)
+    assert np.all(err <= 1e-4 * np.abs(g) + 1e-5 * scale), (float(err.max()), scale)
