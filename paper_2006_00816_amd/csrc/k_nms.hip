@@ -239,14 +239,17 @@ __global__ __launch_bounds__(256) void hog_nms_round_kernel(
                 __hip_atomic_load(st + (in ? R.at(j) : (unsigned)p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             sy[j] = in ? w : (unsigned char)DROPPED;
         }
+        bool kept = false, und = false;
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
-            if (sy[j] == KEPT) {
-                __hip_atomic_store(st + p, (unsigned char)DROPPED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                return;
-            }
-            if (sy[j] == UNDECIDED) blocked = true;
+            kept |= sy[j] == KEPT;
+            und |= sy[j] == UNDECIDED;
         }
+        if (kept) {
+            __hip_atomic_store(st + p, (unsigned char)DROPPED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+        blocked |= und;
     }
     if (!blocked) __hip_atomic_store(st + p, (unsigned char)KEPT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -314,11 +317,15 @@ __device__ __forceinline__ unsigned decide_rec(const unsigned* S, const E* rec, 
                 const unsigned w = state_of<G>(S, in ? (int)R.at(h + j) : 0);
                 sy[j] = in ? w : (unsigned)DROPPED;
             }
+            // branch-free over the 16 entries, one branch per block
+            bool kept = false, und = false;
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
-                if (sy[j] == KEPT) return DROPPED;
-                if (sy[j] == UNDECIDED) blocked = true;
+                kept |= sy[j] == KEPT;
+                und |= sy[j] == UNDECIDED;
             }
+            if (kept) return DROPPED;
+            blocked |= und;
         }
     }
     return blocked ? UNDECIDED : KEPT;
