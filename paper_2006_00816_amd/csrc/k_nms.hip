@@ -79,6 +79,17 @@ __device__ __forceinline__ bool conflicts(const Box& X, int AX, const int2& ry, 
     return (long long)I * iden > inum * (long long)U;
 }
 
+// The same test without branches (for masks over several neighbours).
+__device__ __forceinline__ bool conflicts_bf(const Box& X, int AX, const int2& ry, const int2& cx, long long inum,
+                                             long long iden) {
+    const int iw = min(X.x1, cx.y) - max(X.x0, cx.x);
+    const int ih = min(X.y1, ry.y) - max(X.y0, ry.x);
+    const int I = max(iw, 0) * max(ih, 0);
+    const int U = AX + (cx.y - cx.x) * (ry.y - ry.x) - I;
+    const bool over = (inum == 1 && iden == 2) ? 2 * I > U : (long long)I * iden > inum * (long long)U;
+    return iw > 0 && ih > 0 && over;
+}
+
 __device__ __forceinline__ void decode(unsigned long long key, int& f, int& k, int& r, int& c) {
     const unsigned int pk = ~(unsigned int)(key & 0xffffffffu);
     f = pk >> 27;
@@ -180,12 +191,17 @@ __global__ __launch_bounds__(256) void hog_nms_edges_kernel(
                         kk[q] = keys[base + c2];
                         bc[q] = boxes[M.box_c + c2];
                     }
+                    // conflicting better-ranked columns as a bit mask
+                    // (branch-free), then the appends
+                    unsigned hits = 0;
 #pragma unroll
                     for (int q = 0; q < 8; ++q) {
-                        const int c2 = c0 + q;
-                        if (c2 > R.c_hi) break;
-                        if (kk[q] <= kx) continue;          // worse rank, itself, or not a candidate
-                        if (!conflicts(X, AX, ry, bc[q], inum, iden)) continue;
+                        const bool hit = c0 + q <= R.c_hi && kk[q] > kx && conflicts_bf(X, AX, ry, bc[q], inum, iden);
+                        hits |= (unsigned)hit << q;
+                    }
+                    while (hits) {
+                        const int c2 = c0 + __builtin_ctz(hits);
+                        hits &= hits - 1;
                         const int e = 1 + cnt;
                         if (e < CH) {
                             stage_put<E>(st0, t, e, (unsigned)(base + c2));
