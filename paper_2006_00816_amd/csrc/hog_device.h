@@ -69,25 +69,28 @@ static __device__ __noinline__ int orient_bin_f64(int gxi, int gyi) {
 //
 // Fast path: fold the gradient into the first quadrant (|gx|, |gy|) and
 // count how many of the sector boundaries 10, 30, 50, 70 degrees lie below
-// its angle, from the signs of t_b = |gy| cos b - |gx| sin b; unfold by the
-// signs of gx, gy (an angle of exactly 90 or 270 degrees goes to bin 4 or
-// 13, the first of the two tied directions).  In float32 each t_b carries
-// an error below 2e-7 (|gx| + |gy|); when every |t_b| exceeds 1e-6 (|gx| +
-// |gy|) the signs are exact and the float64 scan above, whose own error is
-// some 1e-16 of the magnitude, picks the same bin.  Otherwise the float64
-// scan itself decides.
+// its angle, from the signs of t_b = |gy| - |gx| tan b (the sign of
+// |gy| cos b - |gx| sin b, as cos b > 0); unfold by the signs of gx, gy (an
+// angle of exactly 90 or 270 degrees goes to bin 4 or 13, the first of the
+// two tied directions).  |gx|, |gy| < 2^24 are exact in float32; each t_b,
+// one fused multiply-add with a rounded tan b, carries an error below
+// 3.3e-7 (|gx| + |gy|).  When every |t_b| exceeds 1e-6 (|gx| + |gy|) the
+// signs are exact and the float64 scan above, whose own error is some
+// 1e-16 of the magnitude, picks the same bin.  Otherwise the float64 scan
+// itself decides.  The unfolding is branch-free.
 static __device__ inline int orient_bin(int gxi, int gyi) {
     const float ax = fabsf((float)gxi), ay = fabsf((float)gyi);
-    const float t0 = fmaf(ay, 0.984807753012f, -ax * 0.173648177667f);
-    const float t1 = fmaf(ay, 0.866025403784f, -ax * 0.5f);
-    const float t2 = fmaf(ay, 0.642787609687f, -ax * 0.766044443119f);
-    const float t3 = fmaf(ay, 0.342020143326f, -ax * 0.939692620786f);
+    const float t0 = fmaf(-ax, 0.176326980708f, ay);   // tan 10
+    const float t1 = fmaf(-ax, 0.577350269190f, ay);   // tan 30
+    const float t2 = fmaf(-ax, 1.191753592594f, ay);   // tan 50
+    const float t3 = fmaf(-ax, 2.747477419455f, ay);   // tan 70
     const float m = fminf(fminf(fabsf(t0), fabsf(t1)), fminf(fabsf(t2), fabsf(t3)));
     if (m <= 1e-6f * (ax + ay)) return orient_bin_f64(gxi, gyi);
     const int j = (t0 > 0.f) + (t1 > 0.f) + (t2 > 0.f) + (t3 > 0.f);
     const bool upper = (gyi > 0) || (gyi == 0 && gxi > 0);
-    if (upper) return gxi >= 0 ? j : NORIENT - j;
-    return gxi <= 0 ? NORIENT + j : (NBINS - j) % NBINS;
+    const int b_up = gxi >= 0 ? j : NORIENT - j;
+    const int b_lo = gxi <= 0 ? NORIENT + j : (j == 0 ? 0 : NBINS - j);
+    return upper ? b_up : b_lo;
 }
 
 // Fixed-point resampling tap: returns {i0, i1, a8, 0} for output index i
