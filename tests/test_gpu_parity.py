@@ -265,3 +265,20 @@ def test_detect_large_frame_nms_states_in_global_memory(H):
     print(f"4096x4096: {n} kept", flush=True)
     assert n > 0
     assert_nms_function(H, frame, Wn, bn, 1, dets, n)
+
+
+@pytest.mark.parametrize("iou,thresh", [(0.6, 0.0), (0.75, 0.5), (0.95, -0.25), (0.5, 1.0)])
+def test_detect_iou_and_threshold(H, iou, thresh):
+    """NMS thresholds above 1/2 (the exact test I * den > num * U on the
+    binary fraction of the float32 iou) and other score thresholds: the GPU
+    result equals the oracle's NMS over the GPU's candidates."""
+    frame, u = case_frame("c1")
+    Wn, bn = synth.filters(range(101, 106))
+    print(f"detect iou={iou} thresh={thresh}", flush=True)
+    dets, n = H.detect(cu(frame), cu(Wn), cu(bn), thresh, iou, u)
+    cg = gpu_candidates(H, frame, Wn, bn, u, thresh)
+    kept = oracle.nms(cg, float(np.float32(iou)))
+    assert n == len(kept), (n, len(kept))
+    m = min(len(dets), len(kept))
+    assert det_key(dets) == cand_key(kept[:m])
+    assert np.array_equal(dets["score"], kept["score"][:m].astype(np.float32))
