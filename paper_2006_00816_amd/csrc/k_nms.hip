@@ -176,21 +176,20 @@ __global__ __launch_bounds__(256) void hog_nms_edges_kernel(
         for (int k2 = L.nms_klo; k2 <= L.nms_khi; ++k2) {
             const DevLevel& M = T.L[k2];
             const Range R = neighbour_range(M, X, AX);
-            for (int r2 = R.r_lo; r2 <= R.r_hi; ++r2) {
-                const int2 ry = boxes[M.box_r + r2];
-                if (min(X.y1, ry.y) <= max(X.y0, ry.x)) continue;
-                const int base = M.pos_off + r2 * M.cols;
-                // 8 columns at a time, their key and box loads in flight
-                // together (columns past the range re-read the last one)
-                for (int c0 = R.c_lo; c0 <= R.c_hi; c0 += 8) {
-                    unsigned long long kk[8];
-                    int2 bc[8];
+            // 8 columns at a time: their box edges once, then each row's 8
+            // keys in flight together (columns past the range re-read the
+            // last one)
+            for (int c0 = R.c_lo; c0 <= R.c_hi; c0 += 8) {
+                int2 bc[8];
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        const int c2 = min(c0 + q, R.c_hi);
-                        kk[q] = keys[base + c2];
-                        bc[q] = boxes[M.box_c + c2];
-                    }
+                for (int q = 0; q < 8; ++q) bc[q] = boxes[M.box_c + min(c0 + q, R.c_hi)];
+                for (int r2 = R.r_lo; r2 <= R.r_hi; ++r2) {
+                    const int2 ry = boxes[M.box_r + r2];
+                    if (min(X.y1, ry.y) <= max(X.y0, ry.x)) continue;
+                    const int base = M.pos_off + r2 * M.cols;
+                    unsigned long long kk[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) kk[q] = keys[base + min(c0 + q, R.c_hi)];
                     // conflicting better-ranked columns as a bit mask
                     // (branch-free), then the appends
                     unsigned hits = 0;
