@@ -86,12 +86,18 @@ __device__ __forceinline__ void score_row(const DevLevel& L, int k, int r, const
         float4 av[SC_KC];
         av[0] = load_a(0);
         av[1] = load_a(1);
+        // B of chunk kc + 1 is read from LDS while chunk kc computes
+        float4 bb[2][NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) bb[0][nt] = sm.B[nt * 64 + lane];
 #pragma unroll
         for (int kc = 0; kc < SC_KC; ++kc) {
             if (kc + 2 < SC_KC) av[kc + 2] = load_a(kc + 2);
-            float4 b[NT];
+            if (kc + 1 < SC_KC) {
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) b[nt] = sm.B[(kc * SC_NT + nt) * 64 + lane];
+                for (int nt = 0; nt < NT; ++nt) bb[(kc + 1) & 1][nt] = sm.B[((kc + 1) * SC_NT + nt) * 64 + lane];
+            }
+            const float4* b = bb[kc & 1];
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kc].x, b[nt].x, acc[nt], 0, 0, 0);
 #pragma unroll
