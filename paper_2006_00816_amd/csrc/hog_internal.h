@@ -44,7 +44,8 @@ constexpr int FGROUP = 5;
 constexpr int SC_K = WIN * FPAD;                 // 320
 constexpr int SC_KC = SC_K / 16;                 // 20 chunks of 16 K values
 constexpr int SC_NT = 3;                         // N tiles of 16 on the matrix cores
-constexpr int SC_PSTR = 52;                      // floats per row of a wave's partial-product tile
+constexpr int SC_RSTR = 20;                      // floats per column of a wave's partial-product tile (16 cells + pad)
+constexpr int SC_RING = 50 * SC_RSTR;             // floats of that tile: 50 columns (f, dc)
 constexpr int SCORE_THREADS = 1024;
 constexpr int ROWS_PER_ITEM = SCORE_THREADS / 64;   // window rows per scoring workgroup item
 constexpr int SCORE_SMALL_ROWS = 4;                 // rows per item for batches too small to fill the GPU

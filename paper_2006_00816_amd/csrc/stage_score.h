@@ -10,11 +10,11 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 // LDS of one scoring item of ROWS window rows (one wave each): the filter
 // group's packed B (62.5 KB) and, per wave, the partial products of one M
-// tile (3.25 KB).
+// tile stored column-major, P[(f, dc)][x] (4 KB).
 template <int ROWS>
 struct ScoreSmemT {
     float4 B[BPACK_PER_GROUP];
-    float P[ROWS][16 * SC_PSTR];
+    float P[ROWS][SC_RING];
 };
 using ScoreSmem = ScoreSmemT<ROWS_PER_ITEM>;
 
@@ -124,30 +124,36 @@ __device__ __forceinline__ void score_row(const DevLevel& L, int k, int r, const
             x8 += __shfl_xor(x8, 32, 64);
             x9 += __shfl_xor(x9, 32, 64);
         }
-        // lane (g4, j) holds P[16 t + 4 g4 + i][16 nt + j]
+        // lane (g4, j) holds P[16 t + 4 g4 + i][16 nt + j], i = 0..3: one
+        // 16-byte store per N tile into the column-major tile
         wave_lds_order();
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) ring[(4 * g4 + i) * SC_PSTR + 16 * nt + j] = acc[nt][i];
+            *reinterpret_cast<float4*>(ring + (16 * nt + j) * SC_RSTR + 4 * g4) =
+                make_float4(acc[nt][0], acc[nt][1], acc[nt][2], acc[nt][3]);
         if (XTRA && g4 == 0) {
-            ring[j * SC_PSTR + 48] = x8;
-            ring[j * SC_PSTR + 49] = x9;
+            ring[48 * SC_RSTR + j] = x8;
+            ring[49 * SC_RSTR + j] = x9;
         }
         wave_lds_order();
 
+        // Window c = 16 t - 9 + j takes P[c + dc] for dc >= 9 - j (cells of
+        // this tile) and window c + 16 starts its carry with the cells
+        // 7 + j + dc <= 15 of this tile; both are cell (7 + j + dc) mod 16,
+        // so one read per dc, added to one sum or the other (zeros keep
+        // the order of the additions).
         float s0 = carry0, s1 = carry1, n0 = 0.f, n1 = 0.f;
 #pragma unroll
         for (int dc = 0; dc < WIN; ++dc) {
-            if (dc >= WIN - 1 - j) {
-                const float* p = ring + (j - (WIN - 1) + dc) * SC_PSTR + dc;
-                s0 += p[WIN * g4];
-                if (f1ok) s1 += p[WIN * 4];
-            }
-            if (dc <= WIN - 2 - j) {
-                const float* p = ring + (j + 16 - (WIN - 1) + dc) * SC_PSTR + dc;
-                n0 += p[WIN * g4];
-                if (f1ok) n1 += p[WIN * 4];
+            const bool mine = dc >= WIN - 1 - j;
+            const float* p = ring + dc * SC_RSTR + ((j + 7 + dc) & 15);
+            const float v0 = p[WIN * SC_RSTR * g4];
+            s0 += mine ? v0 : 0.f;
+            n0 += mine ? 0.f : v0;
+            if (XTRA) {
+                const float v1 = p[WIN * SC_RSTR * 4];
+                s1 += mine ? v1 : 0.f;
+                n1 += mine ? 0.f : v1;
             }
         }
         carry0 = n0;
