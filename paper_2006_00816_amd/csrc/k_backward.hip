@@ -157,7 +157,7 @@ constexpr int BC = WIN + 2;              // 12 cells
 constexpr int BV = 8 * BC + 8;           // 104 voting pixels
 constexpr int BP = BV + 2;               // 106 level pixels
 constexpr int BWIN_PER_WG = 32;          // windows per workgroup (dW partial per workgroup)
-constexpr int BTHREADS = 256;
+constexpr int BTHREADS = 512;
 
 struct BwdShared {
     int V[BP * BP];                                  // level pixels * 2^16
@@ -196,19 +196,32 @@ __global__ __launch_bounds__(BTHREADS) void hog_backward_kernel(
         }
         for (int e = tid; e < BC * BC * NBINS; e += BTHREADS) sm.hq[e] = 0ull;
         __syncthreads();
-        // level pixels of the region
-        for (int e = tid; e < BP * BP; e += BTHREADS) {
-            const int iy = e / BP, ix = e - iy * BP;
-            const int4 a = sm.ty[iy], b = sm.tx[ix];
-            int v = 0;
-            if ((a.w | b.w) == 0) {
+        // level pixels of the region, 8 per thread at a time with their
+        // frame loads in flight together (taps are clamped to the frame;
+        // a pixel outside the level discards its value)
+        for (int e0 = tid; e0 < BP * BP; e0 += 8 * BTHREADS) {
+            int u00[8], u01[8], u10[8], u11[8], az[8], bz[8], in[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int e = min(e0 + r * BTHREADS, BP * BP - 1);
+                const int iy = e / BP, ix = e - iy * BP;
+                const int4 a = sm.ty[iy], b = sm.tx[ix];
+                in[r] = (a.w | b.w) == 0;
+                az[r] = a.z;
+                bz[r] = b.z;
                 const uint8_t* r0 = U + (long long)a.x * pitch;
                 const uint8_t* r1 = U + (long long)a.y * pitch;
-                const int top = (256 - b.z) * r0[b.x] + b.z * r0[b.y];
-                const int bot = (256 - b.z) * r1[b.x] + b.z * r1[b.y];
-                v = (256 - a.z) * top + a.z * bot;
+                u00[r] = r0[b.x];
+                u01[r] = r0[b.y];
+                u10[r] = r1[b.x];
+                u11[r] = r1[b.y];
             }
-            sm.V[e] = v;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int top = (256 - bz[r]) * u00[r] + bz[r] * u01[r];
+                const int bot = (256 - bz[r]) * u10[r] + bz[r] * u11[r];
+                if (e0 + r * BTHREADS < BP * BP) sm.V[e0 + r * BTHREADS] = in[r] ? (256 - az[r]) * top + az[r] * bot : 0;
+            }
         }
         __syncthreads();
         // gradients, bins and fixed-point votes into the 12 x 12 cells
