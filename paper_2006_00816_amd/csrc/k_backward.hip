@@ -156,7 +156,7 @@ hipError_t launch_hinge(const float* S, const float* y, int n, const float* W, i
 constexpr int BC = WIN + 2;              // 12 cells
 constexpr int BV = 8 * BC + 8;           // 104 voting pixels
 constexpr int BP = BV + 2;               // 106 level pixels
-constexpr int BWIN_PER_WG = 32;          // windows per workgroup (dW partial per workgroup)
+constexpr int BWIN_PER_WG = 16;          // windows per workgroup (dW partial per workgroup)
 constexpr int BTHREADS = 512;
 
 struct BwdShared {
