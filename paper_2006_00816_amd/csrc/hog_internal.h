@@ -49,6 +49,8 @@ constexpr int SC_RING = 50 * SC_RSTR;             // floats of that tile: 50 col
 constexpr int SCORE_THREADS = 1024;
 constexpr int ROWS_PER_ITEM = SCORE_THREADS / 64;   // window rows per scoring workgroup item
 constexpr int SCORE_SMALL_ROWS = 4;                 // rows per item for batches too small to fill the GPU
+constexpr int SCORE_ORDER_MAX = 128;                // slots per frame with a host-chosen dispatch order
+constexpr int SCORE_ORDER_SEARCH = 48;              // slots per frame up to which that order is searched
 constexpr int BPACK_MFMA = SC_KC * SC_NT * 64;      // float4 B operands of the matrix-core columns
 constexpr int BPACK_XTRA = SC_KC * 4 * 2;           // float4 weights of the two vector-ALU columns
 constexpr int BPACK_PER_GROUP = BPACK_MFMA + BPACK_XTRA;   // 64,000 bytes per filter group

@@ -1,6 +1,13 @@
 // Linear window scoring on the matrix cores (Sec. IV-A linear
 // classification; Sec. V-A classifier and detection kernels), one launch
 // over all frames, filter groups and levels.
+#include <algorithm>
+#include <array>
+#include <functional>
+#include <map>
+#include <mutex>
+#include <vector>
+
 #include "stage_score.h"
 
 namespace hog {
@@ -9,25 +16,131 @@ namespace hog {
 // of rows; 16, or 4 for small batches, which then spread over more
 // compute units).  Neighbouring rows read 9 of their 10 feature rows in
 // common, so the items of a frame are placed on one XCD (one L2): the
-// launch is 1-D, and block b runs item (b mod 8) * (blocks / 8) + b / 8.
+// launch is 1-D and block b runs on XCD b mod 8 (blocks are dealt to the
+// XCDs in turn, and each XCD starts its blocks in order).  With 8 or more
+// (frame, group) units, XCD x takes units [x U / 8, (x + 1) U / 8) and
+// runs them slot by slot: block 8 p + x runs slot ord[p / u] of unit
+// p mod u (u units on the XCD), where ord is a dispatch order of the
+// slots chosen on the host (score_order below).  With fewer units, XCD x
+// takes items [x P, (x + 1) P) of the unit-major list (P = blocks / 8).
+struct ScoreOrder {
+    unsigned char s[SCORE_ORDER_MAX];
+};
+
 template <int ROWS>
 __global__ __launch_bounds__(ROWS * 64) void hog_score_kernel(
-    LevelTable T, int groups, int per_frame, int items, const float* __restrict__ feat,
+    LevelTable T, ScoreOrder ord, int groups, int per_frame, int units, const float* __restrict__ feat,
     const float4* __restrict__ bpack, const float* __restrict__ bias, int nf, float thresh,
     float* __restrict__ dense, unsigned long long* __restrict__ poskey, int atomic_key) {
     __shared__ ScoreSmemT<ROWS> sm;
-    const int per = (int)(gridDim.x >> 3);
-    const int item = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
-    if (item >= items) return;
-    const int it = item % per_frame;
-    const int grp = (item / per_frame) % groups;
-    const int frame = item / (per_frame * groups);
+    const int x = (int)(blockIdx.x & 7), p = (int)(blockIdx.x >> 3);
+    int unit, it;
+    if (units >= 8) {
+        const int u0 = (int)((long long)x * units / 8);
+        const int nu = (int)((long long)(x + 1) * units / 8) - u0;
+        it = p / nu;
+        unit = u0 + (p - it * nu);
+        if (it >= per_frame) return;
+        if (per_frame <= SCORE_ORDER_MAX) it = ord.s[it];
+    } else {
+        const int item = x * (int)(gridDim.x >> 3) + p;
+        if (item >= units * per_frame) return;
+        it = item % per_frame;
+        unit = item / per_frame;
+    }
+    const int grp = unit % groups;
+    const int frame = unit / groups;
     const int tid = threadIdx.x;
     load_bpack(sm, bpack, grp, tid);
     __syncthreads();
     score_item<ROWS>(T, frame, grp, it, sm, sm.P[tid >> 6], feat, nf, bias, thresh, dense, poskey, atomic_key,
                      tid);
 }
+
+namespace {
+
+// Estimated duration of each slot of ROWS rows, in wave-tiles of the
+// busiest SIMD (waves w, w + 4, ... of a workgroup share a SIMD and its
+// matrix core), plus the start-up of a workgroup (B to LDS, first loads).
+std::vector<double> slot_costs(const LevelTable& T, int rows, int per_frame) {
+    std::vector<double> c(per_frame, 0.0);
+    for (int s = 0; s < per_frame; ++s) {
+        double simd[4] = {0, 0, 0, 0};
+        for (int w = 0; w < rows; ++w) {
+            const int q = s * rows + w;
+            if (q >= T.rows_total) break;
+            int k = 0;
+            while (k + 1 < T.n && T.L[k + 1].row_off <= q) ++k;
+            simd[w & 3] += (T.L[k].cx + 15) / 16;
+        }
+        c[s] = std::max(std::max(simd[0], simd[1]), std::max(simd[2], simd[3])) + 0.5;
+    }
+    return c;
+}
+
+// Makespan of one XCD: `units` copies of every slot, dispatched slot by
+// slot in the given order, each to the compute unit that frees first.
+double xcd_makespan(const std::vector<double>& cost, const std::vector<int>& order, int units, int cus) {
+    std::vector<double> free_at(cus, 0.0);
+    std::make_heap(free_at.begin(), free_at.end(), std::greater<double>());
+    double end = 0.0;
+    for (int s : order)
+        for (int u = 0; u < units; ++u) {
+            std::pop_heap(free_at.begin(), free_at.end(), std::greater<double>());
+            const double t = free_at.back() + cost[s];
+            free_at.back() = t;
+            std::push_heap(free_at.begin(), free_at.end(), std::greater<double>());
+            end = std::max(end, t);
+        }
+    return end;
+}
+
+std::mutex g_order_mu;
+std::map<std::array<int, 6>, ScoreOrder> g_order;
+
+// Dispatch order of the slots for (level geometry, rows, units per XCD,
+// compute units per XCD): longest first, then improved by moving single
+// slots while the simulated makespan drops.
+ScoreOrder score_order(const LevelTable& T, int rows, int per_frame, int units, int cus_xcd) {
+    const std::array<int, 6> key{T.h, T.w, T.upsample, rows, units, cus_xcd};
+    {
+        std::lock_guard<std::mutex> g(g_order_mu);
+        auto it = g_order.find(key);
+        if (it != g_order.end()) return it->second;
+    }
+    const std::vector<double> cost = slot_costs(T, rows, per_frame);
+    std::vector<int> order(per_frame);
+    for (int i = 0; i < per_frame; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    if (per_frame <= SCORE_ORDER_SEARCH) {
+        double best = xcd_makespan(cost, order, units, cus_xcd);
+        for (int pass = 0; pass < 8; ++pass) {
+            bool improved = false;
+            for (int i = 0; i < per_frame; ++i)
+                for (int j = 0; j < per_frame; ++j) {
+                    if (i == j) continue;
+                    std::vector<int> o = order;
+                    const int v = o[i];
+                    o.erase(o.begin() + i);
+                    o.insert(o.begin() + j, v);
+                    const double m = xcd_makespan(cost, o, units, cus_xcd);
+                    if (m < best - 1e-9) {
+                        best = m;
+                        order = o;
+                        improved = true;
+                    }
+                }
+            if (!improved) break;
+        }
+    }
+    ScoreOrder r{};
+    for (int i = 0; i < per_frame; ++i) r.s[i] = (unsigned char)order[i];
+    std::lock_guard<std::mutex> g(g_order_mu);
+    g_order[key] = r;
+    return r;
+}
+
+}  // namespace
 
 int score_rows_auto(const LevelTable& T, int n, int nf, int cus) {
     const long long items16 = (long long)T.ts_total * n * ((nf + FGROUP - 1) / FGROUP);
@@ -39,17 +152,26 @@ hipError_t launch_score(const LevelTable& T, int n, const float* feat, const flo
                         hipStream_t s) {
     const int groups = (nf + FGROUP - 1) / FGROUP;
     const int per_frame = (T.rows_total + rows - 1) / rows;
-    const long long items = (long long)per_frame * n * groups;
+    const long long units = (long long)n * groups;
+    const long long items = (long long)per_frame * units;
     if (items <= 0) return hipSuccess;
     if (items > 0x7fffff00LL) return hipErrorInvalidValue;
-    const int blocks = (int)((items + 7) / 8 * 8);
+    const int blocks = units >= 8 ? (int)((units + 7) / 8 * per_frame * 8) : (int)((items + 7) / 8 * 8);
+    ScoreOrder ord{};
+    for (int i = 0; i < SCORE_ORDER_MAX; ++i) ord.s[i] = (unsigned char)i;
+    if (units >= 8 && per_frame <= SCORE_ORDER_MAX && rows == ROWS_PER_ITEM) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus >= 8)
+            ord = score_order(T, rows, per_frame, (int)((units + 7) / 8), cus / 8);
+    }
     if (rows == SCORE_SMALL_ROWS)
         hipLaunchKernelGGL(hog_score_kernel<SCORE_SMALL_ROWS>, dim3(blocks), dim3(SCORE_SMALL_ROWS * 64), 0, s, T,
-                           groups, per_frame, (int)items, feat, bpack, bias, nf, thresh, dense, poskey,
+                           ord, groups, per_frame, (int)units, feat, bpack, bias, nf, thresh, dense, poskey,
                            atomic_key ? 1 : 0);
     else if (rows == ROWS_PER_ITEM)
-        hipLaunchKernelGGL(hog_score_kernel<ROWS_PER_ITEM>, dim3(blocks), dim3(ROWS_PER_ITEM * 64), 0, s, T, groups,
-                           per_frame, (int)items, feat, bpack, bias, nf, thresh, dense, poskey, atomic_key ? 1 : 0);
+        hipLaunchKernelGGL(hog_score_kernel<ROWS_PER_ITEM>, dim3(blocks), dim3(ROWS_PER_ITEM * 64), 0, s, T, ord, groups,
+                           per_frame, (int)units, feat, bpack, bias, nf, thresh, dense, poskey, atomic_key ? 1 : 0);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

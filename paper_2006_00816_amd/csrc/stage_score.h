@@ -69,6 +69,14 @@ __device__ __forceinline__ void score_row(const DevLevel& L, int k, int r, const
     const float4* __restrict__ X = sm.B + BPACK_MFMA + 2 * g4;
     const int ntiles = (L.cx + 15) >> 4;
     float carry0 = 0.f, carry1 = 0.f;
+    // the first two K chunks of the next tile, loaded while the current
+    // tile's epilogue runs
+    float4 a0n, a1n;
+    {
+        const float* __restrict__ a = Fr + min(j, L.cx + 1) * FPAD;
+        a0n = *reinterpret_cast<const float4*>(a);
+        a1n = *reinterpret_cast<const float4*>(a + 16);
+    }
 
     for (int t = 0; t < ntiles; ++t) {
         floatx4 acc[NT];
@@ -84,8 +92,8 @@ __device__ __forceinline__ void score_row(const DevLevel& L, int k, int r, const
             return *reinterpret_cast<const float4*>(a + (kc >> 1) * pitch + 16 * (kc & 1));
         };
         float4 av[SC_KC];
-        av[0] = load_a(0);
-        av[1] = load_a(1);
+        av[0] = a0n;
+        av[1] = a1n;
         // B of chunk kc + 1 is read from LDS while chunk kc computes
         float4 bb[2][NT];
 #pragma unroll
@@ -134,6 +142,11 @@ __device__ __forceinline__ void score_row(const DevLevel& L, int k, int r, const
         if (XTRA && g4 == 0) {
             ring[48 * SC_RSTR + j] = x8;
             ring[49 * SC_RSTR + j] = x9;
+        }
+        if (t + 1 < ntiles) {
+            const float* __restrict__ an = Fr + min(16 * (t + 1) + j, L.cx + 1) * FPAD;
+            a0n = *reinterpret_cast<const float4*>(an);
+            a1n = *reinterpret_cast<const float4*>(an + 16);
         }
         wave_lds_order();
 
@@ -203,7 +216,9 @@ __device__ __forceinline__ void score_item(const LevelTable& T, int frame, int g
                                            float* __restrict__ ring, const float* __restrict__ feat, int nf,
                                            const float* __restrict__ bias, float thresh, float* __restrict__ dense,
                                            unsigned long long* __restrict__ poskey, int atomic_key, int tid) {
-    const int q = item * ROWS + (tid >> 6);
+    // the wave's row, made wave-uniform so that the level's fields live in
+    // scalar registers
+    const int q = item * ROWS + __builtin_amdgcn_readfirstlane(tid >> 6);
     if (q >= T.rows_total) return;
     const int k = HOG_FIND_LEVEL(T, q, row_off);
     const DevLevel& L = T.L[k];
