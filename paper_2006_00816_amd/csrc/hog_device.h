@@ -93,6 +93,17 @@ static __device__ inline int orient_bin(int gxi, int gyi) {
     return upper ? b_up : b_lo;
 }
 
+// Gradient magnitude of a voting pixel as the fixed-point integer
+// round(|g| 2^6) (|g| in units of 2^-16 of a grey level, so the vote
+// weight is |g| 2^22).  The square root is the hardware one (within an ulp
+// of the rounded root): the quantised magnitude carries a relative error
+// near 1e-7 either way, far inside the tolerance of the histograms.
+static __device__ inline unsigned vote_magnitude(int gxi, int gyi) {
+    const float fx = (float)gxi, fy = (float)gyi;
+    const float mag = __builtin_amdgcn_sqrtf(fmaf(fx, fx, fy * fy));
+    return (unsigned)(mag * 64.0f + 0.5f);
+}
+
 // Fixed-point resampling tap: returns {i0, i1, a8, 0} for output index i
 // of an axis with n_in source samples at inverse scale sig (40 fractional
 // bits): source coordinate ((2i+1) sig - 2^40) / 2^41, weight a8/256 on

@@ -235,9 +235,7 @@ __global__ __launch_bounds__(BTHREADS) void hog_backward_kernel(
                 const int gy = sm.V[p + BP] - sm.V[p - BP];
                 if (gx | gy) {
                     bn = orient_bin(gx, gy);
-                    const float fx = (float)gx, fy = (float)gy;
-                    const float mag = __builtin_sqrtf(fmaf(fx, fx, fy * fy));
-                    const unsigned long long M = (unsigned int)(mag * 64.0f + 0.5f);
+                    const unsigned long long M = vote_magnitude(gx, gy);
                     // cell centres 8i + 3.5: lower cell of pixel yl is floor((yl - 3.5) / 8)
                     const int cyl = (yl + 4) / 8 - 1, cxl = (xl + 4) / 8 - 1;   // yl >= 1
                     const int oy = (yl + 4) & 7, ox = (xl + 4) & 7;               // offset inside the quad block

@@ -63,9 +63,7 @@ __device__ __forceinline__ void quad_votes(const int* __restrict__ sV, int lb, u
         const int gy = V[di + 2][ox + 1] - V[di][ox + 1];
         if ((gx | gy) == 0) continue;
         const int bin = orient_bin(gx, gy);
-        const float fx = (float)gx, fy = (float)gy;
-        const float mag = __builtin_sqrtf(fmaf(fx, fx, fy * fy));     // in units of 2^-16
-        const unsigned long long M = (unsigned int)(mag * 64.0f + 0.5f);   // mag * 2^22
+        const unsigned long long M = vote_magnitude(gx, gy);
         atomicAdd(h00 + bin, M * (unsigned)((15 - 2 * oy) * (15 - 2 * ox)));
         atomicAdd(h00 + CS + bin, M * (unsigned)((15 - 2 * oy) * (2 * ox + 1)));
         atomicAdd(h00 + LC_W * CS + bin, M * (unsigned)((2 * oy + 1) * (15 - 2 * ox)));
@@ -81,6 +79,49 @@ __device__ __forceinline__ void quad_votes_q(int q, const int* sV, int lb, unsig
         case 1: quad_votes<1, CHECK>(sV, lb, h00, ylb, xlb, ylim, xlim); break;
         case 2: quad_votes<2, CHECK>(sV, lb, h00, ylb, xlb, ylim, xlim); break;
         default: quad_votes<3, CHECK>(sV, lb, h00, ylb, xlb, ylim, xlim); break;
+    }
+}
+
+// Level pixels of a tile from the frame, RS pixels per thread at a time
+// with all their frame loads in flight together (taps are clamped to the
+// frame, so every load is in bounds; a zero weight or a pixel outside the
+// level discards the value).  IDENT: every tap weight is zero, so only the
+// first sample is read.
+template <bool IDENT>
+__device__ __forceinline__ void resample_tile(const int4* __restrict__ sTy, const int4* __restrict__ sTx,
+                                              const uint8_t* __restrict__ U, int* __restrict__ sV, int tid) {
+    constexpr int RS = 6;
+    for (int e0 = tid; e0 < TPY * TPX; e0 += RS * HIST_THREADS) {
+        int ty[RS], tx[RS], ay[RS], bx[RS], inside[RS];
+        int u00[RS], u01[RS], u10[RS], u11[RS];
+#pragma unroll
+        for (int r = 0; r < RS; ++r) {
+            const int e = min(e0 + r * HIST_THREADS, TPY * TPX - 1);
+            ty[r] = e / TPX;
+            tx[r] = e - ty[r] * TPX;
+            const int4 a = sTy[ty[r]], b = sTx[tx[r]];
+            ay[r] = a.z;
+            bx[r] = b.z;
+            inside[r] = (a.w | b.w) == 0;
+            u00[r] = U[(unsigned)(a.x + b.x)];
+            if (!IDENT) {
+                u01[r] = U[(unsigned)(a.x + b.y)];
+                u10[r] = U[(unsigned)(a.y + b.x)];
+                u11[r] = U[(unsigned)(a.y + b.y)];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RS; ++r) {
+            int v;
+            if (IDENT) {
+                v = inside[r] ? u00[r] << 16 : 0;
+            } else {
+                const int top = (256 - bx[r]) * u00[r] + bx[r] * u01[r];
+                const int bot = (256 - bx[r]) * u10[r] + bx[r] * u11[r];
+                v = inside[r] ? (256 - ay[r]) * top + ay[r] * bot : 0;
+            }
+            if (e0 + r * HIST_THREADS < TPY * TPX) sV[swz(ty[r], tx[r])] = v;
+        }
     }
 }
 
@@ -136,37 +177,11 @@ __device__ __forceinline__ void hist_tile(const LevelTable& T, const uint8_t* __
     }
     __syncthreads();
 
-    // 1. resample, RS pixels per thread at a time with all their frame
-    // loads in flight together (taps are clamped to the frame, so every
-    // load is in bounds; a zero weight or a pixel outside the level
-    // discards the value)
+    // 1. resample (a level at scale 1 copies the frame: its taps have zero
+    // weights on the second sample)
     if (on) {
-        constexpr int RS = 6;
-        for (int e0 = tid; e0 < TPY * TPX; e0 += RS * HIST_THREADS) {
-            int ty[RS], tx[RS], ay[RS], bx[RS], inside[RS];
-            int u00[RS], u01[RS], u10[RS], u11[RS];
-#pragma unroll
-            for (int r = 0; r < RS; ++r) {
-                const int e = min(e0 + r * HIST_THREADS, TPY * TPX - 1);
-                ty[r] = e / TPX;
-                tx[r] = e - ty[r] * TPX;
-                const int4 a = sTy[ty[r]], b = sTx[tx[r]];
-                ay[r] = a.z;
-                bx[r] = b.z;
-                inside[r] = (a.w | b.w) == 0;
-                u00[r] = U[(unsigned)(a.x + b.x)];
-                u01[r] = U[(unsigned)(a.x + b.y)];
-                u10[r] = U[(unsigned)(a.y + b.x)];
-                u11[r] = U[(unsigned)(a.y + b.y)];
-            }
-#pragma unroll
-            for (int r = 0; r < RS; ++r) {
-                const int top = (256 - bx[r]) * u00[r] + bx[r] * u01[r];
-                const int bot = (256 - bx[r]) * u10[r] + bx[r] * u11[r];
-                const int v = inside[r] ? (256 - ay[r]) * top + ay[r] * bot : 0;
-                if (e0 + r * HIST_THREADS < TPY * TPX) sV[swz(ty[r], tx[r])] = v;
-            }
-        }
+        if (L.sig == (1LL << SIG_BITS)) resample_tile<true>(sTy, sTx, U, sV, tid);
+        else resample_tile<false>(sTy, sTx, U, sV, tid);
     }
     __syncthreads();
 
