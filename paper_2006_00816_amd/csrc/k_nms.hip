@@ -79,17 +79,6 @@ __device__ __forceinline__ bool conflicts(const Box& X, int AX, const int2& ry, 
     return (long long)I * iden > inum * (long long)U;
 }
 
-// The same test without branches (for masks over several neighbours).
-__device__ __forceinline__ bool conflicts_bf(const Box& X, int AX, const int2& ry, const int2& cx, long long inum,
-                                             long long iden) {
-    const int iw = min(X.x1, cx.y) - max(X.x0, cx.x);
-    const int ih = min(X.y1, ry.y) - max(X.y0, ry.x);
-    const int I = max(iw, 0) * max(ih, 0);
-    const int U = AX + (cx.y - cx.x) * (ry.y - ry.x) - I;
-    const bool over = (inum == 1 && iden == 2) ? 2 * I > U : (long long)I * iden > inum * (long long)U;
-    return iw > 0 && ih > 0 && over;
-}
-
 __device__ __forceinline__ void decode(unsigned long long key, int& f, int& k, int& r, int& c) {
     const unsigned int pk = ~(unsigned int)(key & 0xffffffffu);
     f = pk >> 27;
@@ -149,10 +138,20 @@ __device__ __forceinline__ void stage_flush(unsigned (*stage)[256], int t, void*
 }
 
 // ------------------------------------------------------------ edges
+// Exact conflict test from hoisted terms: I = iw+ ih+ (the clamped
+// intersection sides), A' the neighbour's area.  IoU > num/den is
+// I den > num (AX + A' - I); for 1/2 (HALF) that is 3 I > AX + A'.  A
+// box with no overlap has I = 0 and never conflicts (num >= 1, areas > 0).
+template <bool HALF>
+__device__ __forceinline__ bool conflict_terms(int I, int AX, int A2, long long inum, long long iden) {
+    if (HALF) return 3 * I > AX + A2;
+    return (long long)I * iden > inum * (long long)(AX + A2 - I);
+}
+
 // One thread per window position of every frame: the record of the
 // position, and its first-round state (a candidate with no better-ranked
 // conflict is kept).
-template <typename E>
+template <typename E, bool HALF>
 __global__ __launch_bounds__(256) void hog_nms_edges_kernel(
     LevelTable T, const unsigned long long* __restrict__ poskey, const int2* __restrict__ boxes, long long inum,
     long long iden, E* __restrict__ lists, unsigned char* __restrict__ state8) {
@@ -176,36 +175,42 @@ __global__ __launch_bounds__(256) void hog_nms_edges_kernel(
         for (int k2 = L.nms_klo; k2 <= L.nms_khi; ++k2) {
             const DevLevel& M = T.L[k2];
             const Range R = neighbour_range(M, X, AX);
-            // 8 columns at a time: their box edges once, then each row's 8
-            // keys in flight together (columns past the range re-read the
-            // last one)
+            // 8 columns at a time: their clamped horizontal overlaps and
+            // widths once (a column past the range gets overlap 0 and
+            // re-reads the last key), then each row's 8 keys in flight
+            // together and a branch-free mask of the conflicting,
+            // better-ranked ones
             for (int c0 = R.c_lo; c0 <= R.c_hi; c0 += 8) {
-                int2 bc[8];
+                int iw[8], wq[8];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) bc[q] = boxes[M.box_c + min(c0 + q, R.c_hi)];
+                for (int q = 0; q < 8; ++q) {
+                    const int2 cb = boxes[M.box_c + min(c0 + q, R.c_hi)];
+                    iw[q] = c0 + q <= R.c_hi ? max(min(X.x1, cb.y) - max(X.x0, cb.x), 0) : 0;
+                    wq[q] = cb.y - cb.x;
+                }
                 for (int r2 = R.r_lo; r2 <= R.r_hi; ++r2) {
                     const int2 ry = boxes[M.box_r + r2];
-                    if (min(X.y1, ry.y) <= max(X.y0, ry.x)) continue;
-                    const int base = M.pos_off + r2 * M.cols;
+                    const int ih = max(min(X.y1, ry.y) - max(X.y0, ry.x), 0);
+                    const int hr = ry.y - ry.x;
+                    const unsigned base = (unsigned)(M.pos_off + r2 * M.cols);
                     unsigned long long kk[8];
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) kk[q] = keys[base + min(c0 + q, R.c_hi)];
-                    // conflicting better-ranked columns as a bit mask
-                    // (branch-free), then the appends
+                    for (int q = 0; q < 8; ++q) kk[q] = keys[base + (unsigned)min(c0 + q, R.c_hi)];
                     unsigned hits = 0;
 #pragma unroll
                     for (int q = 0; q < 8; ++q) {
-                        const bool hit = c0 + q <= R.c_hi && kk[q] > kx && conflicts_bf(X, AX, ry, bc[q], inum, iden);
-                        hits |= (unsigned)hit << q;
+                        const unsigned better = kk[q] > kx ? 1u : 0u;
+                        const unsigned hit = conflict_terms<HALF>(iw[q] * ih, AX, wq[q] * hr, inum, iden) ? 1u : 0u;
+                        hits |= (better & hit) << q;
                     }
                     while (hits) {
                         const int c2 = c0 + __builtin_ctz(hits);
                         hits &= hits - 1;
                         const int e = 1 + cnt;
                         if (e < CH) {
-                            stage_put<E>(st0, t, e, (unsigned)(base + c2));
+                            stage_put<E>(st0, t, e, base + (unsigned)c2);
                         } else if (e < NMS_LIST) {
-                            stage_put<E>(st1, t, e % CH, (unsigned)(base + c2));
+                            stage_put<E>(st1, t, e % CH, base + (unsigned)c2);
                             if (e % CH == CH - 1) stage_flush(st1, t, rec + (e / CH) * CH);
                         }
                         ++cnt;
@@ -622,15 +627,24 @@ hipError_t launch_nms_edges(const LevelTable& T, int n, const unsigned long long
                             long long iou_num, long long iou_den, void* lists, unsigned char* state8, int rounds,
                             hipStream_t s) {
     const dim3 grid((T.pos_frame + 255) / 256, n);
+    const bool half = iou_num == 1 && iou_den == 2;
     if (nms_wide_lists(T.pos_frame)) {
-        hipLaunchKernelGGL(hog_nms_edges_kernel<unsigned>, grid, dim3(256), 0, s, T, poskey, boxes, iou_num, iou_den,
-                           (unsigned*)lists, state8);
+        if (half)
+            hipLaunchKernelGGL((hog_nms_edges_kernel<unsigned, true>), grid, dim3(256), 0, s, T, poskey, boxes,
+                               iou_num, iou_den, (unsigned*)lists, state8);
+        else
+            hipLaunchKernelGGL((hog_nms_edges_kernel<unsigned, false>), grid, dim3(256), 0, s, T, poskey, boxes,
+                               iou_num, iou_den, (unsigned*)lists, state8);
         for (int r = 0; r < rounds; ++r)
             hipLaunchKernelGGL(hog_nms_round_kernel<unsigned>, grid, dim3(256), 0, s, T, (const unsigned*)lists,
                                state8);
     } else {
-        hipLaunchKernelGGL(hog_nms_edges_kernel<unsigned short>, grid, dim3(256), 0, s, T, poskey, boxes, iou_num,
-                           iou_den, (unsigned short*)lists, state8);
+        if (half)
+            hipLaunchKernelGGL((hog_nms_edges_kernel<unsigned short, true>), grid, dim3(256), 0, s, T, poskey, boxes,
+                               iou_num, iou_den, (unsigned short*)lists, state8);
+        else
+            hipLaunchKernelGGL((hog_nms_edges_kernel<unsigned short, false>), grid, dim3(256), 0, s, T, poskey, boxes,
+                               iou_num, iou_den, (unsigned short*)lists, state8);
         for (int r = 0; r < rounds; ++r)
             hipLaunchKernelGGL(hog_nms_round_kernel<unsigned short>, grid, dim3(256), 0, s, T,
                                (const unsigned short*)lists, state8);
