@@ -88,17 +88,21 @@ __device__ __forceinline__ void decode(unsigned long long key, int& f, int& k, i
 }
 
 // ------------------------------------------------------------ records
-// The record of window position p of a frame: NMS_LIST entries of type E
-// at lists + (frame * P + p) * NMS_LIST; entry 0 is the count, entries
-// 1.. the conflicting better-ranked positions.  A count above NMS_LIST - 1
-// means the list was cut short and the candidate is decided by a direct
-// scan instead.  Records are read and written in 64-byte chunks (4 x 16 B).
+// The record of window position p of a frame: NMS_LIST entries of type E,
+// entry 0 the count, entries 1.. the conflicting better-ranked positions.
+// A count above NMS_LIST - 1 means the list was cut short and the
+// candidate is decided by a direct scan instead.  Records are read and
+// written in 64-byte chunks of CH entries, stored chunk-major per frame:
+// chunk c of position p at lists + frame P NMS_LIST + (c P + p) CH, so the
+// first chunks of neighbouring positions (which every pass reads) are
+// contiguous.
 template <typename E>
 struct Rec {
     static constexpr int CH = 64 / (int)sizeof(E);   // entries per chunk
     uint4 c[4];
-    __device__ __forceinline__ void load(const E* rec, int chunk) {
-        const uint4* r4 = reinterpret_cast<const uint4*>(rec) + 4 * chunk;
+    // the 64-byte chunk at `chunk`
+    __device__ __forceinline__ void load(const E* chunk) {
+        const uint4* r4 = reinterpret_cast<const uint4*>(chunk);
         c[0] = r4[0];
         c[1] = r4[1];
         c[2] = r4[2];
@@ -163,7 +167,7 @@ __global__ __launch_bounds__(256) void hog_nms_edges_kernel(
     if (p >= T.pos_frame) return;
     const unsigned long long* keys = poskey + (long long)frame * T.pos_frame;
     const int P = T.pos_frame;
-    E* rec = lists + ((long long)frame * P + p) * NMS_LIST;
+    E* fl = lists + (long long)frame * P * NMS_LIST;   // the frame's records
     const unsigned long long kx = keys[p];
     int cnt = 0;
     if (kx) {
@@ -211,7 +215,7 @@ __global__ __launch_bounds__(256) void hog_nms_edges_kernel(
                             stage_put<E>(st0, t, e, base + (unsigned)c2);
                         } else if (e < NMS_LIST) {
                             stage_put<E>(st1, t, e % CH, base + (unsigned)c2);
-                            if (e % CH == CH - 1) stage_flush(st1, t, rec + (e / CH) * CH);
+                            if (e % CH == CH - 1) stage_flush(st1, t, fl + ((long long)(e / CH) * P + p) * CH);
                         }
                         ++cnt;
                     }
@@ -220,9 +224,9 @@ __global__ __launch_bounds__(256) void hog_nms_edges_kernel(
         }
     }
     stage_put<E>(st0, t, 0, (unsigned)min(cnt, 65535));
-    stage_flush(st0, t, rec);
+    stage_flush(st0, t, fl + (long long)p * CH);
     const int last = min(cnt, NMS_LIST - 1);
-    if (last >= CH && last % CH != CH - 1) stage_flush(st1, t, rec + (last / CH) * CH);
+    if (last >= CH && last % CH != CH - 1) stage_flush(st1, t, fl + ((long long)(last / CH) * P + p) * CH);
     state8[(long long)frame * T.pos_frame + p] = (unsigned char)(kx == 0ull ? DROPPED : cnt == 0 ? KEPT : UNDECIDED);
 }
 
@@ -242,14 +246,14 @@ __global__ __launch_bounds__(256) void hog_nms_round_kernel(
     if (p >= P) return;
     unsigned char* st = state8 + (long long)frame * P;
     if (st[p] != UNDECIDED) return;
-    const E* rec = lists + ((long long)frame * P + p) * NMS_LIST;
+    const E* rec = lists + (long long)frame * P * NMS_LIST + (long long)p * CH;
     Rec<E> R;
-    R.load(rec, 0);
+    R.load(rec);
     const int cnt = (int)R.at(0);
     if (cnt >= NMS_LIST) return;
     bool blocked = false;
     for (int ch = 0; ch * CH <= cnt; ++ch) {
-        if (ch) R.load(rec, ch);
+        if (ch) R.load(rec + (long long)ch * P * CH);
         unsigned char sy[CH];
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
@@ -316,13 +320,15 @@ __device__ unsigned decide_scan(const LevelTable& T, const unsigned long long* k
     return blocked ? UNDECIDED : KEPT;
 }
 
-// Decision from a position's record whose first chunk is loaded in R.
+// Decision from a position's record whose first chunk (at rec) is loaded
+// in R; chunk c is at rec + c * cstride.
 template <typename E, bool G>
-__device__ __forceinline__ unsigned decide_rec(const unsigned* S, const E* rec, Rec<E>& R, int cnt) {
+__device__ __forceinline__ unsigned decide_rec(const unsigned* S, const E* rec, long long cstride, Rec<E>& R,
+                                               int cnt) {
     constexpr int CH = Rec<E>::CH;
     bool blocked = false;
     for (int ch = 0; ch * CH <= cnt; ++ch) {
-        if (ch) R.load(rec, ch);
+        if (ch) R.load(rec + ch * cstride);
         // all state reads of the chunk in flight together, then the checks
         // (16 at a time; unconditional reads, entries past the count
         // redirected to position 0, so that the compiler does not
@@ -450,7 +456,7 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
             const int* in = wl[cur];
             for (int i = tid; i < n_in; i += NMS_THREADS) {
                 const int p = in[i];
-                const int cnt = (int)lst[(long long)p * NMS_LIST];
+                const int cnt = (int)lst[(long long)p * CH];
                 rc_pos[i] = p;
                 // overflowed lists (decided by a scan) take no chunks: 0xffff
                 rc_first[i] = cnt < NMS_LIST ? (unsigned short)min(atomicAdd(&s_chunks, cnt / CH + 1), 65534)
@@ -461,11 +467,14 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
                 for (int i = tid; i < n_in; i += NMS_THREADS) {
                     rc_wl[0][i] = (unsigned short)i;
                     if (rc_first[i] == 0xffff) continue;
-                    const E* rec = lst + (long long)rc_pos[i] * NMS_LIST;
+                    const E* rec = lst + (long long)rc_pos[i] * CH;
                     const int cnt = (int)rec[0];
-                    const uint4* src = reinterpret_cast<const uint4*>(rec);
                     uint4* dst = rc_chunks + 4 * (int)rc_first[i];
-                    for (int q = 0; q < 4 * (cnt / CH + 1); ++q) dst[q] = src[q];
+                    for (int c = 0; c <= cnt / CH; ++c) {
+                        const uint4* src = reinterpret_cast<const uint4*>(rec + (long long)c * P * CH);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) dst[4 * c + q] = src[q];
+                    }
                 }
                 cached = true;
                 cur = 0;
@@ -488,8 +497,8 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
                     if (first != 0xffff) {
                         const E* rec = reinterpret_cast<const E*>(rc_chunks + 4 * first);
                         Rec<E> R;
-                        R.load(rec, 0);
-                        v = decide_rec<E, G>(S, rec, R, (int)R.at(0));
+                        R.load(rec);
+                        v = decide_rec<E, G>(S, rec, CH, R, (int)R.at(0));
                     } else {
                         v = decide_scan<G>(T, keys, S, boxes, keys[p], inum, iden);
                     }
@@ -510,7 +519,7 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
                 }
 #pragma unroll
                 for (int b = 0; b < RESOLVE_BATCH; ++b)
-                    if (pp[b] >= 0) R[b].load(lst + (long long)pp[b] * NMS_LIST, 0);
+                    if (pp[b] >= 0) R[b].load(lst + (long long)pp[b] * CH);
 #pragma unroll
                 for (int b = 0; b < RESOLVE_BATCH; ++b) {
                     bool keep_working = false;
@@ -518,7 +527,7 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
                     if (p >= 0) {
                         const int cnt = (int)R[b].at(0);
                         const unsigned v = cnt < NMS_LIST
-                                               ? decide_rec<E, G>(S, lst + (long long)p * NMS_LIST, R[b], cnt)
+                                               ? decide_rec<E, G>(S, lst + (long long)p * CH, (long long)P * CH, R[b], cnt)
                                                : decide_scan<G>(T, keys, S, boxes, keys[p], inum, iden);
                         if (v != UNDECIDED) atomicOr(&S[p >> 4], v << ((p & 15) * 2));
                         else keep_working = true;
