@@ -124,8 +124,8 @@ struct Rec {
 
 // Per-thread staging of one 64-byte chunk in LDS, as 16 words; word w of
 // thread t at stage[w][t], so a wave's accesses fall in different banks.
-template <typename E>
-__device__ __forceinline__ void stage_put(unsigned (*stage)[256], int t, int slot, unsigned v) {
+template <typename E, int BS>
+__device__ __forceinline__ void stage_put(unsigned (*stage)[BS], int t, int slot, unsigned v) {
     if (sizeof(E) == 2) {
         unsigned& wd = stage[slot >> 1][t];
         wd = (slot & 1) ? (wd & 0xffffu) | (v << 16) : (wd & 0xffff0000u) | (v & 0xffffu);
@@ -134,7 +134,8 @@ __device__ __forceinline__ void stage_put(unsigned (*stage)[256], int t, int slo
     }
 }
 
-__device__ __forceinline__ void stage_flush(unsigned (*stage)[256], int t, void* dst) {
+template <int BS>
+__device__ __forceinline__ void stage_flush(unsigned (*stage)[BS], int t, void* dst) {
     uint4* d = reinterpret_cast<uint4*>(dst);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
@@ -154,16 +155,17 @@ __device__ __forceinline__ bool conflict_terms(int I, int AX, int A2, long long 
 
 // One thread per window position of every frame: the record of the
 // position, and its first-round state (a candidate with no better-ranked
-// conflict is kept).
-template <typename E, bool HALF>
-__global__ __launch_bounds__(256) void hog_nms_edges_kernel(
+// conflict is kept).  Workgroups of BS threads (64 for a few frames, so
+// that they spread over more compute units).
+template <typename E, bool HALF, int BS>
+__global__ __launch_bounds__(BS) void hog_nms_edges_kernel(
     LevelTable T, const unsigned long long* __restrict__ poskey, const int2* __restrict__ boxes, long long inum,
     long long iden, E* __restrict__ lists, unsigned char* __restrict__ state8) {
     constexpr int CH = Rec<E>::CH;
-    __shared__ unsigned st0[16][256], st1[16][256];   // chunk 0 (holds the count) and the current chunk
+    __shared__ unsigned st0[16][BS], st1[16][BS];   // chunk 0 (holds the count) and the current chunk
     const int frame = blockIdx.y;
     const int t = threadIdx.x;
-    const int p = blockIdx.x * 256 + t;
+    const int p = blockIdx.x * BS + t;
     if (p >= T.pos_frame) return;
     const unsigned long long* keys = poskey + (long long)frame * T.pos_frame;
     const int P = T.pos_frame;
@@ -212,9 +214,9 @@ __global__ __launch_bounds__(256) void hog_nms_edges_kernel(
                         hits &= hits - 1;
                         const int e = 1 + cnt;
                         if (e < CH) {
-                            stage_put<E>(st0, t, e, base + (unsigned)c2);
+                            stage_put<E, BS>(st0, t, e, base + (unsigned)c2);
                         } else if (e < NMS_LIST) {
-                            stage_put<E>(st1, t, e % CH, base + (unsigned)c2);
+                            stage_put<E, BS>(st1, t, e % CH, base + (unsigned)c2);
                             if (e % CH == CH - 1) stage_flush(st1, t, fl + ((long long)(e / CH) * P + p) * CH);
                         }
                         ++cnt;
@@ -223,7 +225,7 @@ __global__ __launch_bounds__(256) void hog_nms_edges_kernel(
             }
         }
     }
-    stage_put<E>(st0, t, 0, (unsigned)min(cnt, 65535));
+    stage_put<E, BS>(st0, t, 0, (unsigned)min(cnt, 65535));
     stage_flush(st0, t, fl + (long long)p * CH);
     const int last = min(cnt, NMS_LIST - 1);
     if (last >= CH && last % CH != CH - 1) stage_flush(st1, t, fl + ((long long)(last / CH) * P + p) * CH);
@@ -239,10 +241,11 @@ __global__ __launch_bounds__(256) void hog_nms_edges_kernel(
 template <typename E>
 __global__ __launch_bounds__(256) void hog_nms_round_kernel(
     LevelTable T, const E* __restrict__ lists, unsigned char* __restrict__ state8) {
+    // workgroups of 64 or 256 threads
     constexpr int CH = Rec<E>::CH;
     const int frame = blockIdx.y;
     const int P = T.pos_frame;
-    const int p = blockIdx.x * 256 + threadIdx.x;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
     unsigned char* st = state8 + (long long)frame * P;
     if (st[p] != UNDECIDED) return;
@@ -632,30 +635,44 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
 // Positions whose states fit in LDS next to the sort buffer.
 constexpr int NMS_LDS_STATE_WORDS = (160 * 1024 - RC_BYTES - 2048) / 4;
 
+// Up to this many frames, the per-position kernels use 64-thread workgroups.
+constexpr int NMS_SMALL_BATCH = 4;
+
+template <typename E>
+void edges_launch(bool half, int bs, dim3 grid, const LevelTable& T, const unsigned long long* poskey,
+                  const int2* boxes, long long inum, long long iden, E* lists, unsigned char* state8, hipStream_t s) {
+    if (half && bs == 64)
+        hipLaunchKernelGGL((hog_nms_edges_kernel<E, true, 64>), grid, dim3(64), 0, s, T, poskey, boxes, inum, iden,
+                           lists, state8);
+    else if (half)
+        hipLaunchKernelGGL((hog_nms_edges_kernel<E, true, 256>), grid, dim3(256), 0, s, T, poskey, boxes, inum, iden,
+                           lists, state8);
+    else if (bs == 64)
+        hipLaunchKernelGGL((hog_nms_edges_kernel<E, false, 64>), grid, dim3(64), 0, s, T, poskey, boxes, inum, iden,
+                           lists, state8);
+    else
+        hipLaunchKernelGGL((hog_nms_edges_kernel<E, false, 256>), grid, dim3(256), 0, s, T, poskey, boxes, inum,
+                           iden, lists, state8);
+}
+
 hipError_t launch_nms_edges(const LevelTable& T, int n, const unsigned long long* poskey, const int2* boxes,
                             long long iou_num, long long iou_den, void* lists, unsigned char* state8, int rounds,
                             hipStream_t s) {
-    const dim3 grid((T.pos_frame + 255) / 256, n);
+    // a few frames: workgroups of 64 threads, so that the positions of a
+    // frame spread over four times as many compute units
+    const int bs = n <= NMS_SMALL_BATCH ? 64 : 256;
+    const dim3 grid((T.pos_frame + bs - 1) / bs, n);
     const bool half = iou_num == 1 && iou_den == 2;
     if (nms_wide_lists(T.pos_frame)) {
-        if (half)
-            hipLaunchKernelGGL((hog_nms_edges_kernel<unsigned, true>), grid, dim3(256), 0, s, T, poskey, boxes,
-                               iou_num, iou_den, (unsigned*)lists, state8);
-        else
-            hipLaunchKernelGGL((hog_nms_edges_kernel<unsigned, false>), grid, dim3(256), 0, s, T, poskey, boxes,
-                               iou_num, iou_den, (unsigned*)lists, state8);
+        edges_launch<unsigned>(half, bs, grid, T, poskey, boxes, iou_num, iou_den, (unsigned*)lists, state8, s);
         for (int r = 0; r < rounds; ++r)
-            hipLaunchKernelGGL(hog_nms_round_kernel<unsigned>, grid, dim3(256), 0, s, T, (const unsigned*)lists,
+            hipLaunchKernelGGL(hog_nms_round_kernel<unsigned>, grid, dim3(bs), 0, s, T, (const unsigned*)lists,
                                state8);
     } else {
-        if (half)
-            hipLaunchKernelGGL((hog_nms_edges_kernel<unsigned short, true>), grid, dim3(256), 0, s, T, poskey, boxes,
-                               iou_num, iou_den, (unsigned short*)lists, state8);
-        else
-            hipLaunchKernelGGL((hog_nms_edges_kernel<unsigned short, false>), grid, dim3(256), 0, s, T, poskey, boxes,
-                               iou_num, iou_den, (unsigned short*)lists, state8);
+        edges_launch<unsigned short>(half, bs, grid, T, poskey, boxes, iou_num, iou_den, (unsigned short*)lists,
+                                     state8, s);
         for (int r = 0; r < rounds; ++r)
-            hipLaunchKernelGGL(hog_nms_round_kernel<unsigned short>, grid, dim3(256), 0, s, T,
+            hipLaunchKernelGGL(hog_nms_round_kernel<unsigned short>, grid, dim3(bs), 0, s, T,
                                (const unsigned short*)lists, state8);
     }
     return hipGetLastError();
