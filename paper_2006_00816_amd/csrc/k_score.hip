@@ -29,7 +29,7 @@ struct ScoreOrder {
 
 template <int ROWS>
 __global__ __launch_bounds__(ROWS * 64) void hog_score_kernel(
-    LevelTable T, ScoreOrder ord, int groups, int per_frame, int units, const float* __restrict__ feat,
+    LevelTable T, ScoreOrder ord, int groups, int per_frame, int units, int halves, const float* __restrict__ feat,
     const float4* __restrict__ bpack, const float* __restrict__ bias, int nf, float thresh,
     float* __restrict__ dense, unsigned long long* __restrict__ poskey, int atomic_key) {
     __shared__ ScoreSmemT<ROWS> sm;
@@ -53,8 +53,9 @@ __global__ __launch_bounds__(ROWS * 64) void hog_score_kernel(
     const int tid = threadIdx.x;
     load_bpack(sm, bpack, grp, tid);
     __syncthreads();
-    score_item<ROWS>(T, frame, grp, it, sm, sm.P[tid >> 6], feat, nf, bias, thresh, dense, poskey, atomic_key,
-                     tid);
+    // halves = 2: slot it runs one half of the tiles of row block it / 2
+    score_item<ROWS>(T, frame, grp, halves == 2 ? it >> 1 : it, sm, sm.P[tid >> 6], feat, nf, bias, thresh, dense,
+                     poskey, atomic_key, tid, halves == 2 ? it & 1 : -1);
 }
 
 namespace {
@@ -151,27 +152,35 @@ hipError_t launch_score(const LevelTable& T, int n, const float* feat, const flo
                         int nf, float thresh, float* dense, unsigned long long* poskey, bool atomic_key, int rows,
                         hipStream_t s) {
     const int groups = (nf + FGROUP - 1) / FGROUP;
-    const int per_frame = (T.rows_total + rows - 1) / rows;
     const long long units = (long long)n * groups;
+    int cus = 0;
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 0;
+    }
+    // small items that still leave compute units idle: split the rows'
+    // tiles in two halves, so that a level-0 row takes 3 tile times, not 5
+    const int blocks_of_rows = (T.rows_total + rows - 1) / rows;
+    const int halves = rows == SCORE_SMALL_ROWS && (long long)blocks_of_rows * units < cus ? 2 : 1;
+    const int per_frame = blocks_of_rows * halves;
     const long long items = (long long)per_frame * units;
     if (items <= 0) return hipSuccess;
     if (items > 0x7fffff00LL) return hipErrorInvalidValue;
     const int blocks = units >= 8 ? (int)((units + 7) / 8 * per_frame * 8) : (int)((items + 7) / 8 * 8);
     ScoreOrder ord{};
     for (int i = 0; i < SCORE_ORDER_MAX; ++i) ord.s[i] = (unsigned char)i;
-    if (units >= 8 && per_frame <= SCORE_ORDER_MAX && rows == ROWS_PER_ITEM) {
-        int dev = 0, cus = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus >= 8)
-            ord = score_order(T, rows, per_frame, (int)((units + 7) / 8), cus / 8);
-    }
+    if (units >= 8 && per_frame <= SCORE_ORDER_MAX && rows == ROWS_PER_ITEM && cus >= 8)
+        ord = score_order(T, rows, per_frame, (int)((units + 7) / 8), cus / 8);
     if (rows == SCORE_SMALL_ROWS)
         hipLaunchKernelGGL(hog_score_kernel<SCORE_SMALL_ROWS>, dim3(blocks), dim3(SCORE_SMALL_ROWS * 64), 0, s, T,
-                           ord, groups, per_frame, (int)units, feat, bpack, bias, nf, thresh, dense, poskey,
+                           ord, groups, per_frame, (int)units, halves, feat, bpack, bias, nf, thresh, dense, poskey,
                            atomic_key ? 1 : 0);
     else if (rows == ROWS_PER_ITEM)
         hipLaunchKernelGGL(hog_score_kernel<ROWS_PER_ITEM>, dim3(blocks), dim3(ROWS_PER_ITEM * 64), 0, s, T, ord, groups,
-                           per_frame, (int)units, feat, bpack, bias, nf, thresh, dense, poskey, atomic_key ? 1 : 0);
+                           per_frame, (int)units, halves, feat, bpack, bias, nf, thresh, dense, poskey,
+                           atomic_key ? 1 : 0);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -53,11 +53,17 @@ __device__ __forceinline__ void wave_lds_order() {
 // and, per window position, the best candidate key over the group's
 // filters (0 if no filter's score exceeds the threshold), stored or merged
 // with atomic max.
+//
+// Tiles [t_begin, t_end) of the row are output.  A range that starts
+// inside the row first recomputes tile t_begin - 1 for the carry alone, so
+// every output takes the same operands in the same order as a whole-row
+// walk: the same bits.
 template <int NT, bool XTRA, int ROWS>
 __device__ __forceinline__ void score_row(const DevLevel& L, int k, int r, const float* __restrict__ Ffr,
                                           const ScoreSmemT<ROWS>& sm, float* __restrict__ ring, int grp, int nf,
                                           const float* __restrict__ bias, float thresh, float* __restrict__ Dfr,
-                                          unsigned long long* __restrict__ PKfr, int atomic_key, int lane) {
+                                          unsigned long long* __restrict__ PKfr, int atomic_key, int lane,
+                                          int t_begin, int t_end) {
     const int g4 = lane >> 4, j = lane & 15;
     const int pitch = (L.cx + 2) * FPAD;
     const float* __restrict__ Fr = Ffr + L.feat_off + (long long)r * pitch + 4 * g4;
@@ -67,18 +73,19 @@ __device__ __forceinline__ void score_row(const DevLevel& L, int k, int r, const
     float* __restrict__ D = Dfr ? Dfr + L.sc_off : nullptr;
     unsigned long long* __restrict__ PK = PKfr ? PKfr + L.pos_off + (long long)r * L.cols : nullptr;
     const float4* __restrict__ X = sm.B + BPACK_MFMA + 2 * g4;
-    const int ntiles = (L.cx + 15) >> 4;
+    const int ntiles = t_end;
+    const int t_first = max(t_begin - 1, 0);
     float carry0 = 0.f, carry1 = 0.f;
     // the first two K chunks of the next tile, loaded while the current
     // tile's epilogue runs
     float4 a0n, a1n;
     {
-        const float* __restrict__ a = Fr + min(j, L.cx + 1) * FPAD;
+        const float* __restrict__ a = Fr + min(16 * t_first + j, L.cx + 1) * FPAD;
         a0n = *reinterpret_cast<const float4*>(a);
         a1n = *reinterpret_cast<const float4*>(a + 16);
     }
 
-    for (int t = 0; t < ntiles; ++t) {
+    for (int t = t_first; t < ntiles; ++t) {
         floatx4 acc[NT];
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -172,6 +179,7 @@ __device__ __forceinline__ void score_row(const DevLevel& L, int k, int r, const
         carry0 = n0;
         carry1 = n1;
         wave_lds_order();
+        if (t < t_begin) continue;   // carry-only tile
 
         const int c = 16 * t - (WIN - 1) + j;
         const bool cok = c >= 0 && c < L.cols;
@@ -209,13 +217,16 @@ __device__ __forceinline__ void score_row(const DevLevel& L, int k, int r, const
 
 // One scoring item: window rows q = ROWS * item + wave of the frame's list
 // of rows (levels in order), filter group grp; sm.B holds the group's B.
-// Waves past the last row do nothing.
+// Waves past the last row do nothing.  half < 0: whole rows; half = 0 or 1:
+// the first or second half of the M tiles of rows with three or more tiles
+// (the second half of a shorter row is empty).
 template <int ROWS>
 __device__ __forceinline__ void score_item(const LevelTable& T, int frame, int grp, int item,
                                            const ScoreSmemT<ROWS>& sm,
                                            float* __restrict__ ring, const float* __restrict__ feat, int nf,
                                            const float* __restrict__ bias, float thresh, float* __restrict__ dense,
-                                           unsigned long long* __restrict__ poskey, int atomic_key, int tid) {
+                                           unsigned long long* __restrict__ poskey, int atomic_key, int tid,
+                                           int half = -1) {
     // the wave's row, made wave-uniform so that the level's fields live in
     // scalar registers
     const int q = item * ROWS + __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -228,14 +239,25 @@ __device__ __forceinline__ void score_item(const LevelTable& T, int frame, int g
     unsigned long long* PKfr = poskey ? poskey + (long long)frame * T.pos_frame : nullptr;
     const int fg = min(FGROUP, nf - grp * FGROUP);
     const int lane = tid & 63;
+    const int ntiles = (L.cx + 15) >> 4;
+    int tb = 0, te = ntiles;
+    if (half >= 0) {
+        const int mid = ntiles >= 3 ? (ntiles + 1) >> 1 : ntiles;
+        tb = half ? mid : 0;
+        te = half ? ntiles : mid;
+        if (tb >= te) return;
+    }
     if (fg == 5)
-        score_row<3, true, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane);
+        score_row<3, true, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane, tb, te);
     else if (fg == 4)
-        score_row<3, false, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane);
+        score_row<3, false, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane, tb,
+                                  te);
     else if (fg >= 2)
-        score_row<2, false, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane);
+        score_row<2, false, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane, tb,
+                                  te);
     else
-        score_row<1, false, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane);
+        score_row<1, false, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane, tb,
+                                  te);
 }
 
 }  // namespace hog
