@@ -287,11 +287,19 @@ __global__ __launch_bounds__(256) void hog_nms_round_kernel(
 // (Frames with too many positions for LDS keep them in global memory,
 // accessed with device-scope atomics.)
 template <bool G>
+__device__ __forceinline__ unsigned state_word(const unsigned* S, int w) {
+    if (G) return __hip_atomic_load(S + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return S[w];
+}
+
+template <bool G>
 __device__ __forceinline__ unsigned state_of(const unsigned* S, int y) {
-    unsigned w;
-    if (G) w = __hip_atomic_load(S + (y >> 4), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    else w = S[y >> 4];
-    return (w >> ((y & 15) * 2)) & 3u;
+    return (state_word<G>(S, y >> 4) >> ((y & 15) * 2)) & 3u;
+}
+
+// The KEPT positions of a state word, as one bit (the low one) per 2-bit state.
+__device__ __forceinline__ unsigned kept_bits(unsigned w) {
+    return w & ~(w >> 1) & 0x55555555u;
 }
 
 // Direct scan of the neighbourhood (lists that did not fit).
@@ -440,9 +448,10 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
             else S[w] = v;
         }
     }
+    __syncthreads();
     for (int p0 = 0; p0 < P; p0 += NMS_THREADS) {
         const int p = p0 + tid;
-        wave_append(p < P && st8[p] == UNDECIDED, p, wl[0], &s_count);
+        wave_append(p < P && state_of<G>(S, p) == UNDECIDED, p, wl[0], &s_count);
     }
     __syncthreads();
 
@@ -548,8 +557,9 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
     // count the kept candidates
     if (tid == 0) s_count = 0;
     __syncthreads();
+    // (positions past the end of the last word are DROPPED)
     int mine = 0;
-    for (int p = tid; p < P; p += NMS_THREADS) mine += state_of<G>(S, p) == KEPT;
+    for (int w = tid; w < nw; w += NMS_THREADS) mine += __popc(kept_bits(state_word<G>(S, w)));
     if (mine) atomicAdd(&s_count, mine);
     __syncthreads();
     const int nkept = s_count;
@@ -588,32 +598,47 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
     // gather kept keys >= thr, pad with zeros to a power of two
     if (tid == 0) s_count = 0;
     __syncthreads();
-    for (int p = tid; p < P; p += NMS_THREADS) {
-        if (state_of<G>(S, p) != KEPT) continue;
-        const unsigned long long kk = keys[p];
-        if (kk < thr) continue;
-        const int slot = atomicAdd(&s_count, 1);
-        if (slot < SORT_CAP) sk[slot] = kk;
+    for (int w = tid; w < nw; w += NMS_THREADS) {
+        unsigned m = kept_bits(state_word<G>(S, w));
+        while (m) {
+            const int p = 16 * w + (__builtin_ctz(m) >> 1);
+            m &= m - 1u;
+            const unsigned long long kk = keys[p];
+            if (kk < thr) continue;
+            const int slot = atomicAdd(&s_count, 1);
+            if (slot < SORT_CAP) sk[slot] = kk;
+        }
     }
     __syncthreads();
     const int ng = min(s_count, SORT_CAP);
-    int npow = 1;
-    while (npow < ng) npow <<= 1;
-    for (int e = ng + tid; e < npow; e += NMS_THREADS) sk[e] = 0ull;
-    __syncthreads();
-
-    // bitonic sort, descending
-    for (int size = 2; size <= npow; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int e = tid; e < npow; e += NMS_THREADS) {
-                const int partner = e ^ stride;
-                if (partner > e) {
-                    const bool desc = (e & size) == 0;
-                    const unsigned long long a = sk[e], b = sk[partner];
-                    if ((a < b) == desc) { sk[e] = b; sk[partner] = a; }
+    if (ng <= NMS_THREADS) {
+        // the keys are distinct, so a key's place in descending order is
+        // the number of larger keys (all threads read the same key at a
+        // time: LDS broadcasts)
+        const unsigned long long mykey = tid < ng ? sk[tid] : 0ull;
+        int rank = 0;
+        for (int i = 0; i < ng; ++i) rank += sk[i] > mykey ? 1 : 0;
+        __syncthreads();
+        if (tid < ng) sk[rank] = mykey;
+        __syncthreads();
+    } else {
+        int npow = 1;
+        while (npow < ng) npow <<= 1;
+        for (int e = ng + tid; e < npow; e += NMS_THREADS) sk[e] = 0ull;
+        __syncthreads();
+        // bitonic sort, descending
+        for (int size = 2; size <= npow; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int e = tid; e < npow; e += NMS_THREADS) {
+                    const int partner = e ^ stride;
+                    if (partner > e) {
+                        const bool desc = (e & size) == 0;
+                        const unsigned long long a = sk[e], b = sk[partner];
+                        if ((a < b) == desc) { sk[e] = b; sk[partner] = a; }
+                    }
                 }
+                __syncthreads();
             }
-            __syncthreads();
         }
     }
 
