@@ -18,6 +18,8 @@
 //    the rounds end, with the result of the sequential greedy pass.  Then
 //    the kept keys are sorted (the top min(cap, 4096) when there are more)
 //    and written out.
+#include <algorithm>
+
 #include "hog_device.h"
 
 namespace hog {
@@ -153,6 +155,49 @@ __device__ __forceinline__ bool conflict_terms(int I, int AX, int A2, long long 
     return (long long)I * iden > inum * (long long)(AX + A2 - I);
 }
 
+// The better-ranked windows of level M that conflict with candidate X
+// (key kx, box X of area AX), in order of column block, row, column;
+// `hit` receives each position index.  8 columns at a time: their clamped
+// horizontal overlaps and widths once (a column past the range gets
+// overlap 0 and re-reads the last key), then each row's 8 keys in flight
+// together and a branch-free mask of the conflicting, better-ranked ones.
+template <bool HALF, typename F>
+__device__ __forceinline__ void scan_level(const DevLevel& M, const Box& X, int AX, unsigned long long kx,
+                                           const unsigned long long* __restrict__ keys,
+                                           const int2* __restrict__ boxes, long long inum, long long iden, F&& hit) {
+    const Range R = neighbour_range(M, X, AX);
+    for (int c0 = R.c_lo; c0 <= R.c_hi; c0 += 8) {
+        int iw[8], wq[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int2 cb = boxes[M.box_c + min(c0 + q, R.c_hi)];
+            iw[q] = c0 + q <= R.c_hi ? max(min(X.x1, cb.y) - max(X.x0, cb.x), 0) : 0;
+            wq[q] = cb.y - cb.x;
+        }
+        for (int r2 = R.r_lo; r2 <= R.r_hi; ++r2) {
+            const int2 ry = boxes[M.box_r + r2];
+            const int ih = max(min(X.y1, ry.y) - max(X.y0, ry.x), 0);
+            const int hr = ry.y - ry.x;
+            const unsigned base = (unsigned)(M.pos_off + r2 * M.cols);
+            unsigned long long kk[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) kk[q] = keys[base + (unsigned)min(c0 + q, R.c_hi)];
+            unsigned hits = 0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const unsigned better = kk[q] > kx ? 1u : 0u;
+                const unsigned h = conflict_terms<HALF>(iw[q] * ih, AX, wq[q] * hr, inum, iden) ? 1u : 0u;
+                hits |= (better & h) << q;
+            }
+            while (hits) {
+                const int c2 = c0 + __builtin_ctz(hits);
+                hits &= hits - 1;
+                hit(base + (unsigned)c2);
+            }
+        }
+    }
+}
+
 // One thread per window position of every frame: the record of the
 // position, and its first-round state (a candidate with no better-ranked
 // conflict is kept).  Workgroups of BS threads (64 for a few frames, so
@@ -178,58 +223,96 @@ __global__ __launch_bounds__(BS) void hog_nms_edges_kernel(
         const DevLevel& L = T.L[k];
         const Box X = window_box(L, boxes, r, c);
         const int AX = (X.x1 - X.x0) * (X.y1 - X.y0);
-        for (int k2 = L.nms_klo; k2 <= L.nms_khi; ++k2) {
-            const DevLevel& M = T.L[k2];
-            const Range R = neighbour_range(M, X, AX);
-            // 8 columns at a time: their clamped horizontal overlaps and
-            // widths once (a column past the range gets overlap 0 and
-            // re-reads the last key), then each row's 8 keys in flight
-            // together and a branch-free mask of the conflicting,
-            // better-ranked ones
-            for (int c0 = R.c_lo; c0 <= R.c_hi; c0 += 8) {
-                int iw[8], wq[8];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const int2 cb = boxes[M.box_c + min(c0 + q, R.c_hi)];
-                    iw[q] = c0 + q <= R.c_hi ? max(min(X.x1, cb.y) - max(X.x0, cb.x), 0) : 0;
-                    wq[q] = cb.y - cb.x;
+        for (int k2 = L.nms_klo; k2 <= L.nms_khi; ++k2)
+            scan_level<HALF>(T.L[k2], X, AX, kx, keys, boxes, inum, iden, [&](unsigned y) {
+                const int e = 1 + cnt;
+                if (e < CH) {
+                    stage_put<E, BS>(st0, t, e, y);
+                } else if (e < NMS_LIST) {
+                    stage_put<E, BS>(st1, t, e % CH, y);
+                    if (e % CH == CH - 1) stage_flush(st1, t, fl + ((long long)(e / CH) * P + p) * CH);
                 }
-                for (int r2 = R.r_lo; r2 <= R.r_hi; ++r2) {
-                    const int2 ry = boxes[M.box_r + r2];
-                    const int ih = max(min(X.y1, ry.y) - max(X.y0, ry.x), 0);
-                    const int hr = ry.y - ry.x;
-                    const unsigned base = (unsigned)(M.pos_off + r2 * M.cols);
-                    unsigned long long kk[8];
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) kk[q] = keys[base + (unsigned)min(c0 + q, R.c_hi)];
-                    unsigned hits = 0;
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        const unsigned better = kk[q] > kx ? 1u : 0u;
-                        const unsigned hit = conflict_terms<HALF>(iw[q] * ih, AX, wq[q] * hr, inum, iden) ? 1u : 0u;
-                        hits |= (better & hit) << q;
-                    }
-                    while (hits) {
-                        const int c2 = c0 + __builtin_ctz(hits);
-                        hits &= hits - 1;
-                        const int e = 1 + cnt;
-                        if (e < CH) {
-                            stage_put<E, BS>(st0, t, e, base + (unsigned)c2);
-                        } else if (e < NMS_LIST) {
-                            stage_put<E, BS>(st1, t, e % CH, base + (unsigned)c2);
-                            if (e % CH == CH - 1) stage_flush(st1, t, fl + ((long long)(e / CH) * P + p) * CH);
-                        }
-                        ++cnt;
-                    }
-                }
-            }
-        }
+                ++cnt;
+            });
     }
     stage_put<E, BS>(st0, t, 0, (unsigned)min(cnt, 65535));
     stage_flush(st0, t, fl + (long long)p * CH);
     const int last = min(cnt, NMS_LIST - 1);
     if (last >= CH && last % CH != CH - 1) stage_flush(st1, t, fl + ((long long)(last / CH) * P + p) * CH);
     state8[(long long)frame * T.pos_frame + p] = (unsigned char)(kx == 0ull ? DROPPED : cnt == 0 ? KEPT : UNDECIDED);
+}
+
+// The same records for a few frames, where one frame has too few positions
+// to fill the GPU: 64 positions per workgroup, and wave s scans level
+// nms_klo + s of each (up to 4 levels) into an LDS list; then wave 0
+// concatenates the lists in level order, which gives the entries in the
+// order of the kernel above.  A level list longer than EDGE_SUB entries
+// marks the record as cut short (the per-frame kernel then scans the
+// neighbourhood directly, exactly as for any record over NMS_LIST - 1).
+constexpr int EDGE_SUB = 64;
+
+template <typename E, bool HALF>
+__global__ __launch_bounds__(256) void hog_nms_edges_split_kernel(
+    LevelTable T, const unsigned long long* __restrict__ poskey, const int2* __restrict__ boxes, long long inum,
+    long long iden, E* __restrict__ lists, unsigned char* __restrict__ state8) {
+    constexpr int CH = Rec<E>::CH;
+    __shared__ E sub[4][EDGE_SUB][64];
+    __shared__ int sub_n[4][64];
+    __shared__ unsigned st0[16][64], st1[16][64];
+    const int frame = blockIdx.y;
+    const int t = threadIdx.x & 63, s = threadIdx.x >> 6;
+    const int P = T.pos_frame;
+    const int p = blockIdx.x * 64 + t;
+    const unsigned long long* keys = poskey + (long long)frame * P;
+    const unsigned long long kx = p < P ? keys[p] : 0ull;
+    int n = 0;
+    if (kx) {
+        int f, k, r, c;
+        decode(kx, f, k, r, c);
+        const DevLevel& L = T.L[k];
+        const int k2 = L.nms_klo + s;
+        if (k2 <= L.nms_khi) {
+            const Box X = window_box(L, boxes, r, c);
+            const int AX = (X.x1 - X.x0) * (X.y1 - X.y0);
+            scan_level<HALF>(T.L[k2], X, AX, kx, keys, boxes, inum, iden, [&](unsigned y) {
+                if (n < EDGE_SUB) sub[s][n][t] = (E)y;
+                ++n;
+            });
+        }
+    }
+    sub_n[s][t] = n;
+    __syncthreads();
+    if (s != 0 || p >= P) return;
+    E* fl = lists + (long long)frame * P * NMS_LIST;
+    int cnt = 0;
+    bool cut = false;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        cnt += sub_n[q][t];
+        cut |= sub_n[q][t] > EDGE_SUB;
+    }
+    if (!cut && cnt < NMS_LIST) {
+        int e = 1;
+        for (int q = 0; q < 4; ++q) {
+            const int nq = sub_n[q][t];
+            for (int i = 0; i < nq; ++i, ++e) {
+                const unsigned y = sub[q][i][t];
+                if (e < CH) {
+                    stage_put<E, 64>(st0, t, e, y);
+                } else {
+                    stage_put<E, 64>(st1, t, e % CH, y);
+                    if (e % CH == CH - 1) stage_flush(st1, t, fl + ((long long)(e / CH) * P + p) * CH);
+                }
+            }
+        }
+        const int last = cnt;
+        if (last >= CH && last % CH != CH - 1) stage_flush(st1, t, fl + ((long long)(last / CH) * P + p) * CH);
+    } else {
+        cnt = max(cnt, NMS_LIST);
+    }
+    stage_put<E, 64>(st0, t, 0, (unsigned)min(cnt, 65535));
+    stage_flush(st0, t, fl + (long long)p * CH);
+    state8[(long long)frame * P + p] = (unsigned char)(kx == 0ull ? DROPPED : cnt == 0 ? KEPT : UNDECIDED);
 }
 
 // One parallel round over every window position of every frame: an
@@ -666,18 +749,31 @@ constexpr int NMS_SMALL_BATCH = 4;
 template <typename E>
 void edges_launch(bool half, int bs, dim3 grid, const LevelTable& T, const unsigned long long* poskey,
                   const int2* boxes, long long inum, long long iden, E* lists, unsigned char* state8, hipStream_t s) {
-    if (half && bs == 64)
-        hipLaunchKernelGGL((hog_nms_edges_kernel<E, true, 64>), grid, dim3(64), 0, s, T, poskey, boxes, inum, iden,
-                           lists, state8);
-    else if (half)
+    int span = 0;
+    for (int k = 0; k < T.n; ++k) span = std::max(span, T.L[k].nms_khi - T.L[k].nms_klo + 1);
+    if (bs == 64 && span > 4) {
+        if (half)
+            hipLaunchKernelGGL((hog_nms_edges_kernel<E, true, 64>), grid, dim3(64), 0, s, T, poskey, boxes, inum,
+                               iden, lists, state8);
+        else
+            hipLaunchKernelGGL((hog_nms_edges_kernel<E, false, 64>), grid, dim3(64), 0, s, T, poskey, boxes, inum,
+                               iden, lists, state8);
+    } else if (bs == 64) {
+        // a few frames: the 4-wave kernel that scans the levels of a
+        // position in parallel (each position's levels span at most 4)
+        if (half)
+            hipLaunchKernelGGL((hog_nms_edges_split_kernel<E, true>), grid, dim3(256), 0, s, T, poskey, boxes, inum,
+                               iden, lists, state8);
+        else
+            hipLaunchKernelGGL((hog_nms_edges_split_kernel<E, false>), grid, dim3(256), 0, s, T, poskey, boxes, inum,
+                               iden, lists, state8);
+    } else if (half) {
         hipLaunchKernelGGL((hog_nms_edges_kernel<E, true, 256>), grid, dim3(256), 0, s, T, poskey, boxes, inum, iden,
                            lists, state8);
-    else if (bs == 64)
-        hipLaunchKernelGGL((hog_nms_edges_kernel<E, false, 64>), grid, dim3(64), 0, s, T, poskey, boxes, inum, iden,
-                           lists, state8);
-    else
+    } else {
         hipLaunchKernelGGL((hog_nms_edges_kernel<E, false, 256>), grid, dim3(256), 0, s, T, poskey, boxes, inum,
                            iden, lists, state8);
+    }
 }
 
 hipError_t launch_nms_edges(const LevelTable& T, int n, const unsigned long long* poskey, const int2* boxes,
