@@ -217,8 +217,9 @@ int hog_tuning_set(int h, int w, int upsample, int n, int nf, const hog_tuning* 
  * HIP events on `stream`), keeps the fastest for this shape as with
  * hog_tuning_set and returns it in `best` with its mean time per call in
  * `best_ms`.  Arguments as hog_detect_batch; blocks the host until done.
- * The candidates: the per-stage schedule with split 1, 2 and 4, 2, 4 or 8
- * NMS rounds and scoring items of 4 or 16 rows, and the fused kernel with 8 or 1 queues, one workgroup per compute unit, and
+ * The candidates: the per-stage schedule with split 1, 2 and 4, 2, 3, 4,
+ * 6, 8 or 12 NMS rounds and scoring items of 4 or 16 rows, and the fused
+ * kernel with 8 or 1 queues, one workgroup per compute unit, and
  * lags (1,2), (1,3), (2,3), (2,4); a candidate that reports an error in
  * any n_dets entry is skipped. */
 int hog_autotune(const hog_params* prm, const uint8_t* frames, int n,

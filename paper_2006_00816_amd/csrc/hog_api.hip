@@ -656,7 +656,7 @@ int hog_autotune(const hog_params* prm, const uint8_t* frames, int n, int h, int
     std::vector<hog_tuning> cand;
     for (int sp : {1, 2, 4}) {
         if (sp > n) break;
-        for (int nr : {2, 4, 8}) {
+        for (int nr : {2, 3, 4, 6, 8, 12}) {
             for (int rows : {SCORE_SMALL_ROWS, ROWS_PER_ITEM}) {
                 cand.push_back(default_tuning(h, w, prm->upsample, n, nf));
                 cand.back().split = sp;
