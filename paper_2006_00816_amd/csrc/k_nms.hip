@@ -509,11 +509,14 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
     unsigned long long* sk = reinterpret_cast<unsigned long long*>(rc_chunks);
     int* rc_pos = reinterpret_cast<int*>(rc_chunks + 4 * RC_CHUNKS);
     unsigned short* rc_first = reinterpret_cast<unsigned short*>(rc_pos + RC_MAXI);
-    unsigned short* rc_wl[2] = {rc_first + RC_MAXI, rc_first + 2 * RC_MAXI};
+    // the two worklists of each kind are addressed by offset, not through an
+    // array of pointers, so that the compiler keeps their address spaces
+    // (LDS / global) instead of generic flat accesses
+    unsigned short* const rc_wl = rc_first + RC_MAXI;   // rc_wl + b * RC_MAXI, b = 0, 1
     __shared__ int s_chunks;
     const unsigned long long* keys = poskey + (long long)frame * P;
     const E* lst = lists + (long long)frame * P * NMS_LIST;
-    int* wl[2] = {work + (long long)frame * 2 * P, work + (long long)frame * 2 * P + P};
+    int* const wl = work + (long long)frame * 2 * P;   // wl + b * P, b = 0, 1
 
     // states left by the parallel rounds, and the worklist of the undecided
     const unsigned char* st8 = state8 + (long long)frame * P;
@@ -534,7 +537,7 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
     __syncthreads();
     for (int p0 = 0; p0 < P; p0 += NMS_THREADS) {
         const int p = p0 + tid;
-        wave_append(p < P && state_of<G>(S, p) == UNDECIDED, p, wl[0], &s_count);
+        wave_append(p < P && state_of<G>(S, p) == UNDECIDED, p, wl, &s_count);
     }
     __syncthreads();
 
@@ -548,7 +551,7 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
             // try to cache the records of the worklist: count their chunks
             if (tid == 0) s_chunks = 0;
             __syncthreads();
-            const int* in = wl[cur];
+            const int* in = wl + (long long)cur * P;
             for (int i = tid; i < n_in; i += NMS_THREADS) {
                 const int p = in[i];
                 const int cnt = (int)lst[(long long)p * CH];
@@ -560,7 +563,7 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
             __syncthreads();
             if (s_chunks <= RC_CHUNKS) {
                 for (int i = tid; i < n_in; i += NMS_THREADS) {
-                    rc_wl[0][i] = (unsigned short)i;
+                    rc_wl[i] = (unsigned short)i;
                     if (rc_first[i] == 0xffff) continue;
                     const E* rec = lst + (long long)rc_pos[i] * CH;
                     const int cnt = (int)rec[0];
@@ -579,7 +582,7 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
         if (tid == 0) s_next = 0;
         __syncthreads();
         if (cached) {
-            const unsigned short* in = rc_wl[cur];
+            const unsigned short* in = rc_wl + cur * RC_MAXI;
             for (int i0 = 0; i0 < n_in; i0 += NMS_THREADS) {
                 const int i = i0 + tid;
                 bool keep_working = false;
@@ -600,10 +603,10 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
                     if (v != UNDECIDED) atomicOr(&S[p >> 4], v << ((p & 15) * 2));
                     else keep_working = true;
                 }
-                wave_append(keep_working, it, rc_wl[cur ^ 1], &s_next);
+                wave_append(keep_working, it, rc_wl + (cur ^ 1) * RC_MAXI, &s_next);
             }
         } else {
-            const int* in = wl[cur];
+            const int* in = wl + (long long)cur * P;
             for (int i0 = 0; i0 < n_in; i0 += RESOLVE_BATCH * NMS_THREADS) {
                 int pp[RESOLVE_BATCH];
                 Rec<E> R[RESOLVE_BATCH];
@@ -627,7 +630,7 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
                         if (v != UNDECIDED) atomicOr(&S[p >> 4], v << ((p & 15) * 2));
                         else keep_working = true;
                     }
-                    wave_append(keep_working, p, wl[cur ^ 1], &s_next);
+                    wave_append(keep_working, p, wl + (long long)(cur ^ 1) * P, &s_next);
                 }
             }
         }
