@@ -59,8 +59,21 @@ def _oracle_worker(args):
     return True
 
 
+def profiler_active(env=None) -> bool:
+    """True when a rocprofiler tool library is preloaded (rocprofv3 sets
+    LD_PRELOAD and ROCPROF* variables): every process started then
+    initialises the GPU under the profiler, so no worker pool may start."""
+    env = os.environ if env is None else env
+    if "rocprof" in env.get("LD_PRELOAD", ""):
+        return True
+    return any(k.startswith(("ROCPROF", "ROCP_")) for k in env)
+
+
 def cpu_baseline(frames, W, b, budget_frames):
-    """The float64 oracle on host cores, one process per frame."""
+    """The float64 oracle on host cores, one process per frame.  Not run
+    under a profiler (returns None without starting a process)."""
+    if profiler_active():
+        return None
     import multiprocessing as mp
     cores = min(len(os.sched_getaffinity(0)), 16, budget_frames)
     sample = [(frames[i % len(frames)], W, b) for i in range(budget_frames)]
@@ -194,6 +207,8 @@ def main():
     wl = synth.config1(seed=1, n=CLIP)
     # the CPU baseline runs first, before this process touches the GPU
     cpu = None if args.no_cpu_baseline else cpu_baseline(wl.frames, wl.W, wl.b, args.cpu_frames)
+    if cpu is None and not args.no_cpu_baseline:
+        print("bench.py: a profiler is preloaded; the CPU-baseline worker pool is not started", file=sys.stderr)
 
     import torch
     from paper_2006_00816_amd import hog355

@@ -96,6 +96,24 @@ typedef struct hog_window {
     int32_t frame, filter, level, row, col;
 } hog_window;
 
+/* The defaults of the detection parameters: upsample 1, thresh 0 (a window
+ * is a face when its score is positive), iou 0.5.  The other constants of
+ * the method are fixed at compile time, because the kernels' tiles are
+ * shaped by them: 8x8-pixel cells and 18 signed orientation bins
+ * (Sec. IV-A, gradient computation and histogramisation), 31 features per
+ * cell and 10x10-cell windows (Sec. IV-A, feature computation and linear
+ * classification), the 5/6 pyramid step down to an 80-px side (Sec. IV-A),
+ * truncation at 0.2 and 1e-4 added to block energies; hog_constants_get
+ * reports them.  Host only; HOG_E_INVAL if p is NULL. */
+int hog_params_default(hog_params* p);
+
+/* The compile-time constants of the method (see hog_params_default). */
+typedef struct hog_constants {
+    int32_t cell_px, bins, features, window_cells, min_side, scale_num, scale_den;
+    float clip, eps;
+} hog_constants;
+int hog_constants_get(hog_constants* c);
+
 /* Version of the library, as major*10000 + minor*100 + patch.  Host only. */
 int hog_version(void);
 
@@ -176,6 +194,14 @@ int hog_graph_create(hog_graph** out, const hog_params* prm, const uint8_t* fram
 int hog_graph_launch(hog_graph* g, void* stream);
 int hog_graph_destroy(hog_graph* g);
 
+/* Set-up of the calling host thread on the current device: the helper
+ * streams and events (default priority) that split schedules fork onto.
+ * hog_tuning_set (for a split schedule) and hog_autotune call it; a detect
+ * call never creates them.  A split schedule run on a thread without them
+ * runs its frame groups one after another on the caller's stream, with
+ * the same detections.  Idempotent.  Host only. */
+int hog_init(void);
+
 /* Schedule of hog_detect_batch for one shape (h, w, upsample, n, nf).
  * fused = 0: one kernel per stage (histograms, features, scores, NMS);
  *   with split = 2..4 the frames run as that many groups on forked
@@ -249,27 +275,46 @@ int hog_orient_bins(const int32_t* gx, const int32_t* gy, int64_t n,
  * n_windows windows.  0 on invalid arguments.  Host only. */
 size_t hog_grad_workspace_bytes(int h, int w, int upsample, int n_frames, int nf, int n_windows);
 
-/* Scores of listed windows (Sec. IV-A, linear classification filter):
+/* Host check of listed windows (host array `windows` of n_windows): every
+ * window must address a frame of the batch (0 <= frame < n), a filter
+ * (0 <= filter < nf), a pyramid level of an h x w frame and an anchor
+ * inside that level (0 <= row < rows, 0 <= col < cols).  Returns HOG_OK, or
+ * HOG_E_INVAL with *first_bad (may be NULL) the index of the first window
+ * that fails.  The kernels below apply the same test to every window they
+ * read.  Host only. */
+int hog_windows_check(int h, int w, int upsample, int n, int nf, const hog_window* windows, int n_windows,
+                      int* first_bad);
+
+/* Scores of listed windows (Sec. IV-A, linear classification filter: the
+ * 3100 features of a 10x10-cell window times the filter weights, summed):
  * scores[i] = bias[f_i] + <filter f_i, 10x10x31 features of window i>.
  * `windows` (device, n_windows) index frames of the batch as in
  * hog_detect_batch; the features are computed from the frames in this
- * call.  Used as the forward pass of filter training. */
+ * call.  Used as the forward pass of filter training.  A window that
+ * fails the test of hog_windows_check is not read and scores NaN. */
 int hog_window_scores(const uint8_t* frames, int n, int h, int w, int pitch, int64_t frame_stride, int upsample,
                       const float* filters, const float* bias, int nf,
                       const hog_window* windows, int n_windows, float* scores,
                       void* ws, size_t ws_bytes, void* stream);
 
 /* The k (1..16) best windows of every frame over all filters, levels and
- * positions, before thresholding and NMS, in rank order (score
- * descending, then filter, level, row, column ascending).  Outputs
- * (device): windows [n][k], scores [n][k]. */
+ * positions, in rank order (score descending, then filter, level, row,
+ * column ascending).  Sec. IV-A scores every 10x10-cell window of every
+ * level with each of the five filters; the selection here reads "the top
+ * window scores" as the k highest of all those scores, taken before the
+ * threshold and before non-maximum suppression, so a frame always has k
+ * windows even when none passes the threshold.  Outputs (device):
+ * windows [n][k], scores [n][k]. */
 int hog_topk_windows(const uint8_t* frames, int n, int h, int w, int pitch, int64_t frame_stride, int upsample,
                      const float* filters, const float* bias, int nf, int k,
                      hog_window* windows, float* scores,
                      void* ws, size_t ws_bytes, void* stream);
 
-/* Backward pass of window scores.  With upstream gradients dscore[i] for
- * windows[i] (device arrays of n_windows):
+/* Backward pass of window scores: every forward step of Sec. IV-A
+ * differentiated in reverse order (linear classification, feature
+ * computation and normalisation, histogramisation, gradient computation,
+ * pyramid resampling).  With upstream gradients dscore[i] for windows[i]
+ * (device arrays of n_windows):
  *   dfilters[f] += sum_i [f_i = f] dscore[i] * features(window i)   (float32 [nf][10][10][31])
  *   dbias[f]    += sum_i [f_i = f] dscore[i]                         (float32 [nf], may be NULL)
  *   dpixels     += sum_i dscore[i] * d score_i / d frame pixels      (float32 [n][h][w], may be NULL)
@@ -278,19 +323,26 @@ int hog_topk_windows(const uint8_t* frames, int n, int h, int w, int pitch, int6
  * nothing is kept from a forward call.  The pixel gradient runs through
  * the clip at 0.2, the block normalisation and energies, the bilinear cell
  * votes, the gradient magnitude (d mag / d g = g / mag, 0 at mag = 0), the
- * central differences and the pyramid resampling, with orientation bins
- * and clip decisions held at their forward values.  dfilters and dbias are
- * summed in a fixed order (deterministic); dpixels with atomic adds. */
+ * central differences and the pyramid resampling.  The orientation bin
+ * and the clip are step functions; their derivative is taken as zero, so
+ * the bins and clip decisions stay at their forward values (exact away
+ * from the switching points).  dfilters and dbias are summed in a fixed
+ * order (deterministic); dpixels with atomic adds.  A window that fails
+ * the test of hog_windows_check is skipped without a read and makes
+ * dfilters[0] NaN. */
 int hog_filter_backward(const uint8_t* frames, int n, int h, int w, int pitch, int64_t frame_stride, int upsample,
                         const float* filters, int nf,
                         const hog_window* windows, const float* dscore, int n_windows,
                         float* dfilters, float* dbias, float* dpixels,
                         void* ws, size_t ws_bytes, void* stream);
 
-/* Mean hinge loss of scores with labels +-1 plus l2 * ||filters||^2
- * (bias not regularised): loss (device float[1]) = mean_i max(0, 1 - y_i s_i)
- * + l2 ||W||^2; dscore[i] = -y_i / n where y_i s_i < 1, else 0; and
- * dfilters += 2 l2 filters.  n <= 2^30. */
+/* Training objective of the linear filter (Sec. IV-A trains one linear
+ * filter per face rotation; the loss is not given there, and this library
+ * takes a linear SVM's): the mean hinge loss of scores with labels +-1
+ * plus l2 * ||filters||^2, the bias not regularised:
+ *   loss (device float[1]) = mean_i max(0, 1 - y_i s_i) + l2 ||W||^2,
+ *   dscore[i] = -y_i / n where y_i s_i < 1, else 0 (at the kink y_i s_i = 1
+ *   the zero subgradient), and dfilters += 2 l2 filters.  n <= 2^30. */
 int hog_hinge_loss(const float* scores, const float* labels, int n, const float* filters, int nf, float l2,
                    float* loss, float* dscore, float* dfilters, void* stream);
 

@@ -305,6 +305,7 @@ hog_tuning lookup_tuning(int h, int w, int u, int n, int nf, bool* found = nullp
 // Pointers of the per-frame workspace regions, starting at frame `lo` of
 // the batch.
 struct FrameBufs {
+    int lo;   // batch index of the group's first frame
     const uint8_t* frames;
     float* hist;
     float* feat;
@@ -322,6 +323,7 @@ FrameBufs frame_bufs(const Plan& P, void* ws, const uint8_t* frames, long long f
     const LevelTable& T = P.T;
     const long long pos = T.pos_frame;
     FrameBufs b;
+    b.lo = lo;
     b.frames = frames + (long long)lo * fstride;
     b.hist = at<float>(ws, P.o_hist) + (long long)lo * T.hist_frame * HSTRIDE;
     b.feat = at<float>(ws, P.o_feat) + (long long)lo * T.feat_frame;
@@ -336,27 +338,36 @@ FrameBufs frame_bufs(const Plan& P, void* ws, const uint8_t* frames, long long f
 }
 
 // Helper streams and events of a host thread for split schedules (default
-// priority), created on first use per device.
+// priority), per device.  hog_init creates them; a detect call only looks
+// them up.
+constexpr int MAX_DEVICES = 64;
 struct SplitRes {
-    int device = -1;
+    bool ready = false;
     hipStream_t st[MAX_SPLIT - 1] = {};
     hipEvent_t ev[MAX_SPLIT] = {};
 };
-thread_local SplitRes g_split;
+thread_local SplitRes g_split[MAX_DEVICES];
 
-int split_resources(SplitRes** out) {
+int init_split_resources() {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return HOG_E_HIP;
-    SplitRes& r = g_split;
-    if (r.device != dev) {
-        for (int j = 0; j < MAX_SPLIT - 1; ++j)
-            if (hipStreamCreateWithFlags(&r.st[j], hipStreamNonBlocking) != hipSuccess) return HOG_E_HIP;
-        for (int j = 0; j < MAX_SPLIT; ++j)
-            if (hipEventCreateWithFlags(&r.ev[j], hipEventDisableTiming) != hipSuccess) return HOG_E_HIP;
-        r.device = dev;
-    }
-    *out = &r;
+    if (dev < 0 || dev >= MAX_DEVICES) return HOG_E_INVAL;
+    SplitRes& r = g_split[dev];
+    if (r.ready) return HOG_OK;
+    for (int j = 0; j < MAX_SPLIT - 1; ++j)
+        if (hipStreamCreateWithFlags(&r.st[j], hipStreamNonBlocking) != hipSuccess) return HOG_E_HIP;
+    for (int j = 0; j < MAX_SPLIT; ++j)
+        if (hipEventCreateWithFlags(&r.ev[j], hipEventDisableTiming) != hipSuccess) return HOG_E_HIP;
+    r.ready = true;
     return HOG_OK;
+}
+
+// The calling thread's helper streams on the current device, or nullptr
+// if hog_init has not created them.
+SplitRes* split_resources() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return nullptr;
+    return g_split[dev].ready ? &g_split[dev] : nullptr;
 }
 
 int nms_chain(const Plan& P, int m, const FrameBufs& b, const hog_params* prm, int cap, const unsigned* upstream,
@@ -376,7 +387,7 @@ int nms_chain(const Plan& P, int m, const FrameBufs& b, const hog_params* prm, i
     }));
     return timed("nms", s, [&] {
         return launch_nms(T, m, b.keys, b.lists, at<int2>(ws, P.o_boxes), num, den, b.dets, cap, b.n_dets, b.gstate,
-                          b.work, b.state8, upstream, fused_need(T, P.nf), s);
+                          b.work, b.state8, upstream, fused_need(T, P.nf), b.lo, s);
     });
 }
 
@@ -432,9 +443,18 @@ int detect_sequence(const Plan& P, const hog_params* prm, const uint8_t* frames,
         return staged_chain(P, P.n, frame_bufs(P, ws, frames, fstride, dets, cap, n_dets, 0), fstride, pitch, prm,
                             bias, cap, tune.nms_rounds, tune.score_rows, ws, s);
     // the frames in `parts` groups on forked streams: one group's NMS
-    // overlaps another's histograms and scores
-    SplitRes* r = nullptr;
-    HOG_TRY(split_resources(&r));
+    // overlaps another's histograms and scores.  Without the calling
+    // thread's helper streams (hog_init) the groups run one after another
+    // on the caller's stream, with the same detections.
+    SplitRes* r = split_resources();
+    if (!r) {
+        for (int j = 0; j < parts; ++j) {
+            const int lo = (int)((long long)j * P.n / parts), hi = (int)((long long)(j + 1) * P.n / parts);
+            HOG_TRY(staged_chain(P, hi - lo, frame_bufs(P, ws, frames, fstride, dets, cap, n_dets, lo), fstride,
+                                 pitch, prm, bias, cap, tune.nms_rounds, tune.score_rows, ws, s));
+        }
+        return HOG_OK;
+    }
     if (hipEventRecord(r->ev[0], s) != hipSuccess) return HOG_E_HIP;
     for (int j = 1; j < parts; ++j)
         if (hipStreamWaitEvent(r->st[j - 1], r->ev[0], 0) != hipSuccess) return HOG_E_HIP;
@@ -473,7 +493,29 @@ struct hog_graph {
 
 extern "C" {
 
-int hog_version(void) { return 100; }
+int hog_version(void) { return 200; }
+
+int hog_params_default(hog_params* p) {
+    if (!p) return HOG_E_INVAL;
+    p->upsample = 1;
+    p->thresh = 0.f;
+    p->iou = 0.5f;
+    return HOG_OK;
+}
+
+int hog_constants_get(hog_constants* c) {
+    if (!c) return HOG_E_INVAL;
+    c->cell_px = CELL;
+    c->bins = NBINS;
+    c->features = NFEAT;
+    c->window_cells = WIN;
+    c->min_side = MIN_SIDE;
+    c->scale_num = 5;
+    c->scale_den = 6;
+    c->clip = 0.2f;
+    c->eps = 1e-4f;
+    return HOG_OK;
+}
 
 const char* hog_strerror(int st) {
     switch (st) {
@@ -631,7 +673,10 @@ int hog_tuning_get(int h, int w, int upsample, int n, int nf, hog_tuning* out) {
     return found ? 1 : 0;
 }
 
+int hog_init(void) { return init_split_resources(); }
+
 int hog_tuning_set(int h, int w, int upsample, int n, int nf, const hog_tuning* t) {
+    if (t && tuning_valid(*t) && t->split > 1) HOG_TRY(init_split_resources());
     std::lock_guard<std::mutex> g(g_tune_mu);
     if (!t) {
         g_tune.erase(ShapeKey{h, w, upsample, n, nf});
@@ -653,6 +698,7 @@ int hog_autotune(const hog_params* prm, const uint8_t* frames, int n, int h, int
     HOG_TRY(check_ws(P, ws, ws_bytes));
     const int cus = compute_units();
     if (cus < 1) return HOG_E_HIP;
+    HOG_TRY(init_split_resources());
     std::vector<hog_tuning> cand;
     for (int sp : {1, 2, 4}) {
         if (sp > n) break;
@@ -772,7 +818,8 @@ int hog_window_scores(const uint8_t* frames, int n, int h, int w, int pitch, int
     hipStream_t s = (hipStream_t)stream;
     HOG_TRY(run_pixels(P, frames, frame_stride, pitch, ws, nullptr, nullptr, s, false));
     return timed("window_scores", s, [&] {
-        return launch_window_scores(P.T, at<float>(ws, P.o_feat), windows, n_windows, filters, bias, scores, s);
+        return launch_window_scores(P.T, n, nf, at<float>(ws, P.o_feat), windows, n_windows, filters, bias, scores,
+                                    s);
     });
 }
 
@@ -817,9 +864,24 @@ int hog_filter_backward(const uint8_t* frames, int n, int h, int w, int pitch, i
         return launch_setup(T, at<int4>(ws, P.o_taps), at<int2>(ws, P.o_boxes), nullptr, 0, nullptr, nullptr, 0, nullptr, 0, s);
     }));
     return timed("backward", s, [&] {
-        return launch_backward(T, frames, frame_stride, pitch, at<int4>(ws, P.o_taps), filters, windows, dscore,
+        return launch_backward(T, n, frames, frame_stride, pitch, at<int4>(ws, P.o_taps), filters, windows, dscore,
                                n_windows, nf, at<float>(ws, P.o_partial), dfilters, dbias, dpixels, s);
     });
+}
+
+int hog_windows_check(int h, int w, int upsample, int n, int nf, const hog_window* windows, int n_windows,
+                      int* first_bad) {
+    if (first_bad) *first_bad = -1;
+    if (n_windows < 0 || (n_windows > 0 && !windows) || nf < 1) return HOG_E_INVAL;
+    Plan P;
+    HOG_TRY(make_plan(h, w, upsample, n, nf, &P));
+    for (int i = 0; i < n_windows; ++i) {
+        if (!window_in_range(P.T, n, nf, windows[i])) {
+            if (first_bad) *first_bad = i;
+            return HOG_E_INVAL;
+        }
+    }
+    return HOG_OK;
 }
 
 int hog_hinge_loss(const float* scores, const float* labels, int n, const float* filters, int nf, float l2,

@@ -124,6 +124,15 @@ __host__ __device__ inline float score_from_order(unsigned int o) {
     unsigned int u = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
     return __builtin_bit_cast(float, u);
 }
+// A listed window addresses frame `frame` of a batch of n, filter `filter`
+// of nf, and an anchor (row, col) of a window of pyramid level `level`.
+__host__ __device__ inline bool window_in_range(const LevelTable& T, int n, int nf, const hog_window& w) {
+    if (w.frame < 0 || w.frame >= n || w.filter < 0 || w.filter >= nf || w.level < 0 || w.level >= T.n)
+        return false;
+    const DevLevel& L = T.L[w.level];
+    return w.row >= 0 && w.row < L.rows && w.col >= 0 && w.col < L.cols;
+}
+
 __host__ __device__ inline unsigned int pack_window(int f, int k, int r, int c) {
     return ((unsigned)f << 27) | ((unsigned)k << 22) | ((unsigned)r << 11) | (unsigned)c;
 }
@@ -159,23 +168,23 @@ hipError_t launch_nms_edges(const LevelTable& T, int n, const unsigned long long
 hipError_t launch_nms(const LevelTable& T, int n, const unsigned long long* poskey, const void* lists,
                       const int2* boxes, long long iou_num, long long iou_den, void* dets, int cap, int* n_dets,
                       unsigned* gstate, int* work, const unsigned char* state8, const unsigned* upstream,
-                      FusedNeed need, hipStream_t s);
+                      FusedNeed need, int frame_base, hipStream_t s);
 hipError_t launch_level_maps(const LevelTable& T, int level, const uint8_t* frame, int pitch,
                              const int4* taps, float* level_px, uint8_t* bins, hipStream_t s);
 hipError_t launch_orient(const int32_t* gx, const int32_t* gy, long long n, uint8_t* bins,
                          hipStream_t s);
 hipError_t launch_fill(int* p, int n, int v, hipStream_t s);
 void orientation_table_host(double* c, double* s);
-hipError_t launch_window_scores(const LevelTable& T, const float* feat, const hog_window* win, int n_win,
-                                const float* W, const float* bias, float* scores, hipStream_t s);
+hipError_t launch_window_scores(const LevelTable& T, int n, int nf, const float* feat, const hog_window* win,
+                                int n_win, const float* W, const float* bias, float* scores, hipStream_t s);
 hipError_t launch_topk(const LevelTable& T, int n, const float* dense, long long dense_frame, int nf, int K,
                        hog_window* out, float* out_scores, hipStream_t s);
 hipError_t launch_hinge(const float* S, const float* y, int n, const float* W, int nw, float lam, float* loss,
                         float* dscore, float* dW, hipStream_t s);
 int backward_groups(int n_win);
 size_t backward_lds_bytes();
-hipError_t launch_backward(const LevelTable& T, const uint8_t* frames, long long fstride, int pitch, const int4* taps,
-                           const float* W, const hog_window* win, const float* dscore, int n_win, int nf,
-                           float* partial, float* dW, float* db, float* dpixels, hipStream_t s);
+hipError_t launch_backward(const LevelTable& T, int n, const uint8_t* frames, long long fstride, int pitch,
+                           const int4* taps, const float* W, const hog_window* win, const float* dscore, int n_win,
+                           int nf, float* partial, float* dW, float* db, float* dpixels, hipStream_t s);
 
 }  // namespace hog

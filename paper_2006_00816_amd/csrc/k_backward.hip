@@ -10,7 +10,10 @@ namespace hog {
 // S = bias_f + <W_f, F[r:r+10, c:c+10, :]> for listed windows, one wave per
 // window, from the padded feature maps; the 3100 products are summed per
 // lane in a fixed order and reduced across the wave in a fixed tree.
-__global__ __launch_bounds__(256) void hog_window_score_kernel(LevelTable T, const float* __restrict__ feat,
+// A window outside the batch (see window_in_range) reads nothing and
+// scores NaN.
+__global__ __launch_bounds__(256) void hog_window_score_kernel(LevelTable T, int n, int nf,
+                                                               const float* __restrict__ feat,
                                                                const hog_window* __restrict__ win, int n_win,
                                                                const float* __restrict__ W,
                                                                const float* __restrict__ bias,
@@ -19,6 +22,10 @@ __global__ __launch_bounds__(256) void hog_window_score_kernel(LevelTable T, con
     const int lane = threadIdx.x & 63;
     if (wi >= n_win) return;
     const hog_window w = win[wi];
+    if (!window_in_range(T, n, nf, w)) {
+        if (lane == 0) scores[wi] = __builtin_nanf("");
+        return;
+    }
     const DevLevel& L = T.L[w.level];
     const float* F = feat + (long long)w.frame * T.feat_frame + L.feat_off;
     const float* Wf = W + (long long)w.filter * WIN * WIN * NFEAT;
@@ -34,11 +41,11 @@ __global__ __launch_bounds__(256) void hog_window_score_kernel(LevelTable T, con
     if (lane == 0) scores[wi] = acc + bias[w.filter];
 }
 
-hipError_t launch_window_scores(const LevelTable& T, const float* feat, const hog_window* win, int n_win,
-                                const float* W, const float* bias, float* scores, hipStream_t s) {
+hipError_t launch_window_scores(const LevelTable& T, int n, int nf, const float* feat, const hog_window* win,
+                                int n_win, const float* W, const float* bias, float* scores, hipStream_t s) {
     if (n_win <= 0) return hipSuccess;
-    hipLaunchKernelGGL(hog_window_score_kernel, dim3((n_win + 3) / 4), dim3(256), 0, s, T, feat, win, n_win, W, bias,
-                       scores);
+    hipLaunchKernelGGL(hog_window_score_kernel, dim3((n_win + 3) / 4), dim3(256), 0, s, T, n, nf, feat, win, n_win, W,
+                       bias, scores);
     return hipGetLastError();
 }
 
@@ -171,10 +178,13 @@ struct BwdShared {
     int4 ty[BP], tx[BP];                             // resampling taps of the region rows / columns
 };
 
+// A window outside the batch (see window_in_range) is skipped without a
+// read and makes the workgroup's partial of dW[0] NaN, so that the filter
+// gradient shows the error.
 __global__ __launch_bounds__(BTHREADS) void hog_backward_kernel(
-    LevelTable T, const uint8_t* __restrict__ frames, long long fstride, int pitch, const int4* __restrict__ taps,
-    const float* __restrict__ W, const hog_window* __restrict__ win, const float* __restrict__ dscore, int n_win,
-    int nf, float* __restrict__ partial, float* __restrict__ dpixels) {
+    LevelTable T, int n, const uint8_t* __restrict__ frames, long long fstride, int pitch,
+    const int4* __restrict__ taps, const float* __restrict__ W, const hog_window* __restrict__ win,
+    const float* __restrict__ dscore, int n_win, int nf, float* __restrict__ partial, float* __restrict__ dpixels) {
     __shared__ BwdShared sm;
     const int tid = threadIdx.x;
     const int w0 = blockIdx.x * BWIN_PER_WG;
@@ -183,6 +193,12 @@ __global__ __launch_bounds__(BTHREADS) void hog_backward_kernel(
 
     for (int wi = w0; wi < min(w0 + BWIN_PER_WG, n_win); ++wi) {
         const hog_window w = win[wi];
+        if (!window_in_range(T, n, nf, w)) {
+            // every thread reads the same record, so the skip is uniform;
+            // element 0 is owned by thread 0, which alone writes it
+            if (tid == 0) P[0] = __builtin_nanf("");
+            continue;
+        }
         const float ds = dscore[wi];
         const DevLevel& L = T.L[w.level];
         const uint8_t* __restrict__ U = frames + (long long)w.frame * fstride;
@@ -454,15 +470,16 @@ __global__ __launch_bounds__(256) void hog_backward_reduce_kernel(const float* _
 
 int backward_groups(int n_win) { return (n_win + BWIN_PER_WG - 1) / BWIN_PER_WG; }
 
-hipError_t launch_backward(const LevelTable& T, const uint8_t* frames, long long fstride, int pitch, const int4* taps,
-                           const float* W, const hog_window* win, const float* dscore, int n_win, int nf,
-                           float* partial, float* dW, float* db, float* dpixels, hipStream_t s) {
+hipError_t launch_backward(const LevelTable& T, int n, const uint8_t* frames, long long fstride, int pitch,
+                           const int4* taps, const float* W, const hog_window* win, const float* dscore, int n_win,
+                           int nf, float* partial, float* dW, float* db, float* dpixels, hipStream_t s) {
     if (n_win <= 0) return hipSuccess;
     const int groups = backward_groups(n_win);
-    hipLaunchKernelGGL(hog_backward_kernel, dim3(groups), dim3(BTHREADS), 0, s, T, frames, fstride,
+    hipLaunchKernelGGL(hog_backward_kernel, dim3(groups), dim3(BTHREADS), 0, s, T, n, frames, fstride,
                        pitch, taps, W, win, dscore, n_win, nf, partial, dpixels);
-    const int n = nf * WIN * WIN * NFEAT + nf;
-    hipLaunchKernelGGL(hog_backward_reduce_kernel, dim3((n + 255) / 256), dim3(256), 0, s, partial, groups, nf, dW, db);
+    const int nw = nf * WIN * WIN * NFEAT + nf;
+    hipLaunchKernelGGL(hog_backward_reduce_kernel, dim3((nw + 255) / 256), dim3(256), 0, s, partial, groups, nf, dW,
+                       db);
     return hipGetLastError();
 }
 

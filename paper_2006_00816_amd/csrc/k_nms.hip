@@ -481,7 +481,8 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
     LevelTable T, const unsigned long long* __restrict__ poskey, const E* __restrict__ lists,
     const int2* __restrict__ boxes, long long inum, long long iden, hog_det* __restrict__ dets, int cap,
     int* __restrict__ n_dets, unsigned* __restrict__ gstate, int* __restrict__ work,
-    const unsigned char* __restrict__ state8, const unsigned* __restrict__ upstream, FusedNeed need, int n) {
+    const unsigned char* __restrict__ state8, const unsigned* __restrict__ upstream, FusedNeed need, int n,
+    int frame_base) {
     extern __shared__ __align__(16) unsigned dyn[];   // [2-bit states (LDS variant)] + record cache
     __shared__ unsigned int hist[256];
     __shared__ int s_count, s_next;
@@ -735,7 +736,7 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
         decode(kk, f, k, r, c);
         const Box b = window_box(T.L[k], boxes, r, c);
         hog_det d;
-        d.frame = frame; d.filter = f; d.level = k; d.row = r; d.col = c;
+        d.frame = frame_base + frame; d.filter = f; d.level = k; d.row = r; d.col = c;
         d.x0 = b.x0; d.y0 = b.y0; d.x1 = b.x1; d.y1 = b.y1;
         d.score = score_from_order((unsigned int)(kk >> 32));
         dets[(long long)frame * cap + e] = d;
@@ -806,7 +807,7 @@ template <typename E>
 void launch_resolve(const LevelTable& T, int n, const unsigned long long* poskey, const void* lists,
                     const int2* boxes, long long iou_num, long long iou_den, void* dets, int cap, int* n_dets,
                     unsigned* gstate, int* work, const unsigned char* state8, const unsigned* upstream,
-                    FusedNeed need, hipStream_t s) {
+                    FusedNeed need, int frame_base, hipStream_t s) {
     const int nw = (T.pos_frame + 15) >> 4;
     if (nw <= NMS_LDS_STATE_WORDS) {
         const size_t lds = sizeof(unsigned) * (size_t)((nw + 3) & ~3) + RC_BYTES;
@@ -814,26 +815,26 @@ void launch_resolve(const LevelTable& T, int n, const unsigned long long* poskey
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL((hog_nms_resolve_kernel<E, false>), dim3(n), dim3(NMS_THREADS), lds, s, T, poskey,
                            (const E*)lists, boxes, iou_num, iou_den, (hog_det*)dets, cap, n_dets, gstate, work,
-                           state8, upstream, need, n);
+                           state8, upstream, need, n, frame_base);
     } else {
         (void)hipFuncSetAttribute((const void*)hog_nms_resolve_kernel<E, true>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, RC_BYTES);
         hipLaunchKernelGGL((hog_nms_resolve_kernel<E, true>), dim3(n), dim3(NMS_THREADS), RC_BYTES, s, T, poskey,
                            (const E*)lists, boxes, iou_num, iou_den, (hog_det*)dets, cap, n_dets, gstate, work,
-                           state8, upstream, need, n);
+                           state8, upstream, need, n, frame_base);
     }
 }
 
 hipError_t launch_nms(const LevelTable& T, int n, const unsigned long long* poskey, const void* lists,
                       const int2* boxes, long long iou_num, long long iou_den, void* dets, int cap, int* n_dets,
                       unsigned* gstate, int* work, const unsigned char* state8, const unsigned* upstream,
-                      FusedNeed need, hipStream_t s) {
+                      FusedNeed need, int frame_base, hipStream_t s) {
     if (nms_wide_lists(T.pos_frame))
         launch_resolve<unsigned>(T, n, poskey, lists, boxes, iou_num, iou_den, dets, cap, n_dets, gstate, work,
-                                 state8, upstream, need, s);
+                                 state8, upstream, need, frame_base, s);
     else
         launch_resolve<unsigned short>(T, n, poskey, lists, boxes, iou_num, iou_den, dets, cap, n_dets, gstate,
-                                       work, state8, upstream, need, s);
+                                       work, state8, upstream, need, frame_base, s);
     return hipGetLastError();
 }
 

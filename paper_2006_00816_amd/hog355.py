@@ -37,6 +37,12 @@ class hog_tuning(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+class hog_constants(ctypes.Structure):
+    _fields_ = [("cell_px", ctypes.c_int32), ("bins", ctypes.c_int32), ("features", ctypes.c_int32),
+                ("window_cells", ctypes.c_int32), ("min_side", ctypes.c_int32), ("scale_num", ctypes.c_int32),
+                ("scale_den", ctypes.c_int32), ("clip", ctypes.c_float), ("eps", ctypes.c_float)]
+
+
 class hog_level(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("h", ctypes.c_int32), ("w", ctypes.c_int32),
                 ("cy", ctypes.c_int32), ("cx", ctypes.c_int32), ("rows", ctypes.c_int32),
@@ -62,6 +68,10 @@ def lib():
     f32 = ctypes.c_float
     sig = {
         "hog_version": ([], i32),
+        "hog_init": ([], i32),
+        "hog_params_default": ([vp], i32),
+        "hog_constants_get": ([vp], i32),
+        "hog_windows_check": ([i32, i32, i32, i32, i32, vp, i32, vp], i32),
         "hog_strerror": ([i32], ctypes.c_char_p),
         "hog_orientation_table": ([vp, vp], i32),
         "hog_pyramid": ([i32, i32, i32, i32, vp, i32, vp], i32),
@@ -114,7 +124,30 @@ def _ptr(t: torch.Tensor):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _fptr(t: torch.Tensor):
+    """Pointer to uint8 frames whose rows may be padded: unit stride along
+    a row; the row pitch and the frame stride come from the tensor's
+    strides (the library checks them)."""
+    if not t.is_cuda:
+        raise HogError("expected a device tensor")
+    if t.dtype != torch.uint8 or t.stride(-1) != 1 or any(st < 0 for st in t.stride()):
+        raise HogError("frames must be uint8 with unit stride along a row")
+    return ctypes.c_void_p(t.data_ptr())
+
+
 # ------------------------------------------------------------ host helpers
+def params_default():
+    p = hog_params()
+    _check(lib().hog_params_default(ctypes.byref(p)), "hog_params_default")
+    return {"upsample": int(p.upsample), "thresh": float(p.thresh), "iou": float(p.iou)}
+
+
+def constants():
+    c = hog_constants()
+    _check(lib().hog_constants_get(ctypes.byref(c)), "hog_constants_get")
+    return {k: getattr(c, k) for k, _ in hog_constants._fields_}
+
+
 def orientation_table():
     c = (ctypes.c_double * 9)()
     s = (ctypes.c_double * 9)()
@@ -175,7 +208,7 @@ def features(frame: torch.Tensor, upsample: int = 1, ws=None):
     total = sum(l["cy"] * l["cx"] * 31 for l in levels)
     out = torch.empty(max(total, 1), dtype=torch.float32, device=frame.device)
     wp, wn = _ws(ws, workspace_bytes(h, w, upsample, 1, 0))
-    _check(lib().hog_features(_ptr(frame), h, w, pitch, upsample, _ptr(out), out.numel(), wp, wn, _stream()),
+    _check(lib().hog_features(_fptr(frame), h, w, pitch, upsample, _ptr(out), out.numel(), wp, wn, _stream()),
            "hog_features")
     return [(l, out[l["feat_offset"]:l["feat_offset"] + l["cy"] * l["cx"] * 31].view(l["cy"], l["cx"], 31))
             for l in levels]
@@ -189,7 +222,7 @@ def scores(frame: torch.Tensor, W: torch.Tensor, b: torch.Tensor, upsample: int 
     total = sum(nf * l["rows"] * l["cols"] for l in levels)
     out = torch.empty(max(total, 1), dtype=torch.float32, device=frame.device)
     wp, wn = _ws(ws, workspace_bytes(h, w, upsample, 1, nf))
-    _check(lib().hog_scores(_ptr(frame), h, w, pitch, upsample, _ptr(W), _ptr(b), nf, _ptr(out), out.numel(),
+    _check(lib().hog_scores(_fptr(frame), h, w, pitch, upsample, _ptr(W), _ptr(b), nf, _ptr(out), out.numel(),
                             wp, wn, _stream()), "hog_scores")
     return [(l, out[l["score_offset"]:l["score_offset"] + nf * l["rows"] * l["cols"]]
              .view(nf, l["rows"], l["cols"])) for l in levels]
@@ -210,7 +243,7 @@ def detect_batch_into(frames: torch.Tensor, W: torch.Tensor, b: torch.Tensor, de
     nf = int(W.shape[0])
     prm = _params(thresh, iou, upsample)
     wp, wn = _ws(ws, workspace_bytes(h, w, upsample, n, nf))
-    _check(lib().hog_detect_batch(ctypes.byref(prm), _ptr(frames), n, h, w, int(frames.stride(1)),
+    _check(lib().hog_detect_batch(ctypes.byref(prm), _fptr(frames), n, h, w, int(frames.stride(1)),
                                   int(frames.stride(0)), _ptr(W), _ptr(b), nf, _ptr(dets), cap, _ptr(n_dets),
                                   wp, wn, _stream()), "hog_detect_batch")
 
@@ -238,7 +271,7 @@ def detect(frame: torch.Tensor, W, b, thresh=0.0, iou=0.5, upsample=1, cap=MAX_D
     dets, nd = alloc_dets(1, cap, frame.device)
     prm = _params(thresh, iou, upsample)
     wp, wn = _ws(ws, workspace_bytes(h, w, upsample, 1, nf))
-    _check(lib().hog_detect(ctypes.byref(prm), _ptr(frame), h, w, pitch, _ptr(W), _ptr(b), nf, _ptr(dets), cap,
+    _check(lib().hog_detect(ctypes.byref(prm), _fptr(frame), h, w, pitch, _ptr(W), _ptr(b), nf, _ptr(dets), cap,
                             _ptr(nd), wp, wn, _stream()), "hog_detect")
     out, cnt = dets_to_numpy(dets, nd)
     return out[0], int(cnt[0])
@@ -278,7 +311,7 @@ def autotune(frames: torch.Tensor, W, b, cap=MAX_DETS, thresh=0.0, iou=0.5, upsa
     wp, wn = _ws(ws, workspace_bytes(h, w, upsample, n, nf))
     best = hog_tuning()
     ms = ctypes.c_float()
-    _check(lib().hog_autotune(ctypes.byref(prm), _ptr(frames), n, h, w, int(frames.stride(1)), int(frames.stride(0)),
+    _check(lib().hog_autotune(ctypes.byref(prm), _fptr(frames), n, h, w, int(frames.stride(1)), int(frames.stride(0)),
                               _ptr(W), _ptr(b), nf, _ptr(dets), cap, _ptr(nd), wp, wn, reps, ctypes.byref(best),
                               ctypes.byref(ms), _stream()), "hog_autotune")
     return best.as_dict(), float(ms.value)
@@ -300,7 +333,7 @@ class BoundGraph:
         self.prm = _params(thresh, iou, upsample)
         self.handle = ctypes.c_void_p()
         st = stream if stream is not None else torch.cuda.current_stream()
-        _check(lib().hog_graph_create(ctypes.byref(self.handle), ctypes.byref(self.prm), _ptr(frames), n, h, w,
+        _check(lib().hog_graph_create(ctypes.byref(self.handle), ctypes.byref(self.prm), _fptr(frames), n, h, w,
                                       int(frames.stride(1)), int(frames.stride(0)), _ptr(W), _ptr(b), nf, _ptr(dets),
                                       int(dets.shape[1]), _ptr(n_dets), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                       ctypes.c_void_p(st.cuda_stream)), "hog_graph_create")
@@ -335,7 +368,7 @@ class DetectGraph:
         self.stream = torch.cuda.Stream(device=frames.device)
         self.handle = ctypes.c_void_p()
         torch.cuda.synchronize(frames.device)
-        _check(lib().hog_graph_create(ctypes.byref(self.handle), ctypes.byref(self.prm), _ptr(frames), n, h, w,
+        _check(lib().hog_graph_create(ctypes.byref(self.handle), ctypes.byref(self.prm), _fptr(frames), n, h, w,
                                       int(frames.stride(1)), int(frames.stride(0)), _ptr(W), _ptr(b), nf,
                                       _ptr(self.dets), cap, _ptr(self.n_dets), ctypes.c_void_p(self.ws.data_ptr()),
                                       self.ws.numel(), ctypes.c_void_p(self.stream.cuda_stream)),
@@ -364,7 +397,7 @@ def level_maps(frame: torch.Tensor, level: int, upsample: int = 1, ws=None):
     bins = torch.empty((lv["h"], lv["w"]), dtype=torch.uint8, device=frame.device)
     hist = torch.empty((lv["cy"], lv["cx"], 18), dtype=torch.float32, device=frame.device)
     wp, wn = _ws(ws, workspace_bytes(h, w, upsample, 1, 0))
-    _check(lib().hog_level_maps(_ptr(frame), h, w, pitch, upsample, level, _ptr(px), _ptr(bins), _ptr(hist),
+    _check(lib().hog_level_maps(_fptr(frame), h, w, pitch, upsample, level, _ptr(px), _ptr(bins), _ptr(hist),
                                 wp, wn, _stream()), "hog_level_maps")
     return px, bins, hist
 
@@ -399,14 +432,33 @@ def windows_tensor(frame, filt, level, row, col, device="cuda"):
     return torch.stack(cols, 1).contiguous().to(device)
 
 
-def window_scores(frames: torch.Tensor, W, b, windows: torch.Tensor, upsample: int = 1, ws=None):
+def windows_check(windows: torch.Tensor, n: int, h: int, w: int, nf: int, upsample: int = 1):
+    """Raises HogError unless every hog_window record (int32 [m][5], any
+    device) addresses a frame of the batch, a filter, a level and an anchor
+    inside that level (the library's own test, run on a host copy)."""
+    if windows.dtype != torch.int32 or windows.dim() != 2 or windows.shape[1] != 5:
+        raise HogError("windows must be int32 [m][5] hog_window records")
+    host = windows.detach().to("cpu").contiguous()
+    bad = ctypes.c_int(-1)
+    st = lib().hog_windows_check(h, w, upsample, n, nf, ctypes.c_void_p(host.data_ptr()), int(host.shape[0]),
+                                 ctypes.byref(bad))
+    if st != HOG_OK:
+        i = bad.value
+        rec = host[i].tolist() if 0 <= i < host.shape[0] else None
+        raise HogError(f"hog_windows_check: window {i} {rec} is outside the batch ({st})")
+
+
+def window_scores(frames: torch.Tensor, W, b, windows: torch.Tensor, upsample: int = 1, ws=None,
+                  check: bool = True):
     """Scores of the listed windows (int32 [m][5] hog_window records)."""
     n, h, w, pitch, stride = _frames_args(frames)
     m = int(windows.shape[0])
     nf = int(W.shape[0])
+    if check:
+        windows_check(windows, n, h, w, nf, upsample)
     out = torch.empty(m, dtype=torch.float32, device=frames.device)
     wp, wn = _ws(ws, grad_workspace_bytes(h, w, upsample, n, nf, m))
-    _check(lib().hog_window_scores(_ptr(frames), n, h, w, pitch, stride, upsample, _ptr(W), _ptr(b), nf,
+    _check(lib().hog_window_scores(_fptr(frames), n, h, w, pitch, stride, upsample, _ptr(W), _ptr(b), nf,
                                    _ptr(windows), m, _ptr(out), wp, wn, _stream()), "hog_window_scores")
     return out
 
@@ -418,22 +470,24 @@ def topk_windows(frames: torch.Tensor, W, b, k: int = 10, upsample: int = 1, ws=
     win = torch.empty((n, k, 5), dtype=torch.int32, device=frames.device)
     sc = torch.empty((n, k), dtype=torch.float32, device=frames.device)
     wp, wn = _ws(ws, grad_workspace_bytes(h, w, upsample, n, nf, 1))
-    _check(lib().hog_topk_windows(_ptr(frames), n, h, w, pitch, stride, upsample, _ptr(W), _ptr(b), nf, k,
+    _check(lib().hog_topk_windows(_fptr(frames), n, h, w, pitch, stride, upsample, _ptr(W), _ptr(b), nf, k,
                                   _ptr(win), _ptr(sc), wp, wn, _stream()), "hog_topk_windows")
     return win, sc
 
 
 def filter_backward(frames: torch.Tensor, W, windows: torch.Tensor, dscore: torch.Tensor, upsample: int = 1,
-                    pixels: bool = False, dW=None, db=None, ws=None):
+                    pixels: bool = False, dW=None, db=None, ws=None, check: bool = True):
     """(dW, db, dpixels or None) for upstream score gradients dscore [m]."""
     n, h, w, pitch, stride = _frames_args(frames)
     m = int(windows.shape[0])
     nf = int(W.shape[0])
+    if check:
+        windows_check(windows, n, h, w, nf, upsample)
     dW = torch.zeros_like(W) if dW is None else dW
     db = torch.zeros(nf, dtype=torch.float32, device=frames.device) if db is None else db
     dpix = torch.zeros((n, h, w), dtype=torch.float32, device=frames.device) if pixels else None
     wp, wn = _ws(ws, grad_workspace_bytes(h, w, upsample, n, nf, m))
-    _check(lib().hog_filter_backward(_ptr(frames), n, h, w, pitch, stride, upsample, _ptr(W), nf, _ptr(windows),
+    _check(lib().hog_filter_backward(_fptr(frames), n, h, w, pitch, stride, upsample, _ptr(W), nf, _ptr(windows),
                                      _ptr(dscore), m, _ptr(dW), _ptr(db), _ptr(dpix) if pixels else None, wp, wn,
                                      _stream()), "hog_filter_backward")
     return dW, db, dpix
@@ -467,6 +521,33 @@ class HogScore(torch.autograd.Function):
         dW, db, _ = filter_backward(frames, W.detach().contiguous(), windows, dscore.contiguous().float(),
                                     ctx.upsample)
         return dW, db, None, None, None
+
+
+class HogPixelScore(torch.autograd.Function):
+    """Window scores as a differentiable function of the frame pixels, the
+    filters and the bias.  ``pixels`` is a float tensor [n][h][w] holding
+    integer grey levels 0..255 (the detector's input is 8-bit); forward
+    hog_window_scores on those frames, backward hog_filter_backward with
+    the pixel gradient (orientation bins and clip decisions held at their
+    forward values)."""
+
+    @staticmethod
+    def forward(ctx, pixels, W, b, windows, upsample=1):
+        if pixels.dim() != 3 or not pixels.is_floating_point():
+            raise HogError("pixels must be a float [n][h][w] tensor of grey levels")
+        frames = pixels.detach().round().clamp(0, 255).to(torch.uint8)
+        if not torch.equal(frames.to(pixels.dtype), pixels.detach()):
+            raise HogError("pixels must hold integer grey levels in 0..255")
+        ctx.save_for_backward(W, frames, windows)
+        ctx.upsample = upsample
+        return window_scores(frames, W.detach().contiguous(), b.detach().contiguous(), windows, upsample)
+
+    @staticmethod
+    def backward(ctx, dscore):
+        W, frames, windows = ctx.saved_tensors
+        dW, db, dpix = filter_backward(frames, W.detach().contiguous(), windows, dscore.contiguous().float(),
+                                       ctx.upsample, pixels=ctx.needs_input_grad[0])
+        return dpix, dW, db, None, None
 
 
 def pixel_gradient(frames: torch.Tensor, W, windows: torch.Tensor, dscore: torch.Tensor, upsample: int = 1):

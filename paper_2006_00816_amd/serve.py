@@ -38,6 +38,7 @@ class Request:
     frame: torch.Tensor          # pinned host uint8 [h][w]
     arrival: float               # seconds on the server clock
     done: float = -1.0
+    batch_index: int = -1        # position in the batch it ran in (its detections' frame field)
     n_dets: int = 0
     dets: np.ndarray = None
 
@@ -117,6 +118,7 @@ class HogServer:
                 t = now_fn()
                 for i, r in enumerate(slot.batch):
                     r.done = t
+                    r.batch_index = i
                     r.n_dets = int(slot.h_n[i])
                     m = min(r.n_dets, self.cap)
                     r.dets = slot.h_dets[i, :m].numpy().copy().view(hog355.DET_DTYPE).reshape(m)

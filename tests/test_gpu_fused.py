@@ -9,7 +9,7 @@ import pytest
 import torch
 
 from paper_2006_00816_amd import synth
-from test_gpu_batch import _same
+from test_gpu_batch import _assert_frames_numbered, _same
 from test_gpu_parity import H, cu  # noqa: F401
 
 pytestmark = pytest.mark.gpu
@@ -28,8 +28,12 @@ def _run(H, fr, W, b, tuning, upsample=1):
 
 
 def _assert_same(a, b, n):
+    """Same counts and detections in every field; frame i of each batch
+    numbered i."""
     (da, na), (db, nb) = a, b
     assert np.array_equal(na, nb), (na, nb)
+    _assert_frames_numbered(da)
+    _assert_frames_numbered(db)
     for i in range(n):
         assert _same(da[i], db[i]), i
 
@@ -75,6 +79,28 @@ def test_split_rounds_rows_equal_staged(H, split, n, rounds, rows):
     ref = _run(H, fr, W, b, {**STAGED, "score_rows": 16})
     got = _run(H, fr, W, b, {**STAGED, "split": split, "nms_rounds": rounds, "score_rows": rows})
     _assert_same(got, ref, n)
+
+
+@pytest.mark.parametrize("split", [2, 4])
+def test_split_clip_64_frames_numbered(H, split):
+    """The 64-frame 640x480 clip under split schedules (frame groups on
+    forked streams, eager and graph-replayed): every field of every
+    detection equals the single-group schedule's, frame index included."""
+    wl = synth.config1(seed=1, n=64)
+    fr, W, b = cu(wl.frames), cu(wl.W), cu(wl.b)
+    print(f"split={split} n=64", flush=True)
+    ref = _run(H, fr, W, b, STAGED)
+    got = _run(H, fr, W, b, {**STAGED, "split": split})
+    _assert_same(got, ref, 64)
+    H.tuning_set(480, 640, 1, 64, 5, {**STAGED, "split": split})
+    try:
+        g = H.DetectGraph(fr, W, b)
+        g.launch()
+        torch.cuda.synchronize()
+        _assert_same(H.dets_to_numpy(g.dets, g.n_dets), ref, 64)
+        g.close()
+    finally:
+        H.tuning_set(480, 640, 1, 64, 5, None)
 
 
 def test_split_graph_replay(H):
@@ -128,3 +154,31 @@ def test_autotune_keeps_detections(H):
     got = H.detect_batch(fr, W, b)
     _assert_same(got, ref, 8)
     H.tuning_set(480, 640, 1, 8, 5, None)
+
+
+def test_split_on_thread_without_helper_streams(H):
+    """A host thread that never ran hog_init has no helper streams: the
+    split schedule then runs its frame groups in order on the caller's
+    stream, with the same detections."""
+    import threading
+    wl = synth.config1(seed=26, n=6)
+    fr, W, b = cu(wl.frames), cu(wl.W), cu(wl.b)
+    ref = _run(H, fr, W, b, STAGED)
+    H.tuning_set(480, 640, 1, 6, 5, {**STAGED, "split": 3})
+    out = {}
+
+    def work():
+        try:
+            out["got"] = H.detect_batch(fr, W, b)
+            torch.cuda.synchronize()
+        except Exception as e:   # reported below
+            out["err"] = e
+
+    try:
+        t = threading.Thread(target=work)
+        t.start()
+        t.join(120)
+    finally:
+        H.tuning_set(480, 640, 1, 6, 5, None)
+    assert "err" not in out, out.get("err")
+    _assert_same(out["got"], ref, 6)

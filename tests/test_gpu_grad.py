@@ -188,3 +188,87 @@ def test_config4_frame_topk_and_pixel_gradient(H):
     assert scale > 0
     err = np.abs(dpix - g)
     assert np.all(err <= 1e-4 * np.abs(g) + 1e-5 * scale), (float(err.max()), scale)
+
+
+def test_hinge_kernel_hand_case(H):
+    """The hand case of the oracle pins on the GPU: loss 0.240031, score
+    gradient (0, -0.2, 0.2, 0, 0) with zero at the kink, dW = 2e-4 W."""
+    S = cu(np.array([2.0, 0.5, -0.3, -2.0, 1.0], np.float32))
+    y = cu(np.array([1.0, 1.0, -1.0, -1.0, 1.0], np.float32))
+    W = cu(np.full((1, 10, 10, 31), 0.01, np.float32))
+    loss, dscore, dW = H.hinge_loss(S, y, W, 1e-4)
+    assert abs(float(loss.item()) - 0.240031) <= 1e-6
+    assert np.array_equal(dscore.cpu().numpy(), np.array([0.0, -0.2, 0.2, 0.0, 0.0], np.float32))
+    assert np.allclose(dW.cpu().numpy(), 2e-6, rtol=1e-6, atol=0)
+
+
+def test_topk_includes_sub_threshold_windows(H):
+    """Constant 80x96 frame: every window of filter f scores b_f (3 window
+    anchors per filter).  With b = (0.3, -0.5, 0.2, -0.1) the top 10 are
+    filter 0's three windows, filter 2's, filter 3's (below the threshold)
+    and the first of filter 1's."""
+    fr = cu(np.full((1, 80, 96), 140, np.uint8))
+    W, _ = synth.filters([11, 12, 13, 14])
+    b = np.array([0.3, -0.5, 0.2, -0.1], np.float32)
+    win, sc = H.topk_windows(fr, cu(W), cu(b), 10)
+    got = [tuple(x) for x in win.cpu().numpy()[0].tolist()]
+    want = [(0, f, 0, 0, c) for f in (0, 2, 3) for c in range(3)] + [(0, 1, 0, 0, 0)]
+    assert got == want
+    assert np.array_equal(sc.cpu().numpy()[0], np.repeat(b[[0, 2, 3, 1]], [3, 3, 3, 1]))
+    ow = oracle.top_windows(np.full((80, 96), 140, np.uint8), W, b, 10)
+    assert [(0, int(r["f"]), int(r["k"]), int(r["r"]), int(r["c"])) for r in ow] == want
+
+
+def test_out_of_range_windows_are_skipped(H):
+    """Windows outside the batch are refused by the binding, and through the
+    raw C ABI the kernels skip them without reading: their scores are NaN,
+    the other scores are unchanged, and dfilters[0] turns NaN."""
+    import ctypes
+    frames, u = _small_frames()[0]
+    W, b = synth.filters([201, 202])
+    Wt, bt = cu(W), cu(b)
+    fr = cu(frames[None])
+    lv = oracle.pyramid(*frames.shape, u)
+    good = [[0, 0, 0, 0, 0], [0, 1, len(lv) - 1, lv[-1].rows - 1, lv[-1].cols - 1]]
+    bad = [[1, 0, 0, 0, 0], [0, 2, 0, 0, 0], [0, 0, len(lv), 0, 0], [0, 0, 0, lv[0].rows, 0],
+           [0, 0, 0, 0, -1], [-5, 0, 0, 0, 0]]
+    win = torch.tensor(good + bad, dtype=torch.int32, device="cuda")
+    with pytest.raises(H.HogError):
+        H.window_scores(fr, Wt, bt, win)
+    s = H.window_scores(fr, Wt, bt, win, check=False).cpu().numpy()
+    ref = H.window_scores(fr, Wt, bt, win[:2].contiguous()).cpu().numpy()
+    assert np.array_equal(s[:2], ref) and np.all(np.isnan(s[2:]))
+    ds = torch.ones(len(good) + len(bad), device="cuda")
+    with pytest.raises(H.HogError):
+        H.filter_backward(fr, Wt, win, ds)
+    dW, db, dpix = H.filter_backward(fr, Wt, win, ds, pixels=True, check=False)
+    dW_ok, db_ok, dpix_ok = H.filter_backward(fr, Wt, win[:2].contiguous(), ds[:2].contiguous(), pixels=True)
+    torch.cuda.synchronize()
+    assert np.isnan(dW.view(-1)[0].item())
+    assert torch.equal(db, db_ok)
+    assert torch.allclose(dpix, dpix_ok, rtol=1e-5, atol=1e-7)
+
+
+def test_pixel_autograd_function(H):
+    """HogPixelScore: autograd reaches the pixels, the filters and the bias;
+    the pixel gradient of the summed top-10 scores equals the oracle's."""
+    frame, u = _small_frames()[0]
+    W, b = synth.filters([201, 202])
+    win, _ = H.topk_windows(cu(frame[None]), cu(W), cu(b), 10, u)
+    win = win.reshape(-1, 5).contiguous()
+    px = cu(frame[None].astype(np.float32)).requires_grad_(True)
+    Wt = cu(W).requires_grad_(True)
+    bt = cu(b).requires_grad_(True)
+    s = H.HogPixelScore.apply(px, Wt, bt, win, u)
+    s.sum().backward()
+    recs = win.cpu().numpy()
+    ow = np.zeros(10, oracle.CAND_DTYPE)
+    ow["f"], ow["k"], ow["r"], ow["c"] = recs[:, 1], recs[:, 2], recs[:, 3], recs[:, 4]
+    want, _ = oracle.topk_pixel_grad(frame, W, b, 10, u, windows=ow)
+    g = px.grad.cpu().numpy()[0].astype(np.float64)
+    scale = np.abs(want).max()
+    assert np.all(np.abs(g - want) <= 1e-4 * np.abs(want) + 1e-5 * scale), float(np.abs(g - want).max())
+    dW, db, _ = H.filter_backward(cu(frame[None]), cu(W), win, torch.ones(10, device="cuda"), u)
+    assert torch.equal(Wt.grad, dW) and torch.equal(bt.grad, db)
+    with pytest.raises(H.HogError):
+        H.HogPixelScore.apply(px.detach() + 0.5, Wt, bt, win, u)

@@ -20,6 +20,7 @@ def test_served_results_equal_alone(H):
         alone, n = H.detect(r.frame.cuda(), W, b, cap=256)
         assert r.n_dets == n
         assert len(r.dets) == len(alone)
+        assert np.all(r.dets["frame"] == r.batch_index) and np.all(alone["frame"] == 0)
         for f in ("filter", "level", "row", "col", "x0", "y0", "x1", "y1"):
             assert np.array_equal(r.dets[f], alone[f]), (r.rid, f)
         assert np.array_equal(r.dets["score"].view(np.int32), alone["score"].view(np.int32))

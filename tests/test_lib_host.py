@@ -130,3 +130,41 @@ def test_tuning_table_roundtrip_and_validation(L):
     assert hog355.tuning_get(*shape)[0] == want
     hog355.tuning_set(*shape, None)
     assert not hog355.tuning_get(*shape)[1]
+
+
+def test_params_default_and_constants(L):
+    from paper_2006_00816_amd import hog355
+    assert hog355.params_default() == {"upsample": 1, "thresh": 0.0, "iou": 0.5}
+    c = hog355.constants()
+    assert (c["cell_px"], c["bins"], c["features"], c["window_cells"], c["min_side"]) == (
+        oracle.CELL, oracle.NBINS, oracle.NFEAT, oracle.WIN, oracle.MIN_SIDE)
+    assert (c["scale_num"], c["scale_den"]) == (oracle.SCALE_NUM, oracle.SCALE_DEN)
+    assert c["clip"] == np.float32(oracle.CLIP) and c["eps"] == np.float32(oracle.EPS)
+    assert L.hog_params_default(None) == -1 and L.hog_constants_get(None) == -1
+
+
+def test_windows_check_range(L):
+    """The window range test the kernels apply, run on host records: every
+    field at its first invalid value on either side is rejected, and the
+    index of the first bad record is reported."""
+    import torch
+    from paper_2006_00816_amd import hog355
+    h, w, u, n, nf = 240, 320, 1, 3, 2
+    lv = oracle.pyramid(h, w, u)
+    ok = [[0, 0, 0, 0, 0], [n - 1, nf - 1, len(lv) - 1, lv[-1].rows - 1, lv[-1].cols - 1],
+          [1, 1, 0, lv[0].rows - 1, lv[0].cols - 1]]
+    hog355.windows_check(torch.tensor(ok, dtype=torch.int32), n, h, w, nf, u)
+    bad = [[-1, 0, 0, 0, 0], [n, 0, 0, 0, 0], [0, -1, 0, 0, 0], [0, nf, 0, 0, 0], [0, 0, -1, 0, 0],
+           [0, 0, len(lv), 0, 0], [0, 0, 0, -1, 0], [0, 0, 0, lv[0].rows, 0], [0, 0, 0, 0, -1],
+           [0, 0, 0, 0, lv[0].cols], [0, 0, len(lv) - 1, lv[-1].rows, 0], [0, 0, len(lv) - 1, 0, lv[-1].cols]]
+    for rec in bad:
+        arr = torch.tensor(ok + [rec] + ok, dtype=torch.int32)
+        first = ctypes.c_int(-7)
+        host = arr.contiguous()
+        st = L.hog_windows_check(h, w, u, n, nf, ctypes.c_void_p(host.data_ptr()), int(host.shape[0]),
+                                 ctypes.byref(first))
+        assert st == -1 and first.value == len(ok), (rec, st, first.value)
+        with pytest.raises(hog355.HogError):
+            hog355.windows_check(arr, n, h, w, nf, u)
+    assert L.hog_windows_check(h, w, u, n, nf, None, 0, None) == 0
+    assert L.hog_windows_check(h, w, u, n, nf, None, 1, None) == -1

@@ -194,6 +194,101 @@ def test_ramp_closed_form_features(a, b):
             assert np.allclose(F[i, j], want, rtol=0, atol=1e-12)
 
 
+# ------------------------------------ unclipped normalisation, by hand
+def test_unclipped_normaliser_hand_pattern():
+    """A 3x3-cell histogram in which no normalised value reaches the 0.2
+    clip, so the 1e-4 term and the grouping of the energies into four 2x2
+    blocks set the centre cell's features.  Centre cell (1, 1): all 18
+    bins = v, so its energy is 9 (2v)^2 = 36 v^2.  Top-left cell (0, 0):
+    one bin = t, energy t^2.  Every other cell is empty.  The centre's
+    blocks are (-1,-1) = {(0,0), (0,1), (1,0), (1,1)}, which holds both
+    energies, and (-1,+1), (+1,-1), (+1,+1), which hold only its own:
+      n_0 = (36 v^2 + t^2 + 1e-4)^-1/2,  n_1 = n_2 = n_3 = (36 v^2 + 1e-4)^-1/2.
+    With v = 1e-3 and t = 5e-3: n_0 = 1/sqrt(1.61e-4) = 78.8110...,
+    n_k = 1/sqrt(1.36e-4) = 85.7492..., so v n_k ~ 0.08 and 2 v n_k ~ 0.17,
+    all below 0.2, and
+      signed   F[b]      = (v n_0 + 3 v n_1) / 2                = 0.168029...
+      unsigned F[18 + o] = (2 v n_0 + 6 v n_1) / 2              = 0.336058...
+      energy   F[27]     = 18 v n_0 / sqrt(18) = sqrt(18) v n_0 = 0.334366...
+               F[28..30] = sqrt(18) v n_1                       = 0.363803...
+    (eps outside the square root, or a missing eps, or blocks of a
+    different shape give other numbers)."""
+    v, t = 1e-3, 5e-3
+    hist = np.zeros((3, 3, 18))
+    hist[1, 1, :] = v
+    hist[0, 0, 5] = t
+    F = hog.features_from_hist(hist)[1, 1]
+    n0 = 1 / math.sqrt(36 * v * v + t * t + 1e-4)
+    n1 = 1 / math.sqrt(36 * v * v + 1e-4)
+    assert abs(n0 - 78.81104062391006) < 1e-9 and abs(n1 - 85.74929257125441) < 1e-9
+    assert np.allclose(F[:18], 0.5 * (v * n0 + 3 * v * n1), rtol=0, atol=1e-15)
+    assert np.allclose(F[18:27], 0.5 * (2 * v * n0 + 6 * v * n1), rtol=0, atol=1e-15)
+    assert abs(F[27] - math.sqrt(18) * v * n0) < 1e-15
+    assert np.allclose(F[28:], math.sqrt(18) * v * n1, rtol=0, atol=1e-15)
+    assert abs(F[0] - 0.16802946) < 1e-8 and abs(F[27] - 0.33436693) < 1e-8 and abs(F[28] - 0.36380344) < 1e-8
+
+
+def test_unclipped_low_contrast_ramp_features():
+    """A horizontal ramp of slope 1e-5 grey levels per pixel: gx = 2e-5 and
+    gy = 0 everywhere inside, so every interior cell holds h = 64 * 2e-5 =
+    1.28e-3 in bin 0 (the tent weights of a cell sum to 64) and energy h^2;
+    an interior cell's four blocks each hold 4 h^2.  Then
+    h n = h / sqrt(4 h^2 + 1e-4) = 0.1240012... < 0.2, unclipped, and
+      F[0] = F[18] = 4 h n / 2 = 2 h n,   F[27 + k] = h n / sqrt(18),
+    every other feature 0.  Through the whole image path: resample,
+    gradients, orientation, bilinear votes, energies, blocks, features."""
+    H, W = 96, 120
+    U = 128.0 + 1e-5 * np.tile(np.arange(W, dtype=np.float64), (H, 1))
+    lv = hog.pyramid(H, W)[0]
+    F = hog.level_features(U, lv)
+    h = 64 * 2e-5
+    hn = h / math.sqrt(4 * h * h + 1e-4)
+    assert abs(hn - 0.12400121) < 1e-8
+    want = np.zeros(31)
+    want[0] = want[18] = 2 * hn
+    want[27:] = hn / math.sqrt(18)
+    for i in range(2, lv.cy - 2):
+        for j in range(2, lv.cx - 2):
+            assert np.allclose(F[i, j], want, rtol=1e-9, atol=1e-14), (i, j)
+
+
+# ----------------------------------------------- hinge loss, by hand
+def test_hinge_loss_hand_case():
+    """Scores 2, 0.5, -0.3, -2, 1 with labels +1, +1, -1, -1, +1: the
+    margins 1 - y s are -1, 0.5, 0.7, -1, 0, so the hinge terms are
+    0, 0.5, 0.7, 0, 0 and their mean is 1.2 / 5 = 0.24.  A filter of 3100
+    weights 0.01 has ||W||^2 = 0.31, times 1e-4 = 3.1e-5: loss 0.240031.
+    The score gradient is -y_i / 5 where y_i s_i < 1 (the second and third
+    score), and 0 elsewhere, also at the kink y s = 1 (the fifth)."""
+    S = np.array([2.0, 0.5, -0.3, -2.0, 1.0])
+    y = np.array([1.0, 1.0, -1.0, -1.0, 1.0])
+    W = np.full((1, 10, 10, 31), 0.01)
+    assert abs(hog.hinge_loss(S, y, W, 1e-4) - 0.240031) < 1e-15
+    assert np.array_equal(hog.hinge_dscore(S, y), np.array([0.0, -0.2, 0.2, 0.0, 0.0]))
+
+
+# ------------------------------------ top windows below the threshold
+def test_top_windows_include_sub_threshold_windows():
+    """On a constant frame every feature is 0, so every window of filter f
+    scores b_f.  With b = (0.3, -0.5), filter 0's windows are the only
+    candidates (score > 0); the top k for k beyond their count continue
+    with filter 1's windows, all below the threshold, in (level, row,
+    column) order.  The 120x160 pyramid has levels of 6x11, 3x7 and 1x4
+    window anchors: 91 windows per filter."""
+    U = np.full((120, 160), 77, np.uint8)
+    W = np.random.default_rng(3).normal(0, 0.1, (2, 10, 10, 31))
+    b = np.array([0.3, -0.5])
+    assert [(l.rows, l.cols) for l in hog.pyramid(120, 160)] == [(6, 11), (3, 7), (1, 4)]
+    cand = hog.candidates(U, W, b)
+    assert len(cand) == 91 and np.all(cand["f"] == 0)
+    top = hog.top_windows(U, W, b, k=96)
+    order = [(0, k, r, c) for k, (R, C) in enumerate([(6, 11), (3, 7), (1, 4)])
+             for r in range(R) for c in range(C)]
+    order += [(1, 0, 0, c) for c in range(5)]
+    assert list(zip(top["f"].tolist(), top["k"].tolist(), top["r"].tolist(), top["c"].tolist())) == order
+    assert np.all(top["score"][:91] == 0.3) and np.all(top["score"][91:] == -0.5)
+
+
 # ------------------------------------------------------ P4 cell mass
 def _tent_matrix(n_cells, n_pix):
     c = (np.arange(n_pix) + 0.5) / 8 - 0.5
