@@ -24,31 +24,94 @@ METRIC = "frames/s + p99 frame latency, 640×480 HOG detect, batched vs plain on
 H, W_PX, NF, CLIP = 480, 640, 5, 64
 FP32_PEAK_TFLOPS = 157.3     # MI355X dense FP32 matrix peak
 HBM_PEAK_GBS = 8000.0
+# Vector-ALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one
+# operation per lane per cycle (no packed FP32 in this build)
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Algorithmic vector operations per pyramid pixel of the histogram stage:
+# resample 6 (three 2-tap lerps; none at a scale-1 level, so 6 x 0.69 = 4 on
+# the 640x480 pyramid), central differences 2, magnitude 3, orientation 11
+# (four boundary tests, their signs, the unfold), four weighted votes 8.
+HIST_OPS_PER_PX = 28
+# Per cell of the feature stage: 4 block sums 12, 4 normalisers 8, 27
+# truncated products x 4 blocks 216 (multiply, min, add), 4 energy sums 72.
+FEAT_OPS_PER_CELL = 308
+
+KERNEL_SOURCES = {
+    "hog_hist_kernel": ("hog_internal.h", "hog_device.h", "stage_hist.h", "k_hist.hip"),
+    "hog_score_kernel": ("hog_internal.h", "hog_device.h", "stage_score.h", "k_score.hip"),
+    "hog_sep_score_kernel": ("hog_internal.h", "hog_device.h", "stage_score.h", "k_score.hip"),
+    "hog_feat_kernel": ("hog_internal.h", "hog_device.h", "stage_feat.h", "k_feat.hip"),
+}
 
 
-def score_traffic():
-    """HBM bytes per launch of the scoring kernel from the committed
-    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, calibrated by a
-    plain copy), if the scorer sources are still the ones profiled; else
-    None."""
+def kernel_traffic(kernel):
+    """HBM bytes per launch of a kernel from the committed rocprofv3
+    counter summaries (FETCH_SIZE and WRITE_SIZE, calibrated by a plain
+    copy), if the kernel's sources are still the ones profiled; else None."""
+    import glob
     import hashlib
-    src = b"".join(open(os.path.join(ROOT, "paper_2006_00816_amd", "csrc", f), "rb").read()
-                   for f in ("hog_internal.h", "stage_score.h", "k_score.hip"))
-    sha = hashlib.sha256(src).hexdigest()[:16]
-    path = os.path.join(ROOT, "profiles", "kernels_64x640x480_staged.md")
-    if not os.path.exists(path):
+    if kernel not in KERNEL_SOURCES:
         return None
-    for line in open(path):
-        if line.startswith("score_traffic "):
-            kv = dict(t.split("=", 1) for t in line.split()[1:])
-            if kv.get("sha256_16") == sha:
-                return int(kv["fetch_bytes"]) + int(kv["write_bytes"])
+    src = b"".join(open(os.path.join(ROOT, "paper_2006_00816_amd", "csrc", f), "rb").read()
+                   for f in KERNEL_SOURCES[kernel])
+    sha = hashlib.sha256(src).hexdigest()[:16]
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(path):
+            if line.startswith("traffic "):
+                kv = dict(t.split("=", 1) for t in line.split()[1:])
+                if kv.get("kernel") == kernel and kv.get("sha256_16") == sha:
+                    return int(kv["fetch_bytes"]) + int(kv["write_bytes"])
     return None
 
 
-def windows_per_frame(h, w):
+def pyramid_stats(h, w, nf):
     from paper_2006_00816_amd import hog355
-    return sum(l["rows"] * l["cols"] for l in hog355.pyramid(h, w, 1, NF))
+    lv = hog355.pyramid(h, w, 1, nf)
+    return {"pixels": sum(l["h"] * l["w"] for l in lv), "cells": sum(l["cy"] * l["cx"] for l in lv),
+            "windows": sum(l["rows"] * l["cols"] for l in lv), "levels": len(lv)}
+
+
+def kernel_times(hog355, run, names, steps):
+    """Per kernel: HIP-event launch durations on the launch streams over
+    `steps` eager steps: ms per launch, launches per step, ms per step."""
+    import torch
+    run()
+    torch.cuda.synchronize()
+    hog355.profile_reset()
+    hog355.profile_enable(True)
+    for _ in range(steps):
+        run()
+    torch.cuda.synchronize()
+    res = {}
+    for name in names:
+        ms, cnt = hog355.profile_read(name)
+        if cnt:
+            res[name] = {"ms_per_launch": round(ms / cnt, 5), "launches_per_step": round(cnt / steps, 3),
+                         "ms_per_step": round(ms / steps, 5)}
+    hog355.profile_enable(False)
+    hog355.profile_reset()
+    return res
+
+
+def rooflines(kt, ps, frames, score_flop_per_window, score_kernel):
+    """Roofline entries of the stage kernels: algorithmic work per launch
+    (per-frame work x frames per launch) over the measured launch time."""
+    entries = []
+    defs = [("hist", "hog_hist_kernel", "alu", HIST_OPS_PER_PX * ps["pixels"], VALU_PEAK_TOPS, "Tops/s"),
+            ("feat", "hog_feat_kernel", "alu", FEAT_OPS_PER_CELL * ps["cells"], VALU_PEAK_TOPS, "Tops/s"),
+            ("score", score_kernel, "mfma", score_flop_per_window * ps["windows"], FP32_PEAK_TFLOPS, "TFLOP/s")]
+    for name, kernel, bound, per_frame, peak, unit in defs:
+        if name not in kt:
+            continue
+        t = kt[name]
+        fpl = frames / t["launches_per_step"]
+        work = per_frame * fpl
+        achieved = work / (t["ms_per_launch"] * 1e-3) / 1e12
+        entries.append({"bound": bound, "kernel": kernel, "achieved": round(achieved, 3), "peak": round(peak, 2),
+                        "unit": unit, "frac": round(achieved / peak, 4), "traffic": kernel_traffic(kernel),
+                        "work_per_launch": work, "frames_per_launch": fpl, "avg_launch_ms": t["ms_per_launch"],
+                        "ms_per_step": t["ms_per_step"]})
+    return entries
 
 
 def _oracle_worker(args):
@@ -160,6 +223,36 @@ def pixel_grad_leg(n_frames, chunk):
             "dpix_abs_max_last_chunk": float(dpix.abs().max())}
 
 
+def separable_leg(hog355, frames, rank, steps, warmup, ksteps, ps):
+    """The clip with separable filters (row and column factors, `rank` pairs
+    per channel, 5 filters): graph-replayed frames/s and the scoring
+    kernel's launch time and roofline."""
+    import torch
+    from paper_2006_00816_amd import synth
+    row, col, b = synth.separable_filters(range(101, 106), rank)
+    bank = hog355.FilterBank(torch.from_numpy(b).cuda(), row=torch.from_numpy(row).cuda(),
+                             col=torch.from_numpy(col).cuda())
+    g = hog355.DetectGraph(frames, bank=bank)
+    for _ in range(warmup):
+        g.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.launch()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    g.close()
+    ws = hog355.Workspace()
+    dets, nd = hog355.alloc_dets(CLIP, hog355.MAX_DETS)
+    kt = kernel_times(hog355, lambda: hog355.detect_batch_bank_into(frames, bank, dets, nd, ws=ws),
+                      ("hist", "feat", "score", "nms_edges", "nms"), ksteps) if ksteps else {}
+    # algorithmic work of a separable filter: 10 + 10 multiply-adds per
+    # window, channel (31), pair and filter
+    lines = rooflines(kt, ps, CLIP, 2.0 * 620 * rank * NF, "hog_sep_score_kernel")
+    return {"rank": rank, "fps": round(CLIP * steps / dt, 1), "ms_per_step": round(1e3 * dt / steps, 4),
+            "kernels_per_step": kt, "score_roofline": [e for e in lines if e["kernel"] == "hog_sep_score_kernel"]}
+
+
 def copy_calibration(mib):
     """A plain device-to-device copy of known size, to scale the HBM byte
     counters (FETCH_SIZE, WRITE_SIZE) of the detector's kernels."""
@@ -190,6 +283,8 @@ def main():
                     help="config-4 frames for the pixel-gradient leg (0: skip)")
     ap.add_argument("--schedule", choices=("auto", "staged", "fused"), default="auto",
                     help="auto: run the library's autotuner on the clip first")
+    ap.add_argument("--separable-rank", type=int, default=1,
+                    help="also time the clip with separable filters of this rank (0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run device-to-device copies of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -252,39 +347,14 @@ def main():
     lat = np.array(lat)
     _, n_kept = hog355.dets_to_numpy(g.dets, g.n_dets)
 
-    # kernel durations with HIP events on the launch stream, eager batched steps
+    # kernel durations with HIP events on the launch streams, eager steps of
+    # the timed schedule
     ws = hog355.Workspace()
     dets, nd = hog355.alloc_dets(CLIP, hog355.MAX_DETS)
-    hog355.detect_batch_into(frames, Wt, bt, dets, nd, ws=ws)
-    torch.cuda.synchronize()
-    hog355.profile_reset()
-    hog355.profile_enable(True)
     ksteps = min(args.steps, args.kernel_steps)
-    for _ in range(ksteps):
-        hog355.detect_batch_into(frames, Wt, bt, dets, nd, ws=ws)
-    torch.cuda.synchronize()
-    kern = {}
-    for name in ("geom", "hist", "feat", "score", "fused", "nms_edges", "nms"):
-        ms, cnt = hog355.profile_read(name)
-        if cnt:
-            kern[name] = ms / cnt
-    hog355.profile_enable(False)
-    hog355.profile_reset()
-    # the per-stage kernels, for the scoring kernel's roofline
-    hog355.tuning_set(H, W_PX, 1, CLIP, NF, staged)
-    hog355.detect_batch_into(frames, Wt, bt, dets, nd, ws=ws)
-    torch.cuda.synchronize()
-    hog355.profile_enable(True)
-    for _ in range(ksteps):
-        hog355.detect_batch_into(frames, Wt, bt, dets, nd, ws=ws)
-    torch.cuda.synchronize()
-    staged_kern = {}
-    for name in ("geom", "hist", "feat", "score", "nms_edges", "nms"):
-        ms, cnt = hog355.profile_read(name)
-        staged_kern[name] = ms / max(cnt, 1)
-    hog355.profile_enable(False)
-    hog355.profile_reset()
-    hog355.tuning_set(H, W_PX, 1, CLIP, NF, tuning)
+    names = ("geom", "hist", "feat", "score", "fused", "nms_edges", "nms")
+    kern = kernel_times(hog355, lambda: hog355.detect_batch_into(frames, Wt, bt, dets, nd, ws=ws), names,
+                        ksteps) if ksteps else {}
 
     # ------------------------------------------------------------ plain
     plain_lat = []
@@ -303,13 +373,12 @@ def main():
     plain_lat = np.array(plain_lat if plain_lat else [0.0])
 
     # ----------------------------------------------------------- roofline
-    win = windows_per_frame(H, W_PX)
+    ps = pyramid_stats(H, W_PX, NF)
+    win = ps["windows"]
     flop_per_frame = 2.0 * 3100 * NF * win
-    achieved = flop_per_frame * CLIP / (max(staged_kern["score"], 1e-9) * 1e-3) / 1e12
-    roofline = {"bound": "mfma", "kernel": "hog_score_kernel", "achieved": round(achieved, 2),
-                "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-                "traffic": score_traffic(),
-                "flop_per_launch": flop_per_frame * CLIP, "avg_launch_ms": round(staged_kern["score"], 5)}
+    lines = rooflines(kern, ps, CLIP, 2.0 * 3100 * NF, "hog_score_kernel")
+    # the dominant kernel: most GPU time per step among the stage kernels
+    roofline = max(lines, key=lambda e: e["ms_per_step"]) if lines else None
     # the whole path against the FP32 and HBM rooflines: algorithmic scoring
     # FLOP, and the bytes a frame must cross (frame in, detections out)
     det_bytes = 40.0 * float(np.mean(n_kept))
@@ -332,7 +401,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "64-frame 640x480 u8 clip (config 1), 5 filters 10x10x31 f32, batched hipGraph",
-                   "frames_per_step": CLIP, "h": H, "w": W_PX, "filters": NF, "levels": 10,
+                   "frames_per_step": CLIP, "h": H, "w": W_PX, "filters": NF, "levels": ps["levels"],
                    "windows_per_frame": win, "thresh": 0.0, "iou": 0.5},
         "batched": {"fps": round(fps, 1), "p50_ms": round(float(np.percentile(lat, 50)), 4),
                     "p99_ms": round(float(np.percentile(lat, 99)), 4),
@@ -342,14 +411,16 @@ def main():
                   "p99_ms": round(float(np.percentile(plain_lat, 99)), 4),
                   "latency": "one frame per call, submit to completion"},
         "schedule": {"tuning": tuning, "autotune_best_ms": tune_ms},
-        "kernels_avg_ms_per_64_frames": {k: round(v, 5) for k, v in kern.items()},
-        "staged_kernels_avg_ms_per_64_frames": {k: round(v, 5) for k, v in staged_kern.items()},
+        "kernels_per_step": kern,
         "kept_per_frame_mean": float(np.mean(n_kept)),
         "roofline": roofline,
+        "roofline_kernels": lines,
         "roofline_path": path,
         "paper_context": {"ms_per_frame": 0.333, "hardware": "NVIDIA Titan X (Pascal), 16 images per launch",
                           "end_to_end_ms_per_frame": 0.533},
     }
+    if args.separable_rank > 0:
+        out["separable"] = separable_leg(hog355, frames, args.separable_rank, args.steps, args.warmup, ksteps, ps)
     if args.serve_seconds > 0:
         # served stream: Poisson arrivals, 40/40/20 % 320x240 / 640x480 / 1280x720
         from paper_2006_00816_amd import serve

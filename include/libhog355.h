@@ -156,6 +156,33 @@ int hog_scores(const uint8_t* frame, int h, int w, int pitch, int upsample,
                float* scores, int64_t scores_cap,
                void* ws, size_t ws_bytes, void* stream);
 
+/* A set of nf linear filters with their biases.  rank = 0: full filters
+ * W float32 [nf][10][10][31] (row, column, channel of the window).
+ * rank = 1..4: separable filters.  The paper's classifier kernels
+ * (Sec. V-A) filter each feature channel along the 10 horizontal
+ * neighbours of a cell (row filter, into a scratch image) and then along
+ * the 10 vertical neighbours (column filter), and add the channels: a
+ * filter of that form, or a sum of `rank` of them per channel, is
+ *   W_f[dr][dc][ch] = sum_i col[f][i][dr][ch] * row[f][i][dc][ch],
+ * given as row and col, float32 [nf][rank][10][31].  Scores of a
+ * separable filter equal those of its full W up to float32 rounding (the
+ * sums run in another order); the scoring kernel does 20 rank instead of
+ * 100 multiply-adds per window, channel and filter.  bias float32 [nf].
+ * 1 <= nf <= 32.  Unused pointers may be NULL. */
+typedef struct hog_filterbank {
+    int32_t nf;
+    int32_t rank;
+    const float* W;
+    const float* row;
+    const float* col;
+    const float* bias;
+} hog_filterbank;
+
+/* hog_scores for a filter bank (full or separable). */
+int hog_scores_bank(const uint8_t* frame, int h, int w, int pitch, int upsample,
+                    const hog_filterbank* fb, float* scores, int64_t scores_cap,
+                    void* ws, size_t ws_bytes, void* stream);
+
 /* Detect faces in one frame: features, scores, threshold, box mapping and
  * NMS pooled over filters and levels (Sec. IV-A; Sec. V-A detection kernel
  * and non-maximum suppression).  Writes up to `cap` detections (1 <= cap
@@ -181,6 +208,13 @@ int hog_detect_batch(const hog_params* prm, const uint8_t* frames, int n,
                      hog_det* dets, int cap, int* n_dets,
                      void* ws, size_t ws_bytes, void* stream);
 
+/* hog_detect_batch for a filter bank (full or separable; separable banks
+ * run the per-stage schedule, with the shape's frame split and NMS rounds). */
+int hog_detect_batch_bank(const hog_params* prm, const uint8_t* frames, int n,
+                          int h, int w, int pitch, int64_t frame_stride,
+                          const hog_filterbank* fb, hog_det* dets, int cap, int* n_dets,
+                          void* ws, size_t ws_bytes, void* stream);
+
 /* A hipGraph holding the launches of one hog_detect_batch call with fixed
  * buffers, for replay.  The caller refreshes the frame buffer between
  * replays.  Creation captures on `stream` and returns after instantiation;
@@ -191,6 +225,9 @@ int hog_graph_create(hog_graph** out, const hog_params* prm, const uint8_t* fram
                      const float* filters, const float* bias, int nf,
                      hog_det* dets, int cap, int* n_dets,
                      void* ws, size_t ws_bytes, void* stream);
+int hog_graph_create_bank(hog_graph** out, const hog_params* prm, const uint8_t* frames, int n,
+                          int h, int w, int pitch, int64_t frame_stride, const hog_filterbank* fb,
+                          hog_det* dets, int cap, int* n_dets, void* ws, size_t ws_bytes, void* stream);
 int hog_graph_launch(hog_graph* g, void* stream);
 int hog_graph_destroy(hog_graph* g);
 

@@ -310,6 +310,21 @@ def window_scores(F: np.ndarray, W: np.ndarray, b: np.ndarray) -> np.ndarray:
     return S
 
 
+def separable_filters(row: np.ndarray, col: np.ndarray) -> np.ndarray:
+    """Full filters of row and column factors.  The paper's classifier
+    kernels (Sec. V-A) filter each feature channel along the 10 horizontal
+    neighbours of a cell with one set of weights (row filter, into a
+    scratch image) and then along the 10 vertical neighbours with another
+    (column filter), and add the channels up: a window score is then
+    sum_ch sum_dr col[dr][ch] sum_dc row[dc][ch] F[r+dr][c+dc][ch], the
+    linear filter W[dr][dc][ch] = col[dr][ch] row[dc][ch].  With `rank`
+    such pairs per filter (row, col: [nf][rank][10][31]) the filter is
+    their sum:  W_f[dr][dc][ch] = sum_i col_f,i[dr][ch] row_f,i[dc][ch]."""
+    row = np.asarray(row, np.float64)
+    col = np.asarray(col, np.float64)
+    return np.einsum("fiaq,fibq->fabq", col, row)
+
+
 def window_box(lv: Level, r, c):
     """Half-open frame-pixel box of window (r, c) of level lv: the window
     covers level pixels [8c, 8c+80) x [8r, 8r+80); each edge is mapped back

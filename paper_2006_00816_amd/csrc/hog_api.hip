@@ -391,26 +391,58 @@ int nms_chain(const Plan& P, int m, const FrameBufs& b, const hog_params* prm, i
     });
 }
 
-// histograms -> features -> scores -> NMS for frames lo .. lo + m - 1
-int staged_chain(const Plan& P, int m, const FrameBufs& b, long long fstride, int pitch, const hog_params* prm,
-                 const float* bias, int cap, int rounds, int score_rows, void* ws, hipStream_t s) {
+// The filters of a call: full [nf][10][10][31] (rank 0), or separable
+// row and column factors [nf][rank][10][31] (rank 1..4).
+struct Bank {
+    const float* W = nullptr;
+    const float* row = nullptr;
+    const float* col = nullptr;
+    int rank = 0;
+    const float* bias = nullptr;
+};
+
+// Window scores of m frames into dense maps and / or keys.
+int score_stage(const Plan& P, int m, const float* feat, const Bank& bank, float thresh, float* dense,
+                unsigned long long* keys, int score_rows, void* ws, hipStream_t s) {
     const LevelTable& T = P.T;
     const bool multi = P.groups > 1;
+    return timed("score", s, [&] {
+        if (bank.rank == 0) {
+            const int rows = score_rows ? score_rows : score_rows_auto(T, m, P.nf, compute_units());
+            return launch_score(T, m, feat, at<float4>(ws, P.o_bpack), bank.bias, P.nf, thresh, dense, keys,
+                                keys && multi, rows, s);
+        }
+        const int rows = score_rows == SCORE_SMALL_ROWS ? SCORE_SMALL_ROWS
+                         : score_rows ? SEP_ROWS
+                                      : sep_rows_auto(T, m, P.nf, compute_units());
+        return launch_score_sep(T, m, feat, bank.row, bank.col, bank.rank, bank.bias, P.nf, thresh, dense, keys,
+                                keys && multi, rows, s);
+    });
+}
+
+// histograms -> features -> scores -> NMS for frames lo .. lo + m - 1
+int staged_chain(const Plan& P, int m, const FrameBufs& b, long long fstride, int pitch, const hog_params* prm,
+                 const Bank& bank, int cap, int rounds, int score_rows, void* ws, hipStream_t s) {
+    const LevelTable& T = P.T;
     HOG_TRY(timed("hist", s, [&] {
         return launch_hist(T, b.frames, fstride, pitch, m, at<int4>(ws, P.o_taps), b.hist, s);
     }));
     HOG_TRY(timed("feat", s, [&] { return launch_feat(T, m, b.hist, b.feat, nullptr, s); }));
-    HOG_TRY(timed("score", s, [&] {
-        const int rows = score_rows ? score_rows : score_rows_auto(T, m, P.nf, compute_units());
-        return launch_score(T, m, b.feat, at<float4>(ws, P.o_bpack), bias, P.nf, prm->thresh, nullptr, b.keys, multi,
-                            rows, s);
-    }));
+    HOG_TRY(score_stage(P, m, b.feat, bank, prm->thresh, nullptr, b.keys, score_rows, ws, s));
     return nms_chain(P, m, b, prm, cap, nullptr, rounds, ws, s);
 }
 
 int detect_sequence(const Plan& P, const hog_params* prm, const uint8_t* frames, long long fstride, int pitch,
-                    const float* filters, const float* bias, hog_det* dets, int cap, int* n_dets, void* ws,
-                    const hog_tuning& tune, hipStream_t s) {
+                    const Bank& bank, hog_det* dets, int cap, int* n_dets, void* ws, const hog_tuning& tune_in,
+                    hipStream_t s) {
+    // separable filters run the per-stage schedule
+    hog_tuning tune = tune_in;
+    if (bank.rank != 0 && tune.fused) {
+        tune.fused = 0;
+        tune.split = 1;
+    }
+    const float* filters = bank.W;
+    const float* bias = bank.bias;
     const LevelTable& T = P.T;
     if (T.n == 0) {
         // no pyramid level: zero detections for every frame
@@ -441,7 +473,7 @@ int detect_sequence(const Plan& P, const hog_params* prm, const uint8_t* frames,
     const int parts = std::min(std::max(tune.split, 1), P.n);
     if (parts == 1)
         return staged_chain(P, P.n, frame_bufs(P, ws, frames, fstride, dets, cap, n_dets, 0), fstride, pitch, prm,
-                            bias, cap, tune.nms_rounds, tune.score_rows, ws, s);
+                            bank, cap, tune.nms_rounds, tune.score_rows, ws, s);
     // the frames in `parts` groups on forked streams: one group's NMS
     // overlaps another's histograms and scores.  Without the calling
     // thread's helper streams (hog_init) the groups run one after another
@@ -451,7 +483,7 @@ int detect_sequence(const Plan& P, const hog_params* prm, const uint8_t* frames,
         for (int j = 0; j < parts; ++j) {
             const int lo = (int)((long long)j * P.n / parts), hi = (int)((long long)(j + 1) * P.n / parts);
             HOG_TRY(staged_chain(P, hi - lo, frame_bufs(P, ws, frames, fstride, dets, cap, n_dets, lo), fstride,
-                                 pitch, prm, bias, cap, tune.nms_rounds, tune.score_rows, ws, s));
+                                 pitch, prm, bank, cap, tune.nms_rounds, tune.score_rows, ws, s));
         }
         return HOG_OK;
     }
@@ -462,7 +494,7 @@ int detect_sequence(const Plan& P, const hog_params* prm, const uint8_t* frames,
     for (int j = 0; j < parts && st == HOG_OK; ++j) {
         const int lo = (int)((long long)j * P.n / parts), hi = (int)((long long)(j + 1) * P.n / parts);
         st = staged_chain(P, hi - lo, frame_bufs(P, ws, frames, fstride, dets, cap, n_dets, lo), fstride, pitch,
-                          prm, bias, cap, tune.nms_rounds, tune.score_rows, ws, j == 0 ? s : r->st[j - 1]);
+                          prm, bank, cap, tune.nms_rounds, tune.score_rows, ws, j == 0 ? s : r->st[j - 1]);
     }
     // join (also after an error, so that no forked stream is left behind a capture)
     for (int j = 1; j < parts; ++j) {
@@ -470,6 +502,33 @@ int detect_sequence(const Plan& P, const hog_params* prm, const uint8_t* frames,
         if (hipStreamWaitEvent(s, r->ev[j], 0) != hipSuccess) return HOG_E_HIP;
     }
     return st;
+}
+
+int check_bank(const hog_filterbank* fb) {
+    if (!fb || !fb->bias || fb->nf < 1) return HOG_E_INVAL;
+    if (fb->nf > MAX_FILTERS) return HOG_E_TOO_LARGE;
+    if (fb->rank == 0) return fb->W ? HOG_OK : HOG_E_INVAL;
+    if (fb->rank < 1 || fb->rank > SEP_MAX_RANK || !fb->row || !fb->col) return HOG_E_INVAL;
+    return HOG_OK;
+}
+
+Bank bank_of(const hog_filterbank* fb) {
+    Bank b;
+    b.W = fb->rank == 0 ? fb->W : nullptr;
+    b.row = fb->row;
+    b.col = fb->col;
+    b.rank = fb->rank;
+    b.bias = fb->bias;
+    return b;
+}
+
+hog_filterbank full_bank(const float* filters, const float* bias, int nf) {
+    hog_filterbank fb{};
+    fb.nf = nf;
+    fb.rank = 0;
+    fb.W = filters;
+    fb.bias = bias;
+    return fb;
 }
 
 int check_detect_args(const hog_params* prm, const void* frames, int pitch, int w, const float* filters,
@@ -577,34 +636,51 @@ int hog_features(const uint8_t* frame, int h, int w, int pitch, int upsample, fl
     return run_pixels(P, frame, 0, pitch, ws, feat, nullptr, (hipStream_t)stream, false);
 }
 
-int hog_scores(const uint8_t* frame, int h, int w, int pitch, int upsample, const float* filters,
-               const float* bias, int nf, float* scores, int64_t scores_cap, void* ws, size_t ws_bytes,
-               void* stream) {
-    if (!frame || !filters || !bias || !scores || pitch < w || pitch > MAX_PITCH || nf < 1) return HOG_E_INVAL;
+int hog_scores_bank(const uint8_t* frame, int h, int w, int pitch, int upsample, const hog_filterbank* fb,
+                    float* scores, int64_t scores_cap, void* ws, size_t ws_bytes, void* stream) {
+    if (!frame || !scores || pitch < w || pitch > MAX_PITCH) return HOG_E_INVAL;
+    HOG_TRY(check_bank(fb));
     Plan P;
-    HOG_TRY(make_plan(h, w, upsample, 1, nf, &P));
+    HOG_TRY(make_plan(h, w, upsample, 1, fb->nf, &P));
     HOG_TRY(check_ws(P, ws, ws_bytes));
     if (scores_cap < P.dense_floats) return HOG_E_CAP;
     if (P.T.n == 0) return HOG_OK;
     hipStream_t s = (hipStream_t)stream;
-    HOG_TRY(run_pixels(P, frame, 0, pitch, ws, nullptr, filters, s, false));
-    return timed("score", s, [&] {
-        return launch_score(P.T, 1, at<float>(ws, P.o_feat), at<float4>(ws, P.o_bpack), bias, nf, 0.f, scores,
-                            nullptr, false, score_rows_auto(P.T, 1, nf, compute_units()), s);
-    });
+    const Bank bank = bank_of(fb);
+    HOG_TRY(run_pixels(P, frame, 0, pitch, ws, nullptr, bank.W, s, false));
+    return score_stage(P, 1, at<float>(ws, P.o_feat), bank, 0.f, scores, nullptr, 0, ws, s);
+}
+
+int hog_scores(const uint8_t* frame, int h, int w, int pitch, int upsample, const float* filters,
+               const float* bias, int nf, float* scores, int64_t scores_cap, void* ws, size_t ws_bytes,
+               void* stream) {
+    if (!filters || !bias || nf < 1) return HOG_E_INVAL;
+    const hog_filterbank fb = full_bank(filters, bias, nf);
+    return hog_scores_bank(frame, h, w, pitch, upsample, &fb, scores, scores_cap, ws, ws_bytes, stream);
+}
+
+int hog_detect_batch_bank(const hog_params* prm, const uint8_t* frames, int n, int h, int w, int pitch,
+                          int64_t frame_stride, const hog_filterbank* fb, hog_det* dets, int cap, int* n_dets,
+                          void* ws, size_t ws_bytes, void* stream) {
+    HOG_TRY(check_bank(fb));
+    HOG_TRY(check_detect_args(prm, frames, pitch, w, fb->rank ? fb->row : fb->W, fb->bias, fb->nf, dets, cap,
+                              n_dets));
+    if (n < 1 || (n > 1 && frame_stride < (int64_t)pitch * h)) return HOG_E_INVAL;
+    Plan P;
+    HOG_TRY(make_plan(h, w, prm->upsample, n, fb->nf, &P));
+    HOG_TRY(check_ws(P, ws, ws_bytes));
+    const hog_tuning tune = lookup_tuning(h, w, prm->upsample, n, fb->nf);
+    return detect_sequence(P, prm, frames, frame_stride, pitch, bank_of(fb), dets, cap, n_dets, ws, tune,
+                           (hipStream_t)stream);
 }
 
 int hog_detect_batch(const hog_params* prm, const uint8_t* frames, int n, int h, int w, int pitch,
                      int64_t frame_stride, const float* filters, const float* bias, int nf, hog_det* dets, int cap,
                      int* n_dets, void* ws, size_t ws_bytes, void* stream) {
     HOG_TRY(check_detect_args(prm, frames, pitch, w, filters, bias, nf, dets, cap, n_dets));
-    if (n < 1 || (n > 1 && frame_stride < (int64_t)pitch * h)) return HOG_E_INVAL;
-    Plan P;
-    HOG_TRY(make_plan(h, w, prm->upsample, n, nf, &P));
-    HOG_TRY(check_ws(P, ws, ws_bytes));
-    const hog_tuning tune = lookup_tuning(h, w, prm->upsample, n, nf);
-    return detect_sequence(P, prm, frames, frame_stride, pitch, filters, bias, dets, cap, n_dets, ws, tune,
-                           (hipStream_t)stream);
+    const hog_filterbank fb = full_bank(filters, bias, nf);
+    return hog_detect_batch_bank(prm, frames, n, h, w, pitch, frame_stride, &fb, dets, cap, n_dets, ws, ws_bytes,
+                                 stream);
 }
 
 int hog_detect(const hog_params* prm, const uint8_t* frame, int h, int w, int pitch, const float* filters,
@@ -614,15 +690,17 @@ int hog_detect(const hog_params* prm, const uint8_t* frame, int h, int w, int pi
                             stream);
 }
 
-int hog_graph_create(hog_graph** out, const hog_params* prm, const uint8_t* frames, int n, int h, int w,
-                     int pitch, int64_t frame_stride, const float* filters, const float* bias, int nf,
-                     hog_det* dets, int cap, int* n_dets, void* ws, size_t ws_bytes, void* stream) {
+int hog_graph_create_bank(hog_graph** out, const hog_params* prm, const uint8_t* frames, int n, int h, int w,
+                          int pitch, int64_t frame_stride, const hog_filterbank* fb, hog_det* dets, int cap,
+                          int* n_dets, void* ws, size_t ws_bytes, void* stream) {
     if (!out) return HOG_E_INVAL;
     *out = nullptr;
-    HOG_TRY(check_detect_args(prm, frames, pitch, w, filters, bias, nf, dets, cap, n_dets));
+    HOG_TRY(check_bank(fb));
+    HOG_TRY(check_detect_args(prm, frames, pitch, w, fb->rank ? fb->row : fb->W, fb->bias, fb->nf, dets, cap,
+                              n_dets));
     if (n < 1 || (n > 1 && frame_stride < (int64_t)pitch * h)) return HOG_E_INVAL;
     Plan P;
-    HOG_TRY(make_plan(h, w, prm->upsample, n, nf, &P));
+    HOG_TRY(make_plan(h, w, prm->upsample, n, fb->nf, &P));
     HOG_TRY(check_ws(P, ws, ws_bytes));
     hipStream_t cs = (hipStream_t)stream;
     bool own = false;
@@ -635,8 +713,8 @@ int hog_graph_create(hog_graph** out, const hog_params* prm, const uint8_t* fram
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         st = HOG_E_HIP;
     } else {
-        const hog_tuning tune = lookup_tuning(h, w, prm->upsample, n, nf);
-        st = detect_sequence(P, prm, frames, frame_stride, pitch, filters, bias, dets, cap, n_dets, ws, tune, cs);
+        const hog_tuning tune = lookup_tuning(h, w, prm->upsample, n, fb->nf);
+        st = detect_sequence(P, prm, frames, frame_stride, pitch, bank_of(fb), dets, cap, n_dets, ws, tune, cs);
         hipGraph_t graph = nullptr;
         const hipError_t e = hipStreamEndCapture(cs, &graph);
         if (st == HOG_OK && e != hipSuccess) st = HOG_E_HIP;
@@ -651,6 +729,17 @@ int hog_graph_create(hog_graph** out, const hog_params* prm, const uint8_t* fram
     }
     *out = g;
     return HOG_OK;
+}
+
+int hog_graph_create(hog_graph** out, const hog_params* prm, const uint8_t* frames, int n, int h, int w,
+                     int pitch, int64_t frame_stride, const float* filters, const float* bias, int nf,
+                     hog_det* dets, int cap, int* n_dets, void* ws, size_t ws_bytes, void* stream) {
+    if (!out) return HOG_E_INVAL;
+    *out = nullptr;
+    HOG_TRY(check_detect_args(prm, frames, pitch, w, filters, bias, nf, dets, cap, n_dets));
+    const hog_filterbank fb = full_bank(filters, bias, nf);
+    return hog_graph_create_bank(out, prm, frames, n, h, w, pitch, frame_stride, &fb, dets, cap, n_dets, ws,
+                                 ws_bytes, stream);
 }
 
 int hog_graph_launch(hog_graph* g, void* stream) {
@@ -726,6 +815,8 @@ int hog_autotune(const hog_params* prm, const uint8_t* frames, int n, int h, int
         }
     }
     hipStream_t s = (hipStream_t)stream;
+    const hog_filterbank fbk = full_bank(filters, bias, nf);
+    const Bank bank = bank_of(&fbk);
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess) return HOG_E_HIP;
     if (hipEventCreate(&b) != hipSuccess) {
@@ -736,11 +827,11 @@ int hog_autotune(const hog_params* prm, const uint8_t* frames, int n, int h, int
     float best_t = -1.f;
     hog_tuning pick = cand[0];
     for (const hog_tuning& t : cand) {
-        st = detect_sequence(P, prm, frames, frame_stride, pitch, filters, bias, dets, cap, n_dets, ws, t, s);
+        st = detect_sequence(P, prm, frames, frame_stride, pitch, bank, dets, cap, n_dets, ws, t, s);
         if (st != HOG_OK) break;
         if (hipEventRecord(a, s) != hipSuccess) { st = HOG_E_HIP; break; }
         for (int i = 0; i < reps && st == HOG_OK; ++i)
-            st = detect_sequence(P, prm, frames, frame_stride, pitch, filters, bias, dets, cap, n_dets, ws, t, s);
+            st = detect_sequence(P, prm, frames, frame_stride, pitch, bank, dets, cap, n_dets, ws, t, s);
         if (st != HOG_OK) break;
         float ms = 0.f;
         if (hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||

@@ -77,7 +77,13 @@ static __device__ __noinline__ int orient_bin_f64(int gxi, int gyi) {
 // 3.3e-7 (|gx| + |gy|).  When every |t_b| exceeds 1e-6 (|gx| + |gy|) the
 // signs are exact and the float64 scan above, whose own error is some
 // 1e-16 of the magnitude, picks the same bin.  Otherwise the float64 scan
-// itself decides.  The unfolding is branch-free.
+// itself decides.
+//
+// Unfolding, branch-free: j = 4 - (number of negative t_b) (no t_b is 0
+// on this path).  With sx = "points left, or straight up" (gx < 0, or
+// gx = 0 and gy < 0) and sy = "points up" (gy < 0), quadrant I (neither)
+// has bin j, II (sx) 9 - j, III (both) 9 + j and IV (sy) 18 - j, which is
+// bin 0 for j = 0.
 static __device__ inline int orient_bin(int gxi, int gyi) {
     const float ax = fabsf((float)gxi), ay = fabsf((float)gyi);
     const float t0 = fmaf(-ax, 0.176326980708f, ay);   // tan 10
@@ -86,11 +92,13 @@ static __device__ inline int orient_bin(int gxi, int gyi) {
     const float t3 = fmaf(-ax, 2.747477419455f, ay);   // tan 70
     const float m = fminf(fminf(fabsf(t0), fabsf(t1)), fminf(fabsf(t2), fabsf(t3)));
     if (m <= 1e-6f * (ax + ay)) return orient_bin_f64(gxi, gyi);
-    const int j = (t0 > 0.f) + (t1 > 0.f) + (t2 > 0.f) + (t3 > 0.f);
-    const bool upper = (gyi > 0) || (gyi == 0 && gxi > 0);
-    const int b_up = gxi >= 0 ? j : NORIENT - j;
-    const int b_lo = gxi <= 0 ? NORIENT + j : (j == 0 ? 0 : NBINS - j);
-    return upper ? b_up : b_lo;
+    const int j = 4 - (int)((__float_as_uint(t0) >> 31) + (__float_as_uint(t1) >> 31) +
+                            (__float_as_uint(t2) >> 31) + (__float_as_uint(t3) >> 31));
+    const bool sy = gyi < 0;
+    const bool sx = gxi < 0 || (gxi == 0 && sy);
+    const int base = sx ? NORIENT : (sy ? NBINS : 0);
+    const int b = (sx != sy) ? base - j : base + j;
+    return b == NBINS ? 0 : b;
 }
 
 // Gradient magnitude of a voting pixel as the fixed-point integer
@@ -102,6 +110,14 @@ static __device__ inline unsigned vote_magnitude(int gxi, int gyi) {
     const float fx = (float)gxi, fy = (float)gyi;
     const float mag = __builtin_amdgcn_sqrtf(fmaf(fx, fx, fy * fy));
     return (unsigned)(mag * 64.0f + 0.5f);
+}
+
+// The same integer magnitude as a float64 (exact): floor(|g| 2^6 + 1/2)
+// of the float32 value, which is already an integer from 2^23 on.
+static __device__ inline double vote_magnitude_f64(int gxi, int gyi) {
+    const float fx = (float)gxi, fy = (float)gyi;
+    const float mag = __builtin_amdgcn_sqrtf(fmaf(fx, fx, fy * fy));
+    return (double)floorf(fmaf(mag, 64.0f, 0.5f));
 }
 
 // Fixed-point resampling tap: returns {i0, i1, a8, 0} for output index i
@@ -117,6 +133,13 @@ static __device__ inline int4 axis_tap(int i, int n_in, long long sig) {
     const int i0 = (int)min(max(base, 0LL), (long long)(n_in - 1));
     const int i1 = (int)min(max(base + 1, 0LL), (long long)(n_in - 1));
     return make_int4(i0, i1, a, 0);
+}
+
+// Orders a wave's LDS accesses on either side (LDS operations of one wave
+// execute in program order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_lds_order() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
 }
 
 // Frame-pixel edge of level-pixel coordinate v: round(v * sig / 2^40).

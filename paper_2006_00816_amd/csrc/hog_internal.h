@@ -156,9 +156,15 @@ hipError_t launch_fused(const LevelTable& T, int n, const FusedCfg& cfg, const u
                         const float* bias, int nf, float thresh, unsigned long long* poskey, bool atomic_key,
                         unsigned* sync, hipStream_t s);
 int score_rows_auto(const LevelTable& T, int n, int nf, int cus);
+int sep_rows_auto(const LevelTable& T, int n, int nf, int cus);
 hipError_t launch_score(const LevelTable& T, int n, const float* feat, const float4* bpack,
                         const float* bias, int nf, float thresh, float* dense,
                         unsigned long long* poskey, bool atomic_key, int rows, hipStream_t s);
+constexpr int SEP_MAX_RANK = 4;   // row / column filter pairs per channel of a separable filter
+constexpr int SEP_ROWS = 8;       // window rows per separable scoring item (256 VGPRs per lane at 512 threads)
+hipError_t launch_score_sep(const LevelTable& T, int n, const float* feat, const float* row, const float* col,
+                            int rank, const float* bias, int nf, float thresh, float* dense,
+                            unsigned long long* poskey, bool atomic_key, int rows, hipStream_t s);
 // NMS records hold 32-bit position indices when a frame has 65536 window
 // positions or more, else 16-bit ones.
 inline bool nms_wide_lists(long long positions) { return positions > 65535; }

@@ -466,14 +466,15 @@ __device__ __forceinline__ void wave_append(bool take, int p, W* list, int* coun
 constexpr int RESOLVE_BATCH = 2;   // worklist items per thread whose records are loaded together
 
 // Record cache of the per-frame kernel: once the worklist is short enough,
-// the records of its candidates are copied into LDS and the remaining
-// rounds read only LDS.  Layout of the dynamic LDS after the states:
+// the records of its candidates are copied into LDS and the rest is
+// decided from LDS.  Layout of the dynamic LDS after the states:
 // RC_CHUNKS 64-byte chunks (also the sort buffer afterwards), then per
 // cached candidate its position and first chunk, then two worklists of
-// cached-candidate indices.
+// cached-candidate indices (the first also the rank order), then the
+// cached candidates' keys.
 constexpr int RC_MAXI = 2048;
 constexpr int RC_CHUNKS = 1536;
-constexpr int RC_BYTES = RC_CHUNKS * 64 + RC_MAXI * (4 + 2 + 2 + 2);
+constexpr int RC_BYTES = RC_CHUNKS * 64 + RC_MAXI * (4 + 2 + 2 + 2 + 8);
 static_assert(RC_CHUNKS * 64 >= SORT_CAP * 8, "sort buffer aliases the chunk cache");
 
 template <typename E, bool G>
@@ -514,6 +515,7 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
     // array of pointers, so that the compiler keeps their address spaces
     // (LDS / global) instead of generic flat accesses
     unsigned short* const rc_wl = rc_first + RC_MAXI;   // rc_wl + b * RC_MAXI, b = 0, 1
+    unsigned long long* const rc_key = reinterpret_cast<unsigned long long*>(rc_wl + 2 * RC_MAXI);
     __shared__ int s_chunks;
     const unsigned long long* keys = poskey + (long long)frame * P;
     const E* lst = lists + (long long)frame * P * NMS_LIST;
@@ -578,6 +580,56 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
                 cached = true;
                 cur = 0;
                 __syncthreads();
+                // The cached candidates in rank order (a candidate's place
+                // is the number of larger keys; keys are distinct), then
+                // decided in that order by the first wave, 64 at a time.
+                // Every listed neighbour of a candidate ranks better, so it
+                // is decided in an earlier block or is an earlier lane of
+                // this block; the earliest undecided lane can therefore
+                // always decide, and each step of a block decides at least
+                // one lane.  The result is the sequential greedy pass.
+                for (int i = tid; i < n_in; i += NMS_THREADS) rc_key[i] = keys[rc_pos[i]];
+                __syncthreads();
+                for (int i = tid; i < n_in; i += NMS_THREADS) {
+                    const unsigned long long ki = rc_key[i];
+                    int rank = 0;
+                    for (int q = 0; q < n_in; ++q) rank += rc_key[q] > ki ? 1 : 0;
+                    rc_wl[rank] = (unsigned short)i;
+                }
+                __syncthreads();
+                if (tid < 64) {
+                    for (int b0 = 0; b0 < n_in; b0 += 64) {
+                        const int idx = b0 + tid;
+                        bool und = idx < n_in;
+                        const int it = und ? (int)rc_wl[idx] : 0;
+                        const int p = rc_pos[it];
+                        const int first = rc_first[it];
+                        // at most 64 steps (each decides a lane); the bound
+                        // also ends the loop if that did not hold
+                        for (int step = 0; step < 64 && __ballot(und); ++step) {
+                            if (und) {
+                                unsigned v;
+                                if (first != 0xffff) {
+                                    const E* rec = reinterpret_cast<const E*>(rc_chunks + 4 * first);
+                                    Rec<E> R;
+                                    R.load(rec);
+                                    v = decide_rec<E, G>(S, rec, CH, R, (int)R.at(0));
+                                } else {
+                                    v = decide_scan<G>(T, keys, S, boxes, keys[p], inum, iden);
+                                }
+                                if (v != UNDECIDED) {
+                                    atomicOr(&S[p >> 4], v << ((p & 15) * 2));
+                                    und = false;
+                                }
+                            }
+                            // this step's decisions before the next step's reads
+                            if (G) __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+                            wave_lds_order();
+                        }
+                    }
+                }
+                __syncthreads();
+                break;
             }
         }
         if (tid == 0) s_next = 0;

@@ -27,12 +27,10 @@ struct ScoreOrder {
     unsigned char s[SCORE_ORDER_MAX];
 };
 
-template <int ROWS>
-__global__ __launch_bounds__(ROWS * 64) void hog_score_kernel(
-    LevelTable T, ScoreOrder ord, int groups, int per_frame, int units, int halves, const float* __restrict__ feat,
-    const float4* __restrict__ bpack, const float* __restrict__ bias, int nf, float thresh,
-    float* __restrict__ dense, unsigned long long* __restrict__ poskey, int atomic_key) {
-    __shared__ ScoreSmemT<ROWS> sm;
+// The (unit, slot) of this block under the mapping above; false for a
+// block past the end.
+__device__ __forceinline__ bool score_slot(const ScoreOrder& ord, int per_frame, int units, int* unit_out,
+                                           int* it_out) {
     const int x = (int)(blockIdx.x & 7), p = (int)(blockIdx.x >> 3);
     int unit, it;
     if (units >= 8) {
@@ -40,14 +38,27 @@ __global__ __launch_bounds__(ROWS * 64) void hog_score_kernel(
         const int nu = (int)((long long)(x + 1) * units / 8) - u0;
         it = p / nu;
         unit = u0 + (p - it * nu);
-        if (it >= per_frame) return;
+        if (it >= per_frame) return false;
         if (per_frame <= SCORE_ORDER_MAX) it = ord.s[it];
     } else {
         const int item = x * (int)(gridDim.x >> 3) + p;
-        if (item >= units * per_frame) return;
+        if (item >= units * per_frame) return false;
         it = item % per_frame;
         unit = item / per_frame;
     }
+    *unit_out = unit;
+    *it_out = it;
+    return true;
+}
+
+template <int ROWS>
+__global__ __launch_bounds__(ROWS * 64) void hog_score_kernel(
+    LevelTable T, ScoreOrder ord, int groups, int per_frame, int units, int halves, const float* __restrict__ feat,
+    const float4* __restrict__ bpack, const float* __restrict__ bias, int nf, float thresh,
+    float* __restrict__ dense, unsigned long long* __restrict__ poskey, int atomic_key) {
+    __shared__ ScoreSmemT<ROWS> sm;
+    int unit, it;
+    if (!score_slot(ord, per_frame, units, &unit, &it)) return;
     const int grp = unit % groups;
     const int frame = unit / groups;
     const int tid = threadIdx.x;
@@ -56,6 +67,25 @@ __global__ __launch_bounds__(ROWS * 64) void hog_score_kernel(
     // halves = 2: slot it runs one half of the tiles of row block it / 2
     score_item<ROWS>(T, frame, grp, halves == 2 ? it >> 1 : it, sm, sm.P[tid >> 6], feat, nf, bias, thresh, dense,
                      poskey, atomic_key, tid, halves == 2 ? it & 1 : -1);
+}
+
+// The same work items and dispatch with separable filters (row and column
+// factors, RANK pairs per channel; see score_row_sep).
+template <int ROWS, int RANK>
+__global__ __launch_bounds__(ROWS * 64) void hog_sep_score_kernel(
+    LevelTable T, ScoreOrder ord, int groups, int per_frame, int units, int halves, const float* __restrict__ feat,
+    const float* __restrict__ row, const float* __restrict__ col, const float* __restrict__ bias, int nf,
+    float thresh, float* __restrict__ dense, unsigned long long* __restrict__ poskey, int atomic_key) {
+    __shared__ SepSmemT<ROWS, RANK> sm;
+    int unit, it;
+    if (!score_slot(ord, per_frame, units, &unit, &it)) return;
+    const int grp = unit % groups;
+    const int frame = unit / groups;
+    const int tid = threadIdx.x;
+    load_sep(sm, row, col, nf, grp, tid);
+    __syncthreads();
+    score_item_sep<ROWS, RANK>(T, frame, grp, halves == 2 ? it >> 1 : it, sm, sm.P[tid >> 6], feat, nf, bias, thresh,
+                               dense, poskey, atomic_key, tid, halves == 2 ? it & 1 : -1);
 }
 
 namespace {
@@ -143,14 +173,13 @@ ScoreOrder score_order(const LevelTable& T, int rows, int per_frame, int units, 
 
 }  // namespace
 
-int score_rows_auto(const LevelTable& T, int n, int nf, int cus) {
-    const long long items16 = (long long)T.ts_total * n * ((nf + FGROUP - 1) / FGROUP);
-    return items16 < cus ? SCORE_SMALL_ROWS : ROWS_PER_ITEM;
-}
+// Grid and dispatch order of a scoring launch (shared by both scorers).
+struct ScoreGrid {
+    int groups, per_frame, units, halves, blocks;
+    ScoreOrder ord;
+};
 
-hipError_t launch_score(const LevelTable& T, int n, const float* feat, const float4* bpack, const float* bias,
-                        int nf, float thresh, float* dense, unsigned long long* poskey, bool atomic_key, int rows,
-                        hipStream_t s) {
+bool score_grid(const LevelTable& T, int n, int nf, int rows, ScoreGrid* g) {
     const int groups = (nf + FGROUP - 1) / FGROUP;
     const long long units = (long long)n * groups;
     int cus = 0;
@@ -166,20 +195,74 @@ hipError_t launch_score(const LevelTable& T, int n, const float* feat, const flo
     const int halves = rows == SCORE_SMALL_ROWS && (long long)blocks_of_rows * units < cus ? 2 : 1;
     const int per_frame = blocks_of_rows * halves;
     const long long items = (long long)per_frame * units;
-    if (items <= 0) return hipSuccess;
-    if (items > 0x7fffff00LL) return hipErrorInvalidValue;
-    const int blocks = units >= 8 ? (int)((units + 7) / 8 * per_frame * 8) : (int)((items + 7) / 8 * 8);
-    ScoreOrder ord{};
-    for (int i = 0; i < SCORE_ORDER_MAX; ++i) ord.s[i] = (unsigned char)i;
-    if (units >= 8 && per_frame <= SCORE_ORDER_MAX && rows == ROWS_PER_ITEM && cus >= 8)
-        ord = score_order(T, rows, per_frame, (int)((units + 7) / 8), cus / 8);
+    if (items <= 0 || items > 0x7fffff00LL) return false;
+    g->groups = groups;
+    g->per_frame = per_frame;
+    g->units = (int)units;
+    g->halves = halves;
+    g->blocks = units >= 8 ? (int)((units + 7) / 8 * per_frame * 8) : (int)((items + 7) / 8 * 8);
+    for (int i = 0; i < SCORE_ORDER_MAX; ++i) g->ord.s[i] = (unsigned char)i;
+    if (units >= 8 && per_frame <= SCORE_ORDER_MAX && rows > SCORE_SMALL_ROWS && cus >= 8)
+        g->ord = score_order(T, rows, per_frame, (int)((units + 7) / 8), cus / 8);
+    return true;
+}
+
+hipError_t launch_score_sep(const LevelTable& T, int n, const float* feat, const float* row, const float* col,
+                            int rank, const float* bias, int nf, float thresh, float* dense,
+                            unsigned long long* poskey, bool atomic_key, int rows, hipStream_t s) {
+    ScoreGrid g;
+    if (T.rows_total <= 0 || n <= 0) return hipSuccess;
+    if (!score_grid(T, n, nf, rows, &g)) return hipErrorInvalidValue;
+    const int ak = atomic_key ? 1 : 0;
+#define HOG_SEP_LAUNCH(R, K)                                                                                      \
+    hipLaunchKernelGGL((hog_sep_score_kernel<R, K>), dim3(g.blocks), dim3(R * 64), 0, s, T, g.ord, g.groups,      \
+                       g.per_frame, g.units, g.halves, feat, row, col, bias, nf, thresh, dense, poskey, ak)
+    if (rows == SCORE_SMALL_ROWS) {
+        switch (rank) {
+            case 1: HOG_SEP_LAUNCH(SCORE_SMALL_ROWS, 1); break;
+            case 2: HOG_SEP_LAUNCH(SCORE_SMALL_ROWS, 2); break;
+            case 3: HOG_SEP_LAUNCH(SCORE_SMALL_ROWS, 3); break;
+            case 4: HOG_SEP_LAUNCH(SCORE_SMALL_ROWS, 4); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else if (rows == SEP_ROWS) {
+        switch (rank) {
+            case 1: HOG_SEP_LAUNCH(SEP_ROWS, 1); break;
+            case 2: HOG_SEP_LAUNCH(SEP_ROWS, 2); break;
+            case 3: HOG_SEP_LAUNCH(SEP_ROWS, 3); break;
+            case 4: HOG_SEP_LAUNCH(SEP_ROWS, 4); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        return hipErrorInvalidValue;
+    }
+#undef HOG_SEP_LAUNCH
+    return hipGetLastError();
+}
+
+int sep_rows_auto(const LevelTable& T, int n, int nf, int cus) {
+    const long long items = (long long)((T.rows_total + SEP_ROWS - 1) / SEP_ROWS) * n * ((nf + FGROUP - 1) / FGROUP);
+    return items < cus ? SCORE_SMALL_ROWS : SEP_ROWS;
+}
+
+int score_rows_auto(const LevelTable& T, int n, int nf, int cus) {
+    const long long items16 = (long long)T.ts_total * n * ((nf + FGROUP - 1) / FGROUP);
+    return items16 < cus ? SCORE_SMALL_ROWS : ROWS_PER_ITEM;
+}
+
+hipError_t launch_score(const LevelTable& T, int n, const float* feat, const float4* bpack, const float* bias,
+                        int nf, float thresh, float* dense, unsigned long long* poskey, bool atomic_key, int rows,
+                        hipStream_t s) {
+    ScoreGrid g;
+    if (T.rows_total <= 0 || n <= 0) return hipSuccess;
+    if (!score_grid(T, n, nf, rows, &g)) return hipErrorInvalidValue;
     if (rows == SCORE_SMALL_ROWS)
-        hipLaunchKernelGGL(hog_score_kernel<SCORE_SMALL_ROWS>, dim3(blocks), dim3(SCORE_SMALL_ROWS * 64), 0, s, T,
-                           ord, groups, per_frame, (int)units, halves, feat, bpack, bias, nf, thresh, dense, poskey,
-                           atomic_key ? 1 : 0);
+        hipLaunchKernelGGL(hog_score_kernel<SCORE_SMALL_ROWS>, dim3(g.blocks), dim3(SCORE_SMALL_ROWS * 64), 0, s, T,
+                           g.ord, g.groups, g.per_frame, g.units, g.halves, feat, bpack, bias, nf, thresh, dense,
+                           poskey, atomic_key ? 1 : 0);
     else if (rows == ROWS_PER_ITEM)
-        hipLaunchKernelGGL(hog_score_kernel<ROWS_PER_ITEM>, dim3(blocks), dim3(ROWS_PER_ITEM * 64), 0, s, T, ord, groups,
-                           per_frame, (int)units, halves, feat, bpack, bias, nf, thresh, dense, poskey,
+        hipLaunchKernelGGL(hog_score_kernel<ROWS_PER_ITEM>, dim3(g.blocks), dim3(ROWS_PER_ITEM * 64), 0, s, T, g.ord,
+                           g.groups, g.per_frame, g.units, g.halves, feat, bpack, bias, nf, thresh, dense, poskey,
                            atomic_key ? 1 : 0);
     else
         return hipErrorInvalidValue;

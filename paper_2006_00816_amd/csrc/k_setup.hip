@@ -51,7 +51,7 @@ __global__ __launch_bounds__(256) void hog_setup_kernel(
         }
     } else if (blockIdx.y == 1) {
         const int ngroups = (nf + FGROUP - 1) / FGROUP;
-        if (e >= (long long)ngroups * BPACK_PER_GROUP) return;
+        if (!W || e >= (long long)ngroups * BPACK_PER_GROUP) return;
         const int grp = (int)(e / BPACK_PER_GROUP);
         const int rem = (int)(e % BPACK_PER_GROUP);
         int n, k0;

@@ -20,7 +20,7 @@ constexpr int CS = NBINS + 1;                     // u64 words per local cell (o
 // LDS of one histogram tile (64 KB).
 struct HistSmem {
     int4 Ty[TPY], Tx[TPX];                        // row / column taps of the tile
-    unsigned long long H[LC_H * LC_W * CS];       // fixed-point cell histograms
+    double H[LC_H * LC_W * CS];                   // cell histograms, integer-valued (see quad_votes)
     int V[64 * PLANE];                            // swizzled level pixels (value * 2^16)
 };
 
@@ -37,8 +37,16 @@ __host__ __device__ constexpr int qoff(int ty, int tx) {
 // Sixteen pixels (offsets 16Q .. 16Q+15 of an 8x8 quad block) of one lane:
 // central differences, orientation, magnitude and four fixed-point votes.
 // All LDS offsets and weights are compile-time constants.
+//
+// A vote is the integer M w, M = round(|g| 2^6) (|g| in units of 2^-16)
+// below 2^31 and w the integer weight product (at most 225), so below
+// 2^39; it is formed and summed in float64, where every partial sum of a
+// cell (at most 256 votes, below 2^47) is an exact integer.  The sums are
+// therefore the exact fixed-point totals whatever the order of the
+// additions (LDS float64 atomics), and float64 multiplies run at the full
+// vector rate where 64-bit integer products do not.
 template <int Q, bool CHECK>
-__device__ __forceinline__ void quad_votes(const int* __restrict__ sV, int lb, unsigned long long* __restrict__ h00,
+__device__ __forceinline__ void quad_votes(const int* __restrict__ sV, int lb, double* __restrict__ h00,
                                            int ylb, int xlb, int ylim, int xlim) {
     // the two pixel rows 2Q, 2Q + 1 of the quad block and their central
     // differences need level rows 2Q .. 2Q + 3 (tile coordinates, one-pixel
@@ -63,16 +71,16 @@ __device__ __forceinline__ void quad_votes(const int* __restrict__ sV, int lb, u
         const int gy = V[di + 2][ox + 1] - V[di][ox + 1];
         if ((gx | gy) == 0) continue;
         const int bin = orient_bin(gx, gy);
-        const unsigned long long M = vote_magnitude(gx, gy);
-        atomicAdd(h00 + bin, M * (unsigned)((15 - 2 * oy) * (15 - 2 * ox)));
-        atomicAdd(h00 + CS + bin, M * (unsigned)((15 - 2 * oy) * (2 * ox + 1)));
-        atomicAdd(h00 + LC_W * CS + bin, M * (unsigned)((2 * oy + 1) * (15 - 2 * ox)));
-        atomicAdd(h00 + (LC_W + 1) * CS + bin, M * (unsigned)((2 * oy + 1) * (2 * ox + 1)));
+        const double M = vote_magnitude_f64(gx, gy);
+        atomicAdd(h00 + bin, M * (double)((15 - 2 * oy) * (15 - 2 * ox)));
+        atomicAdd(h00 + CS + bin, M * (double)((15 - 2 * oy) * (2 * ox + 1)));
+        atomicAdd(h00 + LC_W * CS + bin, M * (double)((2 * oy + 1) * (15 - 2 * ox)));
+        atomicAdd(h00 + (LC_W + 1) * CS + bin, M * (double)((2 * oy + 1) * (2 * ox + 1)));
     }
 }
 
 template <bool CHECK>
-__device__ __forceinline__ void quad_votes_q(int q, const int* sV, int lb, unsigned long long* h00, int ylb, int xlb,
+__device__ __forceinline__ void quad_votes_q(int q, const int* sV, int lb, double* h00, int ylb, int xlb,
                                              int ylim, int xlim) {
     switch (q) {
         case 0: quad_votes<0, CHECK>(sV, lb, h00, ylb, xlb, ylim, xlim); break;
@@ -112,15 +120,19 @@ __device__ __forceinline__ void resample_tile(const int4* __restrict__ sTy, cons
         }
 #pragma unroll
         for (int r = 0; r < RS; ++r) {
-            int v;
+            // 24-bit multiplies (samples < 2^8, weights <= 2^8, rows < 2^16):
+            // full-rate v_mul_u32_u24, where 32-bit products are quarter rate
+            unsigned v;
             if (IDENT) {
-                v = inside[r] ? u00[r] << 16 : 0;
+                v = (unsigned)u00[r] << 16;
             } else {
-                const int top = (256 - bx[r]) * u00[r] + bx[r] * u01[r];
-                const int bot = (256 - bx[r]) * u10[r] + bx[r] * u11[r];
-                v = inside[r] ? (256 - ay[r]) * top + ay[r] * bot : 0;
+                const unsigned wx1 = (unsigned)bx[r], wx0 = 256u - wx1;
+                const unsigned wy1 = (unsigned)ay[r], wy0 = 256u - wy1;
+                const unsigned top = __umul24(wx0, (unsigned)u00[r]) + __umul24(wx1, (unsigned)u01[r]);
+                const unsigned bot = __umul24(wx0, (unsigned)u10[r]) + __umul24(wx1, (unsigned)u11[r]);
+                v = __umul24(wy0, top) + __umul24(wy1, bot);
             }
-            if (e0 + r * HIST_THREADS < TPY * TPX) sV[swz(ty[r], tx[r])] = v;
+            if (e0 + r * HIST_THREADS < TPY * TPX) sV[swz(ty[r], tx[r])] = inside[r] ? (int)v : 0;
         }
     }
 }
@@ -146,7 +158,7 @@ __device__ __forceinline__ void hist_tile(const LevelTable& T, const uint8_t* __
                                           int pitch, const int4* __restrict__ taps, float* __restrict__ hist,
                                           int frame, int tile, int tid, HistSmem& sm) {
     int* __restrict__ sV = sm.V;
-    unsigned long long* __restrict__ sH = sm.H;
+    double* __restrict__ sH = sm.H;
     int4* __restrict__ sTy = sm.Ty;
     int4* __restrict__ sTx = sm.Tx;
     const bool on = tile >= 0;
@@ -159,7 +171,7 @@ __device__ __forceinline__ void hist_tile(const LevelTable& T, const uint8_t* __
     const uint8_t* __restrict__ U = frames + (long long)frame * fstride;
 
     if (on) {
-        for (int e = tid; e < LC_H * LC_W * CS; e += HIST_THREADS) sH[e] = 0ull;
+        for (int e = tid; e < LC_H * LC_W * CS; e += HIST_THREADS) sH[e] = 0.0;
         for (int e = tid; e < TPY + TPX; e += HIST_THREADS) {
             if (e < TPY) {
                 const int y = ybase + e;
@@ -192,7 +204,7 @@ __device__ __forceinline__ void hist_tile(const LevelTable& T, const uint8_t* __
         const int qb = lane & 15;                         // quad-block column 0..15
         const int q = wave >> 1;                          // quarter of the 64 pixel offsets
         const int lb = qa * PL_W + qb;                    // swizzled base of the quad block
-        unsigned long long* h00 = &sH[(qa * LC_W + qb) * CS];
+        double* h00 = &sH[(qa * LC_W + qb) * CS];
         // valid pixels: 1 <= y <= min(8 cy - 1, h - 2), same for x
         const int ylim = min(8 * L.cy - 1, L.h - 2), xlim = min(8 * L.cx - 1, L.w - 2);
         const bool inner =
@@ -208,10 +220,10 @@ __device__ __forceinline__ void hist_tile(const LevelTable& T, const uint8_t* __
         const int li = tid / TCX, lj = tid - li * TCX;
         const int gi = i0 + li, gj = j0 + lj;
         if (gi < L.cy && gj < L.cx) {
-            const unsigned long long* src = &sH[((li + 1) * LC_W + lj + 1) * CS];
+            const double* src = &sH[((li + 1) * LC_W + lj + 1) * CS];
             float h[NBINS];
 #pragma unroll
-            for (int b = 0; b < NBINS; ++b) h[b] = (float)((double)src[b] * 0x1p-30);
+            for (int b = 0; b < NBINS; ++b) h[b] = (float)(src[b] * 0x1p-30);
             float E = 0.f;
 #pragma unroll
             for (int o = 0; o < NORIENT; ++o) {

@@ -25,11 +25,75 @@ __device__ __forceinline__ void load_bpack(ScoreSmemT<ROWS>& sm, const float4* _
     for (int e = tid; e < BPACK_PER_GROUP; e += ROWS * 64) sm.B[e] = g[e];
 }
 
-// Orders a wave's LDS accesses on either side (LDS operations of one wave
-// execute in program order; this keeps the compiler from moving them).
-__device__ __forceinline__ void wave_lds_order() {
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    __builtin_amdgcn_wave_barrier();
+// Window scores of M tile t of window row r from the tile's partial
+// products in `ring`, stored column-major: P[(f, dc)][x] at
+// ring[(10 f + dc) * SC_RSTR + x] for the 16 cells x of the tile (f the
+// filter of the group, dc the window column).  Lane (g4, j) sums filter g4
+// (and, with XTRA, filter 4) for window c = 16 t - 9 + j; the terms of
+// window c + 16 that lie in this tile are carried to the next tile in
+// carry0 / carry1.  Writes the dense scores (optional) and the best
+// candidate key per window position, as score_row describes.
+template <bool XTRA>
+__device__ __forceinline__ void tile_windows(const DevLevel& L, int k, int r, int t, int t_begin,
+                                             const float* __restrict__ ring, float& carry0, float& carry1, int g4,
+                                             int j, int f0, int f1, bool f0ok, bool f1ok, float b0, float b1,
+                                             float thresh, float* __restrict__ D, unsigned long long* __restrict__ PK,
+                                             int atomic_key) {
+    // Window c = 16 t - 9 + j takes P[c + dc] for dc >= 9 - j (cells of
+    // this tile) and window c + 16 starts its carry with the cells
+    // 7 + j + dc <= 15 of this tile; both are cell (7 + j + dc) mod 16,
+    // so one read per dc, added to one sum or the other (zeros keep
+    // the order of the additions).
+    float s0 = carry0, s1 = carry1, n0 = 0.f, n1 = 0.f;
+#pragma unroll
+    for (int dc = 0; dc < WIN; ++dc) {
+        const bool mine = dc >= WIN - 1 - j;
+        const float* p = ring + dc * SC_RSTR + ((j + 7 + dc) & 15);
+        const float v0 = p[WIN * SC_RSTR * g4];
+        s0 += mine ? v0 : 0.f;
+        n0 += mine ? 0.f : v0;
+        if (XTRA) {
+            const float v1 = p[WIN * SC_RSTR * 4];
+            s1 += mine ? v1 : 0.f;
+            n1 += mine ? 0.f : v1;
+        }
+    }
+    carry0 = n0;
+    carry1 = n1;
+    wave_lds_order();
+    if (t < t_begin) return;   // carry-only tile
+
+    const int c = 16 * t - (WIN - 1) + j;
+    const bool cok = c >= 0 && c < L.cols;
+    unsigned long long key = 0ull;
+    if (cok) {
+        s0 += b0;
+        s1 += b1;
+        if (D) {
+            if (f0ok) D[((long long)f0 * L.rows + r) * L.cols + c] = s0;
+            if (f1ok) D[((long long)f1 * L.rows + r) * L.cols + c] = s1;
+        }
+        if (f0ok && s0 > thresh)
+            key = ((unsigned long long)score_order(s0) << 32) | (unsigned long long)(~pack_window(f0, k, r, c));
+        if (f1ok && s1 > thresh) {
+            const unsigned long long k1 =
+                ((unsigned long long)score_order(s1) << 32) | (unsigned long long)(~pack_window(f1, k, r, c));
+            key = k1 > key ? k1 : key;
+        }
+    }
+    // best over the group's filters of the same window: lanes j, j + 16, j + 32, j + 48
+#pragma unroll
+    for (int sft = 16; sft < 64; sft <<= 1) {
+        const unsigned long long o = __shfl_xor(key, sft, 64);
+        key = o > key ? o : key;
+    }
+    if (PK && cok && g4 == 0) {
+        if (atomic_key) {
+            if (key) atomicMax(PK + c, key);
+        } else {
+            PK[c] = key;
+        }
+    }
 }
 
 // The score of filter f at window (r, c) is bias_f plus the 3100-term dot
@@ -157,61 +221,8 @@ __device__ __forceinline__ void score_row(const DevLevel& L, int k, int r, const
         }
         wave_lds_order();
 
-        // Window c = 16 t - 9 + j takes P[c + dc] for dc >= 9 - j (cells of
-        // this tile) and window c + 16 starts its carry with the cells
-        // 7 + j + dc <= 15 of this tile; both are cell (7 + j + dc) mod 16,
-        // so one read per dc, added to one sum or the other (zeros keep
-        // the order of the additions).
-        float s0 = carry0, s1 = carry1, n0 = 0.f, n1 = 0.f;
-#pragma unroll
-        for (int dc = 0; dc < WIN; ++dc) {
-            const bool mine = dc >= WIN - 1 - j;
-            const float* p = ring + dc * SC_RSTR + ((j + 7 + dc) & 15);
-            const float v0 = p[WIN * SC_RSTR * g4];
-            s0 += mine ? v0 : 0.f;
-            n0 += mine ? 0.f : v0;
-            if (XTRA) {
-                const float v1 = p[WIN * SC_RSTR * 4];
-                s1 += mine ? v1 : 0.f;
-                n1 += mine ? 0.f : v1;
-            }
-        }
-        carry0 = n0;
-        carry1 = n1;
-        wave_lds_order();
-        if (t < t_begin) continue;   // carry-only tile
-
-        const int c = 16 * t - (WIN - 1) + j;
-        const bool cok = c >= 0 && c < L.cols;
-        unsigned long long key = 0ull;
-        if (cok) {
-            s0 += b0;
-            s1 += b1;
-            if (D) {
-                if (f0ok) D[((long long)f0 * L.rows + r) * L.cols + c] = s0;
-                if (f1ok) D[((long long)f1 * L.rows + r) * L.cols + c] = s1;
-            }
-            if (f0ok && s0 > thresh)
-                key = ((unsigned long long)score_order(s0) << 32) | (unsigned long long)(~pack_window(f0, k, r, c));
-            if (f1ok && s1 > thresh) {
-                const unsigned long long k1 =
-                    ((unsigned long long)score_order(s1) << 32) | (unsigned long long)(~pack_window(f1, k, r, c));
-                key = k1 > key ? k1 : key;
-            }
-        }
-        // best over the group's filters of the same window: lanes j, j + 16, j + 32, j + 48
-#pragma unroll
-        for (int sft = 16; sft < 64; sft <<= 1) {
-            const unsigned long long o = __shfl_xor(key, sft, 64);
-            key = o > key ? o : key;
-        }
-        if (PK && cok && g4 == 0) {
-            if (atomic_key) {
-                if (key) atomicMax(PK + c, key);
-            } else {
-                PK[c] = key;
-            }
-        }
+        tile_windows<XTRA>(L, k, r, t, t_begin, ring, carry0, carry1, g4, j, f0, f1, f0ok, f1ok, b0, b1, thresh, D,
+                           PK, atomic_key);
     }
 }
 
@@ -258,6 +269,160 @@ __device__ __forceinline__ void score_item(const LevelTable& T, int frame, int g
     else
         score_row<1, false, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane, tb,
                                   te);
+}
+
+// ------------------------------------------- separable (row / column) filters
+// The paper's classifier kernels (Sec. V-A) filter every feature channel
+// along the 10 horizontal neighbours of a cell with a row filter and then
+// along the 10 vertical neighbours with a column filter.  A filter made of
+// RANK such pairs per channel, W_f[dr][dc][ch] = sum_i col_f,i[dr][ch]
+// row_f,i[dc][ch], is scored here in the other order, which suits the
+// matrix cores: for window row r,
+//   G_f,i[x][ch] = sum_dr col_f,i[dr][ch] F[r + dr][x][ch]      (vector ALUs)
+//   P[x][(f, dc)] = sum_i sum_ch G_f,i[x][ch] row_f,i[dc][ch]   (matrix cores)
+// and then S_f(r, c) = bias_f + sum_dc P[c + dc][(f, dc)] exactly as for a
+// full filter (tile_windows).  The contraction has K = 32 RANK per filter
+// instead of 320, and the column pass 10 multiply-adds per (cell, channel,
+// filter, pair).
+
+// LDS of a separable scoring item: per filter f of the group and pair i the
+// column factor colw[f][i][dr][32] (channel 31 zero) and the row factor as
+// MFMA B operands B[f][i][kc][lane] = the four K values (channels)
+// 16 kc + 4 (lane / 16) + s, s = 0..3, of column dc = lane % 16 (zero for
+// dc >= 10); then per wave the partial-product tile.
+template <int ROWS, int RANK>
+struct SepSmemT {
+    float4 B[FGROUP * RANK * 2 * 64];
+    float colw[FGROUP * RANK * WIN * FPAD];
+    float P[ROWS][SC_RING];
+};
+
+// Fills the factors of filter group grp from row / col [nf][RANK][10][31].
+template <int ROWS, int RANK>
+__device__ __forceinline__ void load_sep(SepSmemT<ROWS, RANK>& sm, const float* __restrict__ row,
+                                         const float* __restrict__ col, int nf, int grp, int tid) {
+    for (int e = tid; e < FGROUP * RANK * WIN * FPAD; e += ROWS * 64) {
+        const int ch = e % FPAD, dr = (e / FPAD) % WIN, fi = e / (FPAD * WIN);
+        const int f = grp * FGROUP + fi / RANK, i = fi % RANK;
+        sm.colw[e] = (f < nf && ch < NFEAT) ? col[((f * RANK + i) * WIN + dr) * NFEAT + ch] : 0.f;
+    }
+    for (int e = tid; e < FGROUP * RANK * 2 * 64; e += ROWS * 64) {
+        const int ln = e & 63, kc = (e >> 6) & 1, fi = e >> 7;
+        const int f = grp * FGROUP + fi / RANK, i = fi % RANK;
+        const int dc = ln & 15, ch0 = 16 * kc + 4 * (ln >> 4);
+        float v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int ch = ch0 + q;
+            v[q] = (f < nf && dc < WIN && ch < NFEAT) ? row[((f * RANK + i) * WIN + dc) * NFEAT + ch] : 0.f;
+        }
+        sm.B[e] = make_float4(v[0], v[1], v[2], v[3]);
+    }
+}
+
+// One window row r with separable filters; arguments and outputs as
+// score_row.  Lane (g4, j) reads the float4 of channels 16 kc + 4 g4 ..
+// + 3 of cell 16 t + j in the ten feature rows r .. r + 9, forms G for
+// those channels (the A operand of four MFMAs per chunk kc), and holds
+// P[16 t + 4 g4 + q][dc = j] of each filter after the contraction.
+template <int RANK, bool XTRA, int ROWS>
+__device__ __forceinline__ void score_row_sep(const DevLevel& L, int k, int r, const float* __restrict__ Ffr,
+                                              const SepSmemT<ROWS, RANK>& sm, float* __restrict__ ring, int grp,
+                                              int nf, const float* __restrict__ bias, float thresh,
+                                              float* __restrict__ Dfr, unsigned long long* __restrict__ PKfr,
+                                              int atomic_key, int lane, int t_begin, int t_end) {
+    const int g4 = lane >> 4, j = lane & 15;
+    const int pitch = (L.cx + 2) * FPAD;
+    const float* __restrict__ Fr = Ffr + L.feat_off + (long long)r * pitch + 4 * g4;
+    const int fg = min(FGROUP, nf - grp * FGROUP);
+    const int f0 = grp * FGROUP + g4, f1 = f0 + 4;
+    const bool f0ok = f0 < nf, f1ok = XTRA && g4 == 0;
+    const float b0 = f0ok ? bias[f0] : 0.f, b1 = f1ok ? bias[f1] : 0.f;
+    float* __restrict__ D = Dfr ? Dfr + L.sc_off : nullptr;
+    unsigned long long* __restrict__ PK = PKfr ? PKfr + L.pos_off + (long long)r * L.cols : nullptr;
+    const int t_first = max(t_begin - 1, 0);
+    float carry0 = 0.f, carry1 = 0.f;
+    for (int t = t_first; t < t_end; ++t) {
+        const float* __restrict__ a = Fr + min(16 * t + j, L.cx + 1) * FPAD;
+        // the K chunks (channels 0..15, 16..31) one after the other, so that
+        // only one chunk's ten operands are live; the five filters'
+        // accumulators carry over (a filter past the group's end has zero
+        // factors and is skipped)
+        floatx4 acc[FGROUP];
+#pragma unroll
+        for (int f = 0; f < FGROUP; ++f) acc[f] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kc = 0; kc < 2; ++kc) {
+            float4 av[WIN];
+#pragma unroll
+            for (int dr = 0; dr < WIN; ++dr) av[dr] = *reinterpret_cast<const float4*>(a + dr * pitch + 16 * kc);
+#pragma unroll
+            for (int f = 0; f < FGROUP; ++f) {
+                if (f >= fg) break;
+#pragma unroll
+                for (int i = 0; i < RANK; ++i) {
+                    const float* __restrict__ cw = sm.colw + ((f * RANK + i) * WIN) * FPAD + 16 * kc + 4 * g4;
+                    float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+                    for (int dr = 0; dr < WIN; ++dr) {
+                        const float4 w = *reinterpret_cast<const float4*>(cw + dr * FPAD);
+                        g.x = fmaf(w.x, av[dr].x, g.x);
+                        g.y = fmaf(w.y, av[dr].y, g.y);
+                        g.z = fmaf(w.z, av[dr].z, g.z);
+                        g.w = fmaf(w.w, av[dr].w, g.w);
+                    }
+                    const float4 bq = sm.B[((f * RANK + i) * 2 + kc) * 64 + lane];
+                    acc[f] = __builtin_amdgcn_mfma_f32_16x16x4f32(g.x, bq.x, acc[f], 0, 0, 0);
+                    acc[f] = __builtin_amdgcn_mfma_f32_16x16x4f32(g.y, bq.y, acc[f], 0, 0, 0);
+                    acc[f] = __builtin_amdgcn_mfma_f32_16x16x4f32(g.z, bq.z, acc[f], 0, 0, 0);
+                    acc[f] = __builtin_amdgcn_mfma_f32_16x16x4f32(g.w, bq.w, acc[f], 0, 0, 0);
+                }
+            }
+        }
+        wave_lds_order();
+#pragma unroll
+        for (int f = 0; f < FGROUP; ++f)
+            if (f < fg && j < WIN)
+                *reinterpret_cast<float4*>(ring + (WIN * f + j) * SC_RSTR + 4 * g4) =
+                    make_float4(acc[f][0], acc[f][1], acc[f][2], acc[f][3]);
+        wave_lds_order();
+        tile_windows<XTRA>(L, k, r, t, t_begin, ring, carry0, carry1, g4, j, f0, f1, f0ok, f1ok, b0, b1, thresh, D,
+                           PK, atomic_key);
+    }
+}
+
+// One separable scoring item; as score_item.
+template <int ROWS, int RANK>
+__device__ __forceinline__ void score_item_sep(const LevelTable& T, int frame, int grp, int item,
+                                               const SepSmemT<ROWS, RANK>& sm, float* __restrict__ ring,
+                                               const float* __restrict__ feat, int nf, const float* __restrict__ bias,
+                                               float thresh, float* __restrict__ dense,
+                                               unsigned long long* __restrict__ poskey, int atomic_key, int tid,
+                                               int half = -1) {
+    const int q = item * ROWS + __builtin_amdgcn_readfirstlane(tid >> 6);
+    if (q >= T.rows_total) return;
+    const int k = HOG_FIND_LEVEL(T, q, row_off);
+    const DevLevel& L = T.L[k];
+    const int r = q - L.row_off;
+    const float* Ffr = feat + (long long)frame * T.feat_frame;
+    float* Dfr = dense ? dense + (long long)frame * T.dense_frame : nullptr;
+    unsigned long long* PKfr = poskey ? poskey + (long long)frame * T.pos_frame : nullptr;
+    const int fg = min(FGROUP, nf - grp * FGROUP);
+    const int lane = tid & 63;
+    const int ntiles = (L.cx + 15) >> 4;
+    int tb = 0, te = ntiles;
+    if (half >= 0) {
+        const int mid = ntiles >= 3 ? (ntiles + 1) >> 1 : ntiles;
+        tb = half ? mid : 0;
+        te = half ? ntiles : mid;
+        if (tb >= te) return;
+    }
+    if (fg == FGROUP)
+        score_row_sep<RANK, true, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane,
+                                        tb, te);
+    else
+        score_row_sep<RANK, false, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key,
+                                         lane, tb, te);
 }
 
 }  // namespace hog

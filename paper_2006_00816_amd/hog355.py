@@ -43,6 +43,32 @@ class hog_constants(ctypes.Structure):
                 ("scale_den", ctypes.c_int32), ("clip", ctypes.c_float), ("eps", ctypes.c_float)]
 
 
+class hog_filterbank(ctypes.Structure):
+    _fields_ = [("nf", ctypes.c_int32), ("rank", ctypes.c_int32), ("W", ctypes.c_void_p), ("row", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("bias", ctypes.c_void_p)]
+
+
+class FilterBank:
+    """nf linear filters with biases, on the device: full filters W
+    [nf][10][10][31] (rank 0), or separable row / column factors
+    [nf][rank][10][31] with W[f][dr][dc][ch] = sum_i col[f][i][dr][ch] *
+    row[f][i][dc][ch] (rank 1..4)."""
+
+    def __init__(self, bias: torch.Tensor, W: torch.Tensor = None, row: torch.Tensor = None,
+                 col: torch.Tensor = None):
+        self.bias = bias
+        self.W, self.row, self.col = W, row, col
+        if W is not None:
+            self.nf, self.rank = int(W.shape[0]), 0
+        else:
+            if row is None or col is None or tuple(row.shape) != tuple(col.shape) or row.dim() != 4:
+                raise HogError("separable filters need row and col factors of shape [nf][rank][10][31]")
+            self.nf, self.rank = int(row.shape[0]), int(row.shape[1])
+        self.struct = hog_filterbank(self.nf, self.rank, _ptr(W) if W is not None else None,
+                                     _ptr(row) if row is not None else None, _ptr(col) if col is not None else None,
+                                     _ptr(bias))
+
+
 class hog_level(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("h", ctypes.c_int32), ("w", ctypes.c_int32),
                 ("cy", ctypes.c_int32), ("cx", ctypes.c_int32), ("rows", ctypes.c_int32),
@@ -78,6 +104,9 @@ def lib():
         "hog_workspace_bytes": ([i32, i32, i32, i32, i32], sz),
         "hog_features": ([vp, i32, i32, i32, i32, vp, i64, vp, sz, vp], i32),
         "hog_scores": ([vp, i32, i32, i32, i32, vp, vp, i32, vp, i64, vp, sz, vp], i32),
+        "hog_scores_bank": ([vp, i32, i32, i32, i32, vp, vp, i64, vp, sz, vp], i32),
+        "hog_detect_batch_bank": ([vp, vp, i32, i32, i32, i32, i64, vp, vp, i32, vp, vp, sz, vp], i32),
+        "hog_graph_create_bank": ([vp, vp, vp, i32, i32, i32, i32, i64, vp, vp, i32, vp, vp, sz, vp], i32),
         "hog_detect": ([vp, vp, i32, i32, i32, vp, vp, i32, vp, i32, vp, vp, sz, vp], i32),
         "hog_detect_batch": ([vp, vp, i32, i32, i32, i32, i64, vp, vp, i32, vp, i32, vp, vp, sz, vp], i32),
         "hog_graph_create": ([vp, vp, vp, i32, i32, i32, i32, i64, vp, vp, i32, vp, i32, vp, vp, sz, vp], i32),
@@ -228,6 +257,41 @@ def scores(frame: torch.Tensor, W: torch.Tensor, b: torch.Tensor, upsample: int 
              .view(nf, l["rows"], l["cols"])) for l in levels]
 
 
+def scores_bank(frame: torch.Tensor, bank: FilterBank, upsample: int = 1, ws=None):
+    """Dense window scores per level for a filter bank: list of (level dict,
+    tensor [nf][rows][cols])."""
+    h, w, pitch = _frame_args(frame)
+    nf = bank.nf
+    levels = pyramid(h, w, upsample, nf)
+    total = sum(nf * l["rows"] * l["cols"] for l in levels)
+    out = torch.empty(max(total, 1), dtype=torch.float32, device=frame.device)
+    wp, wn = _ws(ws, workspace_bytes(h, w, upsample, 1, nf))
+    _check(lib().hog_scores_bank(_fptr(frame), h, w, pitch, upsample, ctypes.byref(bank.struct), _ptr(out),
+                                 out.numel(), wp, wn, _stream()), "hog_scores_bank")
+    return [(l, out[l["score_offset"]:l["score_offset"] + nf * l["rows"] * l["cols"]]
+             .view(nf, l["rows"], l["cols"])) for l in levels]
+
+
+def detect_batch_bank_into(frames: torch.Tensor, bank: FilterBank, dets: torch.Tensor, n_dets: torch.Tensor,
+                           thresh: float = 0.0, iou: float = 0.5, upsample: int = 1, ws=None):
+    """Enqueue hog_detect_batch_bank into caller-provided outputs."""
+    if frames.dtype != torch.uint8 or frames.dim() != 3:
+        raise HogError("frames must be a uint8 [n][h][w] device tensor")
+    n, h, w = (int(v) for v in frames.shape)
+    prm = _params(thresh, iou, upsample)
+    wp, wn = _ws(ws, workspace_bytes(h, w, upsample, n, bank.nf))
+    _check(lib().hog_detect_batch_bank(ctypes.byref(prm), _fptr(frames), n, h, w, int(frames.stride(1)),
+                                       int(frames.stride(0)), ctypes.byref(bank.struct), _ptr(dets),
+                                       int(dets.shape[1]), _ptr(n_dets), wp, wn, _stream()), "hog_detect_batch_bank")
+
+
+def detect_batch_bank(frames: torch.Tensor, bank: FilterBank, thresh=0.0, iou=0.5, upsample=1, cap=MAX_DETS,
+                      ws=None):
+    dets, nd = alloc_dets(int(frames.shape[0]), cap, frames.device)
+    detect_batch_bank_into(frames, bank, dets, nd, thresh, iou, upsample, ws)
+    return dets_to_numpy(dets, nd)
+
+
 def _params(thresh, iou, upsample):
     return hog_params(upsample, thresh, iou)
 
@@ -356,23 +420,27 @@ class BoundGraph:
 
 class DetectGraph:
     """hog_detect_batch captured once as a hipGraph over fixed buffers and
-    replayed; refresh ``frames`` in place between replays."""
+    replayed; refresh ``frames`` in place between replays.  ``bank`` (a
+    FilterBank) takes the place of W and b when given."""
 
-    def __init__(self, frames: torch.Tensor, W, b, cap=MAX_DETS, thresh=0.0, iou=0.5, upsample=1):
+    def __init__(self, frames: torch.Tensor, W=None, b=None, cap=MAX_DETS, thresh=0.0, iou=0.5, upsample=1,
+                 bank: FilterBank = None):
         n, h, w = (int(v) for v in frames.shape)
-        nf = int(W.shape[0])
-        self.frames, self.W, self.b = frames, W, b
+        if bank is None:
+            bank = FilterBank(b, W=W)
+        nf = bank.nf
+        self.frames, self.bank = frames, bank
         self.dets, self.n_dets = alloc_dets(n, cap, frames.device)
         self.ws = torch.empty(workspace_bytes(h, w, upsample, n, nf), dtype=torch.uint8, device=frames.device)
         self.prm = _params(thresh, iou, upsample)
         self.stream = torch.cuda.Stream(device=frames.device)
         self.handle = ctypes.c_void_p()
         torch.cuda.synchronize(frames.device)
-        _check(lib().hog_graph_create(ctypes.byref(self.handle), ctypes.byref(self.prm), _fptr(frames), n, h, w,
-                                      int(frames.stride(1)), int(frames.stride(0)), _ptr(W), _ptr(b), nf,
-                                      _ptr(self.dets), cap, _ptr(self.n_dets), ctypes.c_void_p(self.ws.data_ptr()),
-                                      self.ws.numel(), ctypes.c_void_p(self.stream.cuda_stream)),
-               "hog_graph_create")
+        _check(lib().hog_graph_create_bank(ctypes.byref(self.handle), ctypes.byref(self.prm), _fptr(frames), n, h,
+                                           w, int(frames.stride(1)), int(frames.stride(0)), ctypes.byref(bank.struct),
+                                           _ptr(self.dets), cap, _ptr(self.n_dets),
+                                           ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                           ctypes.c_void_p(self.stream.cuda_stream)), "hog_graph_create_bank")
 
     def launch(self):
         _check(lib().hog_graph_launch(self.handle, _stream()), "hog_graph_launch")

@@ -81,6 +81,21 @@ def filters(seeds, sigma: float = 0.1, bias: float = -0.5):
     return W, b
 
 
+def separable_filters(seeds, rank: int = 1, bias: float = -0.5):
+    """Separable filters: row and column factors [nf][rank][10][31] with
+    N(0, s^2) entries, one seed per filter, s = (0.01 / rank)^(1/4), so that
+    the combined weights sum_i col * row have the variance 0.01 of the full
+    random filters; and a constant bias per filter."""
+    sd = (0.01 / rank) ** 0.25
+    rows, cols = [], []
+    for s in seeds:
+        rng = np.random.default_rng(s)
+        rows.append(rng.normal(0.0, sd, (rank, WIN_CELLS, NFEAT)))
+        cols.append(rng.normal(0.0, sd, (rank, WIN_CELLS, NFEAT)))
+    b = np.full(len(rows), bias, dtype=np.float32)
+    return np.stack(rows).astype(np.float32), np.stack(cols).astype(np.float32), b
+
+
 @dataclasses.dataclass
 class Workload:
     frames: np.ndarray            # uint8 [n][h][w]

@@ -51,11 +51,21 @@ def decisions(windows, thresh, iou, near):
     """Three-valued greedy NMS over `windows` (oracle CAND_DTYPE records of
     every window scoring above thresh - near).  Returns the windows in rank
     order and their decisions."""
+    c, st, _ = decisions_with_conflicts(windows, thresh, iou, near)
+    return c, st
+
+
+def decisions_with_conflicts(windows, thresh, iou, near):
+    """decisions(), also returning the conflict lists (rank order)."""
     c = windows[oracle.rank_order(windows)]
-    s = c["score"]
-    maybe = np.abs(s - thresh) < near          # candidacy not certain
     conf = _conflict_lists(c, iou)
-    tie = np.zeros(len(c), bool)                # rank against a conflicting window not certain
+    return c, _decide(c, conf, thresh, near), conf
+
+
+def _decide(c, conf, thresh, near):
+    s = c["score"]
+    maybe = np.abs(s - thresh) < near
+    tie = np.zeros(len(c), bool)
     for i, js in enumerate(conf):
         if len(js) and np.any(np.abs(s[js] - s[i]) < near):
             tie[i] = True
@@ -69,15 +79,45 @@ def decisions(windows, thresh, iou, near):
             st[i] = UNKNOWN
         elif np.all(sb == DROPPED):
             st[i] = KEPT
-    return c, st
+    return st
 
 
-def check_kept(frame, W, b, upsample, dets, thresh=0.0, iou=0.5, near=1e-4):
+def check_ranking(c, conf, cand_gpu, near):
+    """Among the GPU's candidates (structured array with the GPU's float32
+    scores), every pair of conflicting windows is ranked as the oracle
+    ranks them (c: oracle windows in rank order, conf: their conflict
+    lists), unless the two oracle scores are within `near`.  Returns the
+    number of conflicting pairs checked."""
+    key = {k: i for i, k in enumerate(zip(c["f"].tolist(), c["k"].tolist(), c["r"].tolist(), c["c"].tolist()))}
+    n = len(c)
+    gs = np.full(n, np.nan)
+    gidx = np.full(n, -1, np.int64)
+    g = cand_gpu[oracle.rank_order(cand_gpu)]
+    for pos, kk in enumerate(zip(g["f"].tolist(), g["k"].tolist(), g["r"].tolist(), g["c"].tolist())):
+        i = key[kk]
+        gs[i] = g["score"][pos]
+        gidx[i] = pos                      # the GPU's rank
+    s = c["score"]
+    pairs = 0
+    for i, js in enumerate(conf):
+        if gidx[i] < 0:
+            continue
+        js = js[(js < i) & (gidx[js] >= 0)]          # oracle ranks j before i
+        pairs += len(js)
+        flipped = js[gidx[js] > gidx[i]]
+        bad = flipped[np.abs(s[flipped] - s[i]) >= near]
+        assert len(bad) == 0, (f"GPU ranks window {i} above conflicting window {int(bad[0])} although "
+                               f"their oracle scores differ by {float(s[bad[0]] - s[i]):.3g}")
+    return pairs
+
+
+def check_kept(frame, W, b, upsample, dets, thresh=0.0, iou=0.5, near=1e-4, cand_gpu=None):
     """End-to-end check of a frame's GPU detections against the oracle:
     every window whose decision is sure must be kept or dropped on the GPU
-    exactly as by the oracle; returns statistics of the comparison."""
+    exactly as by the oracle; with the GPU's candidates, also their rank
+    order (check_ranking).  Returns statistics of the comparison."""
     allw = oracle.candidates(frame, W, b, thresh - near, upsample)
-    c, st = decisions(allw, thresh, iou, near)
+    c, st, conf = decisions_with_conflicts(allw, thresh, iou, near)
     key = list(zip(c["f"].tolist(), c["k"].tolist(), c["r"].tolist(), c["c"].tolist()))
     index = {k: i for i, k in enumerate(key)}
     got = list(zip(dets["filter"].tolist(), dets["level"].tolist(), dets["row"].tolist(), dets["col"].tolist()))
@@ -90,6 +130,8 @@ def check_kept(frame, W, b, upsample, dets, thresh=0.0, iou=0.5, near=1e-4):
     bad = np.nonzero(sure & (kept_gpu != want))[0]
     stats = {"windows": int(len(c)), "unknown": int((~sure).sum()), "kept_sure": int(want.sum()),
              "kept_unknown_gpu": int((kept_gpu & ~sure).sum()), "differ_sure": int(len(bad))}
+    if cand_gpu is not None:
+        stats["ranked_pairs"] = check_ranking(c, conf, cand_gpu, near)
     assert len(bad) == 0, (f"sure decisions differ at {len(bad)} windows, e.g. "
                            f"{[(key[i], float(c['score'][i]), int(st[i])) for i in bad[:5]]}; {stats}")
     return stats

@@ -460,3 +460,59 @@ def test_nms_properties_random():
     perm = rng.permutation(n)
     assert np.array_equal(hog.nms(c[perm]), kept)
     assert np.all(np.diff(kept["score"]) <= 0)
+
+
+# ------------------------------------- separable (row / column) filters
+def test_separable_one_hot_factors_read_one_feature():
+    """Row factor e_(dc0, ch0) and column factor e_(dr0, ch0): the filter is
+    one-hot at (dr0, dc0, ch0), so the score reads F[r + dr0][c + dc0][ch0]
+    (a transposed or swapped factor reads another cell)."""
+    rng = np.random.default_rng(41)
+    F = rng.random((14, 17, 31))
+    for dr0, dc0, ch0 in ((0, 0, 0), (3, 7, 12), (9, 2, 30), (5, 9, 27)):
+        row = np.zeros((1, 1, 10, 31))
+        col = np.zeros((1, 1, 10, 31))
+        row[0, 0, dc0, ch0] = 1.0
+        col[0, 0, dr0, ch0] = 1.0
+        S = hog.window_scores(F, hog.separable_filters(row, col), np.array([0.25]))
+        assert np.array_equal(S[0], F[dr0:dr0 + 5, dc0:dc0 + 8, ch0] + 0.25)
+
+
+def test_separable_full_rank_svd_reproduces_filter():
+    """numpy's SVD of each channel's 10x10 weight matrix W[:, :, ch] =
+    U diag(s) V^T gives rank-10 factors col_i = s_i U[:, i] (over dr) and
+    row_i = V^T[i, :] (over dc); their sum is the filter again."""
+    rng = np.random.default_rng(42)
+    W = rng.normal(0, 0.1, (3, 10, 10, 31))
+    row = np.zeros((3, 10, 10, 31))
+    col = np.zeros((3, 10, 10, 31))
+    for f in range(3):
+        for ch in range(31):
+            U, sv, Vt = np.linalg.svd(W[f, :, :, ch])
+            for i in range(10):
+                col[f, i, :, ch] = sv[i] * U[:, i]
+                row[f, i, :, ch] = Vt[i, :]
+    assert np.allclose(hog.separable_filters(row, col), W, rtol=0, atol=1e-14)
+
+
+def test_separable_two_pass_equals_filter_scores():
+    """The paper's two passes written out as loops on a tiny feature map
+    (row filter into a scratch image per channel, then the column filter,
+    then the sum over channels) equal the scores of the combined filter."""
+    rng = np.random.default_rng(43)
+    F = rng.random((12, 13, 31))
+    row = rng.normal(0, 0.1, (2, 2, 10, 31))
+    col = rng.normal(0, 0.1, (2, 2, 10, 31))
+    b = np.array([0.1, -0.2])
+    S = hog.window_scores(F, hog.separable_filters(row, col), b)
+    R, C = 3, 4
+    for f in range(2):
+        for r in range(R):
+            for c in range(C):
+                tot = b[f]
+                for i in range(2):
+                    for ch in range(31):
+                        scratch = [sum(row[f, i, dc, ch] * F[y, c + dc, ch] for dc in range(10))
+                                   for y in range(r, r + 10)]
+                        tot += sum(col[f, i, dr, ch] * scratch[dr] for dr in range(10))
+                assert abs(S[f, r, c] - tot) < 1e-12
