@@ -49,11 +49,14 @@ extern "C" {
 #define HOG_E_NOTIMPL    -6
 #define HOG_E_DEVICE     -7   /* written to n_dets: a bounded device-side wait of the fused kernel
                                  gave up; that frame's detections are not valid */
+#define HOG_E_SCRATCH    -8   /* hog_detect_batch_static: the call needs more workspace than
+                                 HOG_STATIC_SCRATCH_BYTES */
 
 #define HOG_MAX_SIDE     4096
 #define HOG_MAX_FILTERS  32
 #define HOG_MAX_LEVELS   28
 #define HOG_MAX_DETS     4096 /* largest per-frame detection capacity */
+#define HOG_STATIC_SCRATCH_BYTES (64u << 20)  /* fixed workspace of hog_detect_batch_static */
 
 /* Detection parameters (Sec. IV-A, classification and NMS). */
 typedef struct hog_params {
@@ -208,6 +211,25 @@ int hog_detect_batch(const hog_params* prm, const uint8_t* frames, int n,
                      hog_det* dets, int cap, int* n_dets,
                      void* ws, size_t ws_bytes, void* stream);
 
+/* hog_detect_batch without a workspace argument, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  The workspace is a fixed array
+ * of HOG_STATIC_SCRATCH_BYTES (64 MiB) inside the library, one per GPU,
+ * held from the first call (or hog_init) on that GPU until the process
+ * ends.  Shapes whose hog_workspace_bytes(h, w, upsample, n, nf) exceeds it
+ * return HOG_E_SCRATCH with nothing enqueued (64 MiB holds 8 frames of
+ * 640x480 with 5 filters, or 3 of 1280x720).  The call allocates nothing:
+ * no hipMalloc, no hipFree, no allocating library routine.  Every call on
+ * one GPU uses the same array and leaves its contents behind; each call
+ * clears what must start at zero.  Calls that overlap in time on one GPU
+ * (two streams, two host threads) race on the array and give wrong
+ * detections: serialise them.  Arguments, outputs, schedule and detections
+ * are those of hog_detect_batch. */
+int hog_detect_batch_static(const hog_params* prm, const uint8_t* frames, int n,
+                            int h, int w, int pitch, int64_t frame_stride,
+                            const float* filters, const float* bias, int nf,
+                            hog_det* dets, int cap, int* n_dets, void* stream);
+
 /* hog_detect_batch for a filter bank (full or separable; separable banks
  * run the per-stage schedule, with the shape's frame split and NMS rounds). */
 int hog_detect_batch_bank(const hog_params* prm, const uint8_t* frames, int n,
@@ -232,7 +254,8 @@ int hog_graph_launch(hog_graph* g, void* stream);
 int hog_graph_destroy(hog_graph* g);
 
 /* Set-up of the calling host thread on the current device: the helper
- * streams and events (default priority) that split schedules fork onto.
+ * streams and events (default priority) that split schedules fork onto,
+ * and the device address of the fixed array of hog_detect_batch_static.
  * hog_tuning_set (for a split schedule) and hog_autotune call it; a detect
  * call never creates them.  A split schedule run on a thread without them
  * runs its frame groups one after another on the caller's stream, with

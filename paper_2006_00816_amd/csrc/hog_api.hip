@@ -504,6 +504,36 @@ int detect_sequence(const Plan& P, const hog_params* prm, const uint8_t* frames,
     return st;
 }
 
+// ------------------------------------------ fixed scratch (no allocation)
+// The workspace of hog_detect_batch_static: one fixed array per GPU, held
+// until the process ends.  Host code never passes `scratch` itself to a
+// kernel (its host-side name is not a device address); it uses the address
+// that hipGetSymbolAddress reports for the current device.
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[HOG_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+// Device address of the current device's scratch array, looked up once per
+// device (hog_init, else the first hog_detect_batch_static on the device).
+int static_scratch(void** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return HOG_E_HIP;
+    if (dev < 0 || dev >= MAX_DEVICES) return HOG_E_INVAL;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return HOG_E_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return HOG_OK;
+}
+
 int check_bank(const hog_filterbank* fb) {
     if (!fb || !fb->bias || fb->nf < 1) return HOG_E_INVAL;
     if (fb->nf > MAX_FILTERS) return HOG_E_TOO_LARGE;
@@ -586,6 +616,7 @@ const char* hog_strerror(int st) {
         case HOG_E_HIP: return "HIP launch or runtime failure";
         case HOG_E_NOTIMPL: return "not implemented";
         case HOG_E_DEVICE: return "a bounded device-side wait gave up (detections not valid)";
+        case HOG_E_SCRATCH: return "the call needs more workspace than the library's fixed scratch array";
         default: return "unknown status";
     }
 }
@@ -683,6 +714,22 @@ int hog_detect_batch(const hog_params* prm, const uint8_t* frames, int n, int h,
                                  stream);
 }
 
+int hog_detect_batch_static(const hog_params* prm, const uint8_t* frames, int n, int h, int w, int pitch,
+                            int64_t frame_stride, const float* filters, const float* bias, int nf, hog_det* dets,
+                            int cap, int* n_dets, void* stream) {
+    HOG_TRY(check_detect_args(prm, frames, pitch, w, filters, bias, nf, dets, cap, n_dets));
+    if (n < 1 || (n > 1 && frame_stride < (int64_t)pitch * h)) return HOG_E_INVAL;
+    Plan P;
+    HOG_TRY(make_plan(h, w, prm->upsample, n, nf, &P));
+    if (P.total > (size_t)HOG_STATIC_SCRATCH_BYTES) return HOG_E_SCRATCH;
+    void* ws = nullptr;
+    HOG_TRY(static_scratch(&ws));
+    const hog_filterbank fb = full_bank(filters, bias, nf);
+    const hog_tuning tune = lookup_tuning(h, w, prm->upsample, n, nf);
+    return detect_sequence(P, prm, frames, frame_stride, pitch, bank_of(&fb), dets, cap, n_dets, ws, tune,
+                           (hipStream_t)stream);
+}
+
 int hog_detect(const hog_params* prm, const uint8_t* frame, int h, int w, int pitch, const float* filters,
                const float* bias, int nf, hog_det* dets, int cap, int* n_dets, void* ws, size_t ws_bytes,
                void* stream) {
@@ -762,7 +809,11 @@ int hog_tuning_get(int h, int w, int upsample, int n, int nf, hog_tuning* out) {
     return found ? 1 : 0;
 }
 
-int hog_init(void) { return init_split_resources(); }
+int hog_init(void) {
+    HOG_TRY(init_split_resources());
+    void* p = nullptr;
+    return static_scratch(&p);
+}
 
 int hog_tuning_set(int h, int w, int upsample, int n, int nf, const hog_tuning* t) {
     if (t && tuning_valid(*t) && t->split > 1) HOG_TRY(init_split_resources());

@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(_PKG, "libhog355.so")
 
 HOG_OK = 0
 MAX_DETS = 4096
+STATIC_SCRATCH_BYTES = 64 << 20
+HOG_E_SCRATCH = -8
 
 
 class HogError(RuntimeError):
@@ -109,6 +111,7 @@ def lib():
         "hog_graph_create_bank": ([vp, vp, vp, i32, i32, i32, i32, i64, vp, vp, i32, vp, vp, sz, vp], i32),
         "hog_detect": ([vp, vp, i32, i32, i32, vp, vp, i32, vp, i32, vp, vp, sz, vp], i32),
         "hog_detect_batch": ([vp, vp, i32, i32, i32, i32, i64, vp, vp, i32, vp, i32, vp, vp, sz, vp], i32),
+        "hog_detect_batch_static": ([vp, vp, i32, i32, i32, i32, i64, vp, vp, i32, vp, i32, vp, vp], i32),
         "hog_graph_create": ([vp, vp, vp, i32, i32, i32, i32, i64, vp, vp, i32, vp, i32, vp, vp, sz, vp], i32),
         "hog_graph_launch": ([vp, vp], i32),
         "hog_graph_destroy": ([vp], i32),
@@ -310,6 +313,20 @@ def detect_batch_into(frames: torch.Tensor, W: torch.Tensor, b: torch.Tensor, de
     _check(lib().hog_detect_batch(ctypes.byref(prm), _fptr(frames), n, h, w, int(frames.stride(1)),
                                   int(frames.stride(0)), _ptr(W), _ptr(b), nf, _ptr(dets), cap, _ptr(n_dets),
                                   wp, wn, _stream()), "hog_detect_batch")
+
+
+def detect_batch_static_into(frames: torch.Tensor, W: torch.Tensor, b: torch.Tensor, dets: torch.Tensor,
+                             n_dets: torch.Tensor, thresh: float = 0.0, iou: float = 0.5, upsample: int = 1):
+    """Enqueue hog_detect_batch_static (the library's fixed scratch array as
+    workspace, no allocation) into caller-provided outputs, as
+    detect_batch_into."""
+    if frames.dtype != torch.uint8 or frames.dim() != 3:
+        raise HogError("frames must be a uint8 [n][h][w] device tensor")
+    n, h, w = (int(v) for v in frames.shape)
+    prm = _params(thresh, iou, upsample)
+    _check(lib().hog_detect_batch_static(ctypes.byref(prm), _fptr(frames), n, h, w, int(frames.stride(1)),
+                                         int(frames.stride(0)), _ptr(W), _ptr(b), int(W.shape[0]), _ptr(dets),
+                                         int(dets.shape[1]), _ptr(n_dets), _stream()), "hog_detect_batch_static")
 
 
 def alloc_dets(n: int, cap: int, device="cuda"):

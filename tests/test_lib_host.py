@@ -37,7 +37,7 @@ def test_exports_every_declared_function(L):
 
 def test_version_and_strerror(L):
     assert L.hog_version() >= 100
-    for code in (0, -1, -2, -3, -4, -5, -6, -7):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8):
         assert L.hog_strerror(code)
     assert L.hog_strerror(-99) == b"unknown status"
 
@@ -100,6 +100,25 @@ def test_argument_errors_reported_before_launch(L):
     assert _detect(L, up=3) == -1
     assert _detect(L, ws_bytes=16) == -3
     assert _detect(L, ws=0) == -1
+
+
+def test_static_entry_point_checks_before_launch(L):
+    """hog_detect_batch_static: argument errors and shapes beyond the fixed
+    scratch array are rejected on the host (dummy pointers, no GPU)."""
+    from paper_2006_00816_amd import hog355
+    v = ctypes.c_void_p
+
+    def call(n, h, w, nf=5, frame=1):
+        p = hog355.hog_params(1, 0.0, 0.5)
+        return L.hog_detect_batch_static(ctypes.byref(p), v(frame) if frame else None, n, h, w, w, h * w, v(1),
+                                         v(1), nf, v(1), 16, v(1), None)
+    assert call(64, 480, 640) == hog355.HOG_E_SCRATCH == -8
+    assert call(1, 1080, 1920) == -8
+    assert hog355.workspace_bytes(480, 640, 1, 64, 5) > hog355.STATIC_SCRATCH_BYTES
+    assert call(1, 480, 640, frame=0) == -1
+    assert call(1, 480, 640, nf=0) == -1
+    assert call(0, 480, 640) == -1
+    assert L.hog_strerror(-8) == b"the call needs more workspace than the library's fixed scratch array"
 
 
 def test_level_table_limits(L):
