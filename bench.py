@@ -253,6 +253,40 @@ def separable_leg(hog355, frames, rank, steps, warmup, ksteps, ps):
             "kernels_per_step": kt, "score_roofline": [e for e in lines if e["kernel"] == "hog_sep_score_kernel"]}
 
 
+def pipeline_leg(frames_np, W, b, batches):
+    """The host pipeline (Sec. V-C): 64-frame batches of the clip submitted
+    from host memory, detections back to a consumer thread that counts the
+    boxes.  frames/s including both PCIe transfers, for frames in pageable
+    memory copied straight from there, pageable memory through the
+    pipeline's page-locked staging, and page-locked memory copied straight
+    from there."""
+    import torch
+    from paper_2006_00816_amd import hog355
+    n = frames_np.shape[0]
+    pinned = torch.from_numpy(frames_np).pin_memory()
+    out = []
+    for name, staging, src in (("pageable, direct", False, frames_np), ("pageable, staged", True, frames_np),
+                               ("page-locked, direct", False, pinned)):
+        boxes = [0]
+        p = hog355.Pipeline(W, b, H, W_PX, n, depth=3, cap=64, consumer_threads=2, staging=staging,
+                            consumer=lambda first, d, nd: boxes.__setitem__(0, boxes[0] + int(nd.sum())))
+        for i in range(2):
+            p.submit(src, i * n)
+        p.drain()
+        boxes[0] = 0
+        t0 = time.perf_counter()
+        for i in range(batches):
+            p.submit(src, i * n)
+        p.drain()
+        dt = time.perf_counter() - t0
+        p.close()
+        fps = batches * n / dt
+        out.append({"source": name, "fps": round(fps, 1), "ms_per_batch": round(1e3 * dt / batches, 4),
+                    "h2d_gbs": round(fps * H * W_PX / 1e9, 3), "boxes_per_frame": round(boxes[0] / (batches * n), 2)})
+    return {"workload": f"{batches} batches of the 64-frame 640x480 clip from host memory, 3 stages, 2 consumer "
+                        "threads, 64 detections per frame copied back", "legs": out}
+
+
 def copy_calibration(mib):
     """A plain device-to-device copy of known size, to scale the HBM byte
     counters (FETCH_SIZE, WRITE_SIZE) of the detector's kernels."""
@@ -265,6 +299,86 @@ def copy_calibration(mib):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes": n, "copies": 3}), flush=True)
+
+
+def batched_leg(hog355, frames, Wt, bt, args):
+    """The clip replayed from a hipGraph under the schedule the autotuner
+    picks (or the one named), with per-kernel HIP-event times of eager
+    steps of that schedule."""
+    import torch
+    staged = {"fused": 0, "queues": 8, "wg_per_queue": 32, "lag_f": 1, "lag_s": 2, "split": 1, "nms_rounds": 3,
+              "score_rows": 0}
+    fused = {**staged, "fused": 1}
+    tune_ms = None
+    if args.schedule == "auto":
+        tuning, tune_ms = hog355.autotune(frames, Wt, bt, reps=5)
+    else:
+        tuning = staged if args.schedule == "staged" else fused
+        hog355.tuning_set(H, W_PX, 1, CLIP, NF, tuning)
+    torch.cuda.synchronize()
+
+    g = hog355.DetectGraph(frames, Wt, bt)
+    for _ in range(args.warmup):
+        g.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.launch()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+
+    lat = []
+    for _ in range(min(args.steps, 200)):
+        t1 = time.perf_counter()
+        g.launch()
+        torch.cuda.synchronize()
+        lat.append(1e3 * (time.perf_counter() - t1))
+    lat = np.array(lat)
+    _, n_kept = hog355.dets_to_numpy(g.dets, g.n_dets)
+    g.close()
+
+    # kernel durations with HIP events on the launch streams, eager steps:
+    # of the timed schedule, and of the per-stage schedule with one group
+    # (every launch covers all 64 frames, no launch overlaps another), from
+    # which the rooflines are taken
+    ws = hog355.Workspace()
+    dets, nd = hog355.alloc_dets(CLIP, hog355.MAX_DETS)
+    ksteps = min(args.steps, args.kernel_steps)
+    names = ("geom", "hist", "feat", "score", "fused", "nms_edges", "nms")
+    run = lambda: hog355.detect_batch_into(frames, Wt, bt, dets, nd, ws=ws)
+    kern = kernel_times(hog355, run, names, ksteps) if ksteps else {}
+    if tuning == staged:
+        kern_staged = kern
+    else:
+        hog355.tuning_set(H, W_PX, 1, CLIP, NF, staged)
+        kern_staged = kernel_times(hog355, run, names, ksteps) if ksteps else {}
+        hog355.tuning_set(H, W_PX, 1, CLIP, NF, tuning)
+    return {"dt": dt, "lat": lat, "n_kept": n_kept, "tuning": tuning, "tune_ms": tune_ms, "kern": kern,
+            "kern_staged": kern_staged, "staged": staged, "ksteps": ksteps}
+
+
+def plain_leg(hog355, frames, Wt, bt, n_frames):
+    """One frame per call, submit to completion, on the clip's frames."""
+    import torch
+    ws = hog355.Workspace()
+    one = frames[0]
+    for _ in range(20):
+        hog355.detect(one, Wt, bt, ws=ws)
+    torch.cuda.synchronize()
+    pdets, pnd = hog355.alloc_dets(1, hog355.MAX_DETS)
+    plain_lat = []
+    t0 = time.perf_counter()
+    for i in range(n_frames):
+        t1 = time.perf_counter()
+        hog355.detect_batch_into(frames[i % CLIP:i % CLIP + 1], Wt, bt, pdets, pnd, ws=ws)
+        torch.cuda.synchronize()
+        plain_lat.append(1e3 * (time.perf_counter() - t1))
+    plain_dt = time.perf_counter() - t0
+    plain_lat = np.array(plain_lat)
+    return {"fps": round(n_frames / max(plain_dt, 1e-9), 1),
+            "p50_ms": round(float(np.percentile(plain_lat, 50)), 4),
+            "p99_ms": round(float(np.percentile(plain_lat, 99)), 4),
+            "latency": "one frame per call, submit to completion"}
 
 
 def main():
@@ -285,6 +399,11 @@ def main():
                     help="auto: run the library's autotuner on the clip first")
     ap.add_argument("--separable-rank", type=int, default=1,
                     help="also time the clip with separable filters of this rank (0: skip)")
+    ap.add_argument("--pipeline-batches", type=int, default=20,
+                    help="64-frame batches through the host pipeline per source (0: skip)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched clip (autotune, graph replay, kernel timing), e.g. to profile the "
+                         "other legs alone; the line then has no value")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run device-to-device copies of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -314,87 +433,17 @@ def main():
     bt = torch.from_numpy(wl.b).cuda()
     torch.cuda.synchronize()
 
-    # ---------------------------------------------------------- schedule
-    staged = {"fused": 0, "queues": 8, "wg_per_queue": 32, "lag_f": 1, "lag_s": 2, "split": 1, "nms_rounds": 3, "score_rows": 0}
-    fused = {"fused": 1, "queues": 8, "wg_per_queue": 32, "lag_f": 1, "lag_s": 2, "split": 1, "nms_rounds": 3, "score_rows": 0}
-    tune_ms = None
-    if args.schedule == "auto":
-        tuning, tune_ms = hog355.autotune(frames, Wt, bt, reps=5)
-    else:
-        tuning = staged if args.schedule == "staged" else fused
-        hog355.tuning_set(H, W_PX, 1, CLIP, NF, tuning)
-    torch.cuda.synchronize()
-
-    # ---------------------------------------------------------- batched
-    g = hog355.DetectGraph(frames, Wt, bt)
-    for _ in range(args.warmup):
-        g.launch()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        g.launch()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    fps = CLIP * args.steps / dt
-    ms_per_step = 1e3 * dt / args.steps
-
-    lat = []
-    for _ in range(min(args.steps, 200)):
-        t1 = time.perf_counter()
-        g.launch()
-        torch.cuda.synchronize()
-        lat.append(1e3 * (time.perf_counter() - t1))
-    lat = np.array(lat)
-    _, n_kept = hog355.dets_to_numpy(g.dets, g.n_dets)
-
-    # kernel durations with HIP events on the launch streams, eager steps of
-    # the timed schedule
-    ws = hog355.Workspace()
-    dets, nd = hog355.alloc_dets(CLIP, hog355.MAX_DETS)
-    ksteps = min(args.steps, args.kernel_steps)
-    names = ("geom", "hist", "feat", "score", "fused", "nms_edges", "nms")
-    kern = kernel_times(hog355, lambda: hog355.detect_batch_into(frames, Wt, bt, dets, nd, ws=ws), names,
-                        ksteps) if ksteps else {}
-
-    # ------------------------------------------------------------ plain
-    plain_lat = []
-    one = frames[0]
-    for _ in range(20 if args.plain_frames else 0):
-        hog355.detect(one, Wt, bt, ws=ws)
-    torch.cuda.synchronize()
-    pdets, pnd = hog355.alloc_dets(1, hog355.MAX_DETS)
-    t0 = time.perf_counter()
-    for i in range(args.plain_frames):
-        t1 = time.perf_counter()
-        hog355.detect_batch_into(frames[i % CLIP:i % CLIP + 1], Wt, bt, pdets, pnd, ws=ws)
-        torch.cuda.synchronize()
-        plain_lat.append(1e3 * (time.perf_counter() - t1))
-    plain_dt = time.perf_counter() - t0
-    plain_lat = np.array(plain_lat if plain_lat else [0.0])
-
-    # ----------------------------------------------------------- roofline
     ps = pyramid_stats(H, W_PX, NF)
     win = ps["windows"]
     flop_per_frame = 2.0 * 3100 * NF * win
-    lines = rooflines(kern, ps, CLIP, 2.0 * 3100 * NF, "hog_score_kernel")
-    # the dominant kernel: most GPU time per step among the stage kernels
-    roofline = max(lines, key=lambda e: e["ms_per_step"]) if lines else None
-    # the whole path against the FP32 and HBM rooflines: algorithmic scoring
-    # FLOP, and the bytes a frame must cross (frame in, detections out)
-    det_bytes = 40.0 * float(np.mean(n_kept))
-    path = {"fp32_tflops": round(flop_per_frame * fps / 1e12, 3),
-            "fp32_frac": round(flop_per_frame * fps / 1e12 / FP32_PEAK_TFLOPS, 4),
-            "hbm_gbs": round((H * W_PX + det_bytes) * fps / 1e9, 2),
-            "hbm_frac": round((H * W_PX + det_bytes) * fps / 1e9 / HBM_PEAK_GBS, 5)}
-
     out = {
         "metric": METRIC,
-        "value": round(fps, 1),
+        "value": None,
         "unit": "frames/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -403,22 +452,42 @@ def main():
         "config": {"workload": "64-frame 640x480 u8 clip (config 1), 5 filters 10x10x31 f32, batched hipGraph",
                    "frames_per_step": CLIP, "h": H, "w": W_PX, "filters": NF, "levels": ps["levels"],
                    "windows_per_frame": win, "thresh": 0.0, "iou": 0.5},
-        "batched": {"fps": round(fps, 1), "p50_ms": round(float(np.percentile(lat, 50)), 4),
-                    "p99_ms": round(float(np.percentile(lat, 99)), 4),
-                    "latency": "clip submit to completion (every frame of the clip)"},
-        "plain": {"fps": round(args.plain_frames / max(plain_dt, 1e-9), 1),
-                  "p50_ms": round(float(np.percentile(plain_lat, 50)), 4),
-                  "p99_ms": round(float(np.percentile(plain_lat, 99)), 4),
-                  "latency": "one frame per call, submit to completion"},
-        "schedule": {"tuning": tuning, "autotune_best_ms": tune_ms},
-        "kernels_per_step": kern,
-        "kept_per_frame_mean": float(np.mean(n_kept)),
-        "roofline": roofline,
-        "roofline_kernels": lines,
-        "roofline_path": path,
-        "paper_context": {"ms_per_frame": 0.333, "hardware": "NVIDIA Titan X (Pascal), 16 images per launch",
-                          "end_to_end_ms_per_frame": 0.533},
     }
+    if not args.no_batched:
+        bl = batched_leg(hog355, frames, Wt, bt, args)
+        fps = CLIP * args.steps / bl["dt"]
+        lines = rooflines(bl["kern_staged"], ps, CLIP, 2.0 * 3100 * NF, "hog_score_kernel")
+        # the dominant kernel: most GPU time per step among the stage kernels
+        roofline = max(lines, key=lambda e: e["ms_per_step"]) if lines else None
+        # the whole path against the FP32 and HBM rooflines: algorithmic
+        # scoring FLOP, and the bytes a frame must cross (frame in,
+        # detections out)
+        det_bytes = 40.0 * float(np.mean(bl["n_kept"]))
+        path = {"fp32_tflops": round(flop_per_frame * fps / 1e12, 3),
+                "fp32_frac": round(flop_per_frame * fps / 1e12 / FP32_PEAK_TFLOPS, 4),
+                "hbm_gbs": round((H * W_PX + det_bytes) * fps / 1e9, 2),
+                "hbm_frac": round((H * W_PX + det_bytes) * fps / 1e9 / HBM_PEAK_GBS, 5)}
+        out.update({
+            "value": round(fps, 1),
+            "ms_per_step": round(1e3 * bl["dt"] / args.steps, 4),
+            "batched": {"fps": round(fps, 1), "p50_ms": round(float(np.percentile(bl["lat"], 50)), 4),
+                        "p99_ms": round(float(np.percentile(bl["lat"], 99)), 4),
+                        "latency": "clip submit to completion (every frame of the clip)"},
+            "schedule": {"tuning": bl["tuning"], "autotune_best_ms": bl["tune_ms"]},
+            "kernels_per_step": bl["kern"],
+            "kernels_per_step_staged": {"tuning": bl["staged"], "kernels": bl["kern_staged"],
+                                        "note": "per-stage schedule, one group: each launch covers all 64 "
+                                                "frames and runs alone; the rooflines are taken from these"},
+            "kept_per_frame_mean": float(np.mean(bl["n_kept"])),
+            "roofline": roofline,
+            "roofline_kernels": lines,
+            "roofline_path": path,
+        })
+    if args.plain_frames > 0:
+        out["plain"] = plain_leg(hog355, frames, Wt, bt, args.plain_frames)
+    out["paper_context"] = {"ms_per_frame": 0.333, "hardware": "NVIDIA Titan X (Pascal), 16 images per launch",
+                            "end_to_end_ms_per_frame": 0.533}
+    ksteps = min(args.steps, args.kernel_steps)
     if args.separable_rank > 0:
         out["separable"] = separable_leg(hog355, frames, args.separable_rank, args.steps, args.warmup, ksteps, ps)
     if args.serve_seconds > 0:
@@ -427,8 +496,8 @@ def main():
         pools, Ws, bs = serve.pinned_pools(per_res=64)
         out["served"] = [serve.served_stream(rate, args.serve_seconds, Ws, bs, pools)[0]
                          for rate in (500.0, 2000.0, 8000.0)]
-    g.close()
-    del g, ws
+    if args.pipeline_batches > 0:
+        out["pipeline"] = pipeline_leg(wl.frames, Wt, bt, args.pipeline_batches)
     if args.train_steps > 0:
         out["train"] = train_leg(args.train_steps)
     if args.pixel_grad_frames > 0:

@@ -58,7 +58,33 @@ extern "C" {
 #define HOG_MAX_DETS     4096 /* largest per-frame detection capacity */
 #define HOG_STATIC_SCRATCH_BYTES (64u << 20)  /* fixed workspace of hog_detect_batch_static */
 
-/* Detection parameters (Sec. IV-A, classification and NMS). */
+/* Or-ed into an `upsample` argument (or hog_params.upsample): the recursive
+ * pyramid of the paper's image-scaling kernel (Sec. V-A: each scaled image
+ * is computed from the image one scale higher) instead of resampling every
+ * level from the frame.  Level 0 is the frame (upsample 1) or its 2x
+ * enlargement rounded to grey levels (upsample 2); level k is the bilinear
+ * 5/6 reduction of level k-1 (output pixel i at (12 i + 1) / 10 of the
+ * input, weights rounded to 1/256) rounded half up to 8-bit grey levels,
+ * of size floor(5 h_{k-1} / 6) x floor(5 w_{k-1} / 6).  Windows map back to
+ * the frame with the nominal scale u (5/6)^k as before.  The level images
+ * are built in the workspace.  Forward calls only: hog_filter_backward
+ * returns HOG_E_NOTIMPL for it. */
+#define HOG_PYRAMID_CASCADE 0x100
+
+/* Search region of one frame: only windows of pyramid levels
+ * k_lo <= k <= k_hi whose frame-pixel box lies inside the half-open
+ * rectangle [x0, x1) x [y0, y1) are candidates.  Sec. VII proposes
+ * restricting the scales and locations analysed per frame, as faces move
+ * little between consecutive video frames; hog_track_regions derives the
+ * next frame's region from this frame's detections.  The whole frame at
+ * every level is {0, 0, w, h, 0, HOG_ALL_LEVELS}. */
+typedef struct hog_region {
+    int32_t x0, y0, x1, y1, k_lo, k_hi;
+} hog_region;
+#define HOG_ALL_LEVELS (1 << 30)
+
+/* Detection parameters (Sec. IV-A, classification and NMS; Sec. V-A,
+ * image sequence with constant size). */
 typedef struct hog_params {
     int32_t upsample;  /* 1, or 2 to start the pyramid at twice the frame size
                           (Sec. III-B evaluates on 2x upscaled images) */
@@ -68,6 +94,18 @@ typedef struct hog_params {
                           (tested exactly on integer areas as
                           inter > iou * union, iou taken as its float32
                           value) */
+    int32_t min_face;  /* 0, or the smallest face side in frame pixels: the
+                          levels whose 80x80 window spans fewer frame pixels,
+                          80 / s_k < min_face, are not analysed at all
+                          (Sec. V-A skips the largest scale of 640x480 frames
+                          whose faces are at least 20 % of the image:
+                          min_face 96).  0 <= min_face <= 65536. */
+    const hog_region* regions;  /* NULL, or (device) one search region per
+                          frame of the call: windows outside it are not
+                          candidates, and histogram tiles and window rows
+                          that no window inside it needs are skipped.  Read
+                          when the work runs, so a captured graph sees the
+                          values current at each replay. */
 } hog_params;
 
 /* One pyramid level.  Level k has scale s_k = upsample * (5/6)^k and size
@@ -237,6 +275,20 @@ int hog_detect_batch_bank(const hog_params* prm, const uint8_t* frames, int n,
                           const hog_filterbank* fb, hog_det* dets, int cap, int* n_dets,
                           void* ws, size_t ws_bytes, void* stream);
 
+/* The next frame's search regions from this frame's detections, one per
+ * frame of a batch (for example, one per video stream): the box of the
+ * frame's best detection (dets[i * cap], the first in rank order) grown by
+ * `margin` frame pixels on every side and clipped to the h x w frame, with
+ * levels [level - span, level + span] (k_lo clipped at 0); where a frame has
+ * no valid detection (n_dets[i] <= 0), the whole frame at every level.
+ * Sec. VII proposes restricting the scales and locations analysed per
+ * frame, since faces move little between consecutive frames.  Runs on the
+ * device, so a detect -> track -> detect sequence needs no host round trip.
+ * dets [n][cap], n_dets [n], regions [n] (device).  0 <= margin <= 65536,
+ * 0 <= span <= HOG_MAX_LEVELS. */
+int hog_track_regions(const hog_det* dets, const int* n_dets, int n, int cap, int h, int w,
+                      int margin, int span, hog_region* regions, void* stream);
+
 /* A hipGraph holding the launches of one hog_detect_batch call with fixed
  * buffers, for replay.  The caller refreshes the frame buffer between
  * replays.  Creation captures on `stream` and returns after instantiation;
@@ -405,6 +457,51 @@ int hog_filter_backward(const uint8_t* frames, int n, int h, int w, int pitch, i
  *   the zero subgradient), and dfilters += 2 l2 filters.  n <= 2^30. */
 int hog_hinge_loss(const float* scores, const float* labels, int n, const float* filters, int nf, float l2,
                    float* loss, float* dscore, float* dfilters, void* stream);
+
+/* Host pipeline (Sec. V-C, pipelining: while the GPU detects faces in one
+ * batch of frames, CPU threads process the detections of the previous
+ * batch; Sec. V-A, data transfers between host and device).  A pipeline
+ * owns `depth` stages, each a stream with its own device frame buffer,
+ * workspace and detection buffers, and page-locked host buffers.
+ * hog_pipeline_submit() takes a free stage (waiting for one if all are in
+ * flight), puts the host frames on the device, enqueues hog_detect_batch
+ * and the copy of the detections back to page-locked memory, and returns;
+ * consumer threads wait for each batch, call `consumer` with its
+ * detections and free the stage.  Frames are copied to the device either
+ * through the stage's page-locked staging buffer (staging = 1: a host copy,
+ * then an asynchronous transfer that overlaps the GPU work of other
+ * stages) or straight from the caller's memory (staging = 0; from pageable
+ * memory the runtime blocks the caller for the transfer).
+ *
+ * Unlike the calls above, a pipeline allocates its buffers (device and
+ * page-locked host memory) at creation and frees them in destroy.  The
+ * filters and bias (device) must outlive it; prm->regions must be NULL. */
+typedef void (*hog_consumer_fn)(void* user, int64_t first_frame, int n, const hog_det* dets /* host [n][cap] */,
+                                const int* n_dets /* host [n] */, int cap);
+typedef struct hog_pipeline_config {
+    int32_t h, w;              /* frame size (frames are packed: pitch w, stride h * w) */
+    int32_t batch;             /* frames per submit, 1..1024 */
+    int32_t depth;             /* stages, 1..16 */
+    int32_t cap;               /* detections kept per frame, 1..HOG_MAX_DETS */
+    int32_t consumer_threads;  /* 1..64 */
+    int32_t staging;           /* 1: through page-locked staging, 0: straight from the caller's memory */
+    int32_t reserved;
+    hog_consumer_fn consumer;  /* called on a consumer thread per batch; may be NULL.  The
+                                  pointers are valid during the call only; it must not call
+                                  hog_pipeline_* on the same pipeline. */
+    void* user;
+} hog_pipeline_config;
+typedef struct hog_pipeline hog_pipeline;
+int hog_pipeline_create(hog_pipeline** out, const hog_params* prm, const hog_pipeline_config* cfg,
+                        const float* filters, const float* bias, int nf);
+/* frames: host [n][h][w], 1 <= n <= batch; first_frame is passed to the
+ * consumer.  Returns once the work is enqueued (the frames have been read
+ * when it returns). */
+int hog_pipeline_submit(hog_pipeline* p, const uint8_t* frames, int n, int64_t first_frame);
+/* Waits until every submitted batch has been consumed; returns the first
+ * error of a batch since the last drain (HOG_OK if none). */
+int hog_pipeline_drain(hog_pipeline* p);
+int hog_pipeline_destroy(hog_pipeline* p);
 
 /* Kernel timing with HIP events, for benchmarks.  While enabled, each
  * launch of the library's kernels outside graph capture is bracketed by

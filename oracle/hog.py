@@ -84,6 +84,71 @@ def pyramid(h: int, w: int, upsample: int = 1) -> list[Level]:
         k += 1
 
 
+def pyramid_cascade(h: int, w: int, upsample: int = 1) -> list[Level]:
+    """Levels of the recursive pyramid (R20): level k is scaled down from
+    level k-1 by 5/6, so its size is floor(5 h_{k-1} / 6) x
+    floor(5 w_{k-1} / 6) (Sec. V-A, image-scaling kernel: each scaled
+    image is based on the image one scale higher; Sec. IV-A: down to the
+    80x80 window).  Level 0 is the frame, or the 2x enlargement for
+    upsample = 2.  The nominal scale of level k stays u (5/6)^k, which maps
+    its pixel edges back to the frame as for the direct pyramid."""
+    out = []
+    hk, wk = h * upsample, w * upsample
+    k = 0
+    while min(hk, wk) >= MIN_SIDE:
+        out.append(Level(k, upsample * SCALE_NUM ** k, SCALE_DEN ** k, hk, wk))
+        hk, wk = (hk * SCALE_NUM) // SCALE_DEN, (wk * SCALE_NUM) // SCALE_DEN
+        k += 1
+    return out
+
+
+def cascade_taps(n_out: int, n_in: int):
+    """Bilinear taps of one 5/6 step along an axis (R20): output sample i
+    of the smaller image sits at (i + 1/2) 6/5 - 1/2 = (12 i + 1) / 10 of
+    the larger one (pixel centres aligned); its integer part i0 and its
+    fractional part, rounded half-up to a multiple of 1/256, give taps i0,
+    i0 + 1 (clamped) with weights (256 - a)/256 and a/256."""
+    i = np.arange(n_out, dtype=np.int64)
+    num = 12 * i + 1
+    i0 = num // 10
+    a = (256 * (num % 10) + 5) // 10
+    return np.minimum(i0, n_in - 1), np.minimum(i0 + 1, n_in - 1), a
+
+
+def round_grey(v):
+    """Round half up to integer grey levels, as images of 8-bit pixels."""
+    return np.floor(np.asarray(v, np.float64) + 0.5)
+
+
+def cascade_levels(frame: np.ndarray, upsample: int = 1):
+    """Level images of the recursive pyramid (R20), as float64 arrays of
+    integer grey levels: level 0 is the frame (upsample 1) or its 2x
+    bilinear enlargement (R3) rounded to grey levels; level k is the
+    bilinear 5/6 reduction of level k-1 (cascade_taps) rounded to grey
+    levels, as an image of 8-bit pixels is (Sec. V-A: the scaling kernel
+    writes each scaled image, which the next step reads)."""
+    U = np.asarray(frame, np.float64)
+    H, W = U.shape
+    levels = pyramid_cascade(H, W, upsample)
+    out = []
+    prev = None
+    for lv in levels:
+        if lv.k == 0:
+            img = U.copy() if upsample == 1 else round_grey(resample(U, pyramid(H, W, upsample)[0]))
+        else:
+            y0, y1, ay = cascade_taps(lv.h, prev.shape[0])
+            x0, x1, ax = cascade_taps(lv.w, prev.shape[1])
+            wy0, wy1 = (256 - ay) / 256.0, ay / 256.0
+            wx0, wx1 = (256 - ax) / 256.0, ax / 256.0
+            img = round_grey((wy0[:, None] * wx0[None, :]) * prev[np.ix_(y0, x0)]
+                             + (wy0[:, None] * wx1[None, :]) * prev[np.ix_(y0, x1)]
+                             + (wy1[:, None] * wx0[None, :]) * prev[np.ix_(y1, x0)]
+                             + (wy1[:, None] * wx1[None, :]) * prev[np.ix_(y1, x1)])
+        out.append((lv, img))
+        prev = img
+    return out
+
+
 SIG_BITS = 40
 
 
@@ -341,21 +406,88 @@ def window_box(lv: Level, r, c):
     return edge(8 * c), edge(8 * r), edge(8 * c + 80), edge(8 * r + 80)
 
 
+# ------------------------------------ analysed levels and search regions
+def face_levels(levels, min_face: int):
+    """The levels analysed when every face spans at least ``min_face``
+    frame pixels (R17).  Sec. V-A ("image sequence with constant size")
+    skips the largest scale of 640x480 frames whose faces cover at least
+    20 % of the image: there the 80x80 window is smaller than the
+    smallest face (128x96), and one 5/6 step down that face is
+    window-sized (107x80), so no face can be missed.  Stated per level: a
+    level whose window spans fewer than min_face frame pixels,
+    80 q/p < min_face, only matches faces below the minimum and is
+    skipped; every later level is kept.  Exact integer test.  Sec. VI
+    (scalability) uses the same rule to keep the analysed work of larger
+    frames independent of their size.  min_face = 0 keeps every level."""
+    return [lv for lv in levels if WIN * CELL * lv.q >= min_face * lv.p]
+
+
+def window_in_region(lv: Level, r, c, region):
+    """True where window (r, c) of level lv is searched under ``region`` =
+    (x0, y0, x1, y1, k_lo, k_hi) (R18): its level lies in [k_lo, k_hi] and
+    its frame-pixel box (R12) lies inside the half-open rectangle
+    [x0, x1) x [y0, y1).  Sec. VII proposes restricting the scales and
+    locations analysed in a frame, as faces move little between
+    consecutive frames; None searches every window."""
+    r = np.asarray(r, np.int64)
+    c = np.asarray(c, np.int64)
+    if region is None:
+        return np.ones(np.broadcast(r, c).shape, bool)
+    x0, y0, x1, y1, k_lo, k_hi = (int(v) for v in region)
+    bx0, by0, bx1, by1 = window_box(lv, r, c)
+    return (k_lo <= lv.k) & (lv.k <= k_hi) & (bx0 >= x0) & (by0 >= y0) & (bx1 <= x1) & (by1 <= y1)
+
+
+def track_region(kept, h: int, w: int, margin: int, span: int):
+    """The search region of the next frame from the kept detections of
+    this one (R19; Sec. VII: faces move little between consecutive frames,
+    so both the locations and the scales searched can be limited): the box
+    of the best kept detection grown by ``margin`` pixels on every side and
+    clipped to the h x w frame, with the levels of that detection +- span
+    (clipped at level 0).  With no detection the whole frame at every
+    level.  ``kept`` is in rank order (:func:`detect`)."""
+    if len(kept) == 0:
+        return (0, 0, w, h, 0, HUGE_LEVEL)
+    d = kept[0]
+    return (max(int(d["x0"]) - margin, 0), max(int(d["y0"]) - margin, 0),
+            min(int(d["x1"]) + margin, w), min(int(d["y1"]) + margin, h),
+            max(int(d["k"]) - span, 0), int(d["k"]) + span)
+
+
+HUGE_LEVEL = 1 << 30   # level bound of a region that does not restrict levels
+
+
 CAND_DTYPE = np.dtype([("score", "f8"), ("f", "i4"), ("k", "i4"), ("r", "i4"), ("c", "i4"),
                        ("x0", "i8"), ("y0", "i8"), ("x1", "i8"), ("y1", "i8")])
 
 
-def candidates(frame, W, b, thresh: float = 0.0, upsample: int = 1, levels_out=None):
+def level_images(frame, upsample: int = 1, cascade: bool = False):
+    """(level, level image) pairs of the direct pyramid (R1, R2) or of the
+    recursive one (R20)."""
+    if cascade:
+        return cascade_levels(frame, upsample)
+    H, Wd = np.asarray(frame).shape
+    return [(lv, resample(frame, lv)) for lv in pyramid(H, Wd, upsample)]
+
+
+def candidates(frame, W, b, thresh: float = 0.0, upsample: int = 1, levels_out=None, min_face: int = 0,
+               region=None, cascade: bool = False):
     """All windows with score strictly above the threshold, over every
     filter and pyramid level (Sec. IV-A; Sec. V-A, detection kernel;
-    R10)."""
-    H, Wd = np.asarray(frame).shape
+    R10); only the levels of :func:`face_levels` and the windows of
+    :func:`window_in_region`."""
     rows = []
-    for lv in pyramid(H, Wd, upsample):
-        S = window_scores(level_features(frame, lv), W, b)
+    imgs = level_images(frame, upsample, cascade)
+    keep = set(lv.k for lv in face_levels([lv for lv, _ in imgs], min_face))
+    for lv, L in imgs:
+        if lv.k not in keep:
+            continue
+        S = window_scores(features_from_hist(cell_histograms(L)), W, b)
         if levels_out is not None:
             levels_out.append((lv, S))
         f, r, c = np.nonzero(S > thresh)
+        inside = window_in_region(lv, r, c, region)
+        f, r, c = f[inside], r[inside], c[inside]
         if len(f) == 0:
             continue
         x0, y0, x1, y1 = window_box(lv, r, c)
@@ -400,9 +532,10 @@ def nms(c: np.ndarray, iou: float = 0.5) -> np.ndarray:
     return c[keep]
 
 
-def detect(frame, W, b, thresh: float = 0.0, iou: float = 0.5, upsample: int = 1):
+def detect(frame, W, b, thresh: float = 0.0, iou: float = 0.5, upsample: int = 1, min_face: int = 0,
+           region=None, cascade: bool = False):
     """Frame in, kept face boxes and scores out, in rank order."""
-    return nms(candidates(frame, W, b, thresh, upsample), iou)
+    return nms(candidates(frame, W, b, thresh, upsample, min_face=min_face, region=region, cascade=cascade), iou)
 
 
 # ------------------------------------------------- training (dW, db)

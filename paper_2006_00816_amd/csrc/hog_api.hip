@@ -16,26 +16,46 @@ using namespace hog;
 
 namespace {
 
+// One image of the recursive pyramid: level k of the full pyramid (also
+// when the level is not analysed, since later levels are computed from
+// it), at byte offset `off` of a frame's block; off < 0: the frame itself.
+struct ChainLevel {
+    int h = 0, w = 0, off = -1;
+    long long sig = 0;
+};
+
 struct Plan {
     LevelTable T;
     int n = 0, nf = 0, groups = 0;
+    bool cascade = false;            // recursive pyramid (HOG_PYRAMID_CASCADE)
+    int chain_n = 0;
+    ChainLevel chain[MAX_LEVELS];
     // workspace offsets (bytes)
     size_t o_taps = 0, o_boxes = 0, o_bpack = 0, o_hist = 0, o_feat = 0, o_key = 0, o_state = 0, o_list = 0,
-           o_work = 0, o_state8 = 0, o_sync = 0, o_dense = 0, o_partial = 0, total = 0;
+           o_work = 0, o_state8 = 0, o_sync = 0, o_casc = 0, o_dense = 0, o_partial = 0, total = 0;
     long long packed_floats = 0, dense_floats = 0;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+constexpr int MAX_MIN_FACE = 1 << 16;
+
 typedef __int128 i128;
 
 // Levels of an h x w frame: scale s_k = u 5^k / 6^k, size floor(h s_k) x
 // floor(w s_k), kept while both sides are >= 80 px (Sec. IV-A).
-int pyramid_levels(int h, int w, int u, int* hk, int* wk, long long* sig, int maxl) {
+// With `cascade` the sizes are those of the recursive pyramid instead:
+// u h x u w, then floor(5 x / 6) of the previous level (Sec. V-A,
+// image-scaling kernel); the scales s_k, and so the inverse scales, are
+// the same.
+int pyramid_levels(int h, int w, int u, int* hk, int* wk, long long* sig, int maxl, bool cascade = false) {
     int n = 0;
     i128 p = u, q = 1;
+    long long ch = (long long)u * h, cw = (long long)u * w;
     for (int k = 0; k < 64; ++k) {
-        const i128 hh = (i128)h * p / q, ww = (i128)w * p / q;
+        const i128 hh = cascade ? (i128)ch : (i128)h * p / q, ww = cascade ? (i128)cw : (i128)w * p / q;
+        ch = ch * SCALE_NUM / SCALE_DEN;
+        cw = cw * SCALE_NUM / SCALE_DEN;
         if (hh < MIN_SIDE || ww < MIN_SIDE) break;
         if (n >= maxl) return -1;
         hk[n] = (int)hh;
@@ -50,7 +70,8 @@ int pyramid_levels(int h, int w, int u, int* hk, int* wk, long long* sig, int ma
 }
 
 int check_frame(int h, int w, int upsample) {
-    if (h <= 0 || w <= 0 || (upsample != 1 && upsample != 2)) return HOG_E_INVAL;
+    const int u = upsample & ~HOG_PYRAMID_CASCADE;
+    if (h <= 0 || w <= 0 || (u != 1 && u != 2)) return HOG_E_INVAL;
     if (h > MAX_SIDE || w > MAX_SIDE) return HOG_E_TOO_LARGE;
     return HOG_OK;
 }
@@ -66,26 +87,68 @@ void box_bounds(long long sig, int* lo, int* hi) {
 
 // n_windows > 0 adds the regions of the gradient calls: dense scores of
 // every frame and the per-workgroup partial filter gradients.
-int make_plan(int h, int w, int u, int n, int nf, Plan* P, int n_windows = 0) {
-    int st = check_frame(h, w, u);
+// min_face > 0 leaves out the leading levels whose 80-px window spans
+// fewer than min_face frame px (80 q_k < min_face p_k, exact): the table
+// then starts at pyramid level k_base.
+int make_plan(int h, int w, int upsample, int n, int nf, Plan* P, int n_windows = 0, int min_face = 0) {
+    int st = check_frame(h, w, upsample);
     if (st) return st;
-    if (n < 1 || nf < 0) return HOG_E_INVAL;
+    if (n < 1 || nf < 0 || min_face < 0 || min_face > MAX_MIN_FACE) return HOG_E_INVAL;
     if (nf > MAX_FILTERS) return HOG_E_TOO_LARGE;
+    const bool cascade = (upsample & HOG_PYRAMID_CASCADE) != 0;
+    const int u = upsample & ~HOG_PYRAMID_CASCADE;
     int hk[MAX_LEVELS], wk[MAX_LEVELS];
     long long sig[MAX_LEVELS];
-    const int nl = pyramid_levels(h, w, u, hk, wk, sig, MAX_LEVELS);
+    int nl = pyramid_levels(h, w, u, hk, wk, sig, MAX_LEVELS, cascade);
     if (nl < 0) return HOG_E_TOO_LARGE;
+    // images of the recursive pyramid, one per level of the full pyramid
+    // (level 0 at upsample 1 is the frame itself)
+    P->cascade = cascade;
+    P->chain_n = cascade ? nl : 0;
+    long long casc_bytes = 0;
+    for (int k = 0; k < P->chain_n; ++k) {
+        ChainLevel& c = P->chain[k];
+        c.h = hk[k];
+        c.w = wk[k];
+        c.sig = sig[k];
+        c.off = -1;
+        if (k > 0 || u != 1) {
+            c.off = (int)casc_bytes;
+            casc_bytes += ((long long)hk[k] * wk[k] + 255) & ~255LL;
+        }
+    }
+    if (casc_bytes > 0x7fffffffLL) return HOG_E_TOO_LARGE;
+    int k_base = 0;
+    {
+        i128 p = u, q = 1;
+        while (k_base < nl && (i128)MIN_SIDE * q < (i128)min_face * p) {
+            ++k_base;
+            p *= 5;
+            q *= 6;
+        }
+    }
+    nl -= k_base;
+    for (int i = 0; i < nl; ++i) {
+        hk[i] = hk[i + k_base];
+        wk[i] = wk[i + k_base];
+        sig[i] = sig[i + k_base];
+    }
     LevelTable& T = P->T;
     memset(&T, 0, sizeof(T));
     T.n = nl;
+    T.k_base = k_base;
     T.h = h;
     T.w = w;
-    T.upsample = u;
+    T.upsample = upsample;
+    T.casc_frame = casc_bytes;
     int taps = 0, boxes = 0, th = 0, tf = 0, ts = 0;
     long long hist = 0, feat = 0, pos = 0, pk = 0, sc = 0;
     for (int k = 0; k < nl; ++k) {
         DevLevel& L = T.L[k];
-        L.k = k;
+        L.k = k + k_base;
+        L.src = cascade && P->chain[k + k_base].off >= 0 ? 1 : 0;
+        L.src_off = L.src ? P->chain[k + k_base].off : 0;
+        L.ident = L.src || sig[k] == (1LL << SIG_BITS);
         L.h = hk[k];
         L.w = wk[k];
         L.cy = hk[k] / CELL;
@@ -176,6 +239,8 @@ int make_plan(int h, int w, int u, int n, int nf, Plan* P, int n_windows = 0) {
     o = align256(o + (size_t)n * std::max(pos, 1LL));
     P->o_sync = o;
     o = align256(o + sizeof(unsigned) * (size_t)fused_sync_words(n));
+    P->o_casc = o;
+    o = align256(o + (size_t)n * casc_bytes);
     T.dense_frame = (int)sc;
     P->o_dense = o;
     P->o_partial = o;
@@ -239,6 +304,26 @@ int check_ws(const Plan& P, void* ws, size_t ws_bytes) {
     return HOG_OK;
 }
 
+// The level images of the recursive pyramid for m frames (casc: the block
+// of the first), level by level, each from the one before.  Nothing for
+// the direct pyramid.
+int run_cascade(const Plan& P, int m, const uint8_t* frames, long long fstride, int pitch, uint8_t* casc,
+                hipStream_t s) {
+    for (int k = 0; k < P.chain_n; ++k) {
+        const ChainLevel& c = P.chain[k];
+        if (c.off < 0) continue;   // level 0 at upsample 1: the frame itself
+        HOG_TRY(timed("cascade", s, [&] {
+            if (k == 0)
+                return launch_cascade(frames, fstride, pitch, m, casc, P.T.casc_frame, c.h, c.w, c.off, P.T.h, P.T.w,
+                                      -1, c.sig, s);
+            const ChainLevel& q = P.chain[k - 1];
+            return launch_cascade(frames, fstride, pitch, m, casc, P.T.casc_frame, c.h, c.w, c.off, q.h, q.w, q.off,
+                                  0, s);
+        }));
+    }
+    return HOG_OK;
+}
+
 int run_pixels(const Plan& P, const uint8_t* frames, long long fstride, int pitch, void* ws, float* packed,
                const float* filters, hipStream_t s, bool zero_keys) {
     const LevelTable& T = P.T;
@@ -247,8 +332,10 @@ int run_pixels(const Plan& P, const uint8_t* frames, long long fstride, int pitc
                             at<float4>(ws, P.o_bpack), zero_keys ? at<unsigned long long>(ws, P.o_key) : nullptr,
                             (long long)P.n * T.pos_frame, nullptr, 0, s);
     }));
+    HOG_TRY(run_cascade(P, P.n, frames, fstride, pitch, at<uint8_t>(ws, P.o_casc), s));
     HOG_TRY(timed("hist", s, [&] {
-        return launch_hist(T, frames, fstride, pitch, P.n, at<int4>(ws, P.o_taps), at<float>(ws, P.o_hist), s);
+        return launch_hist(T, frames, fstride, pitch, P.n, at<int4>(ws, P.o_taps), at<float>(ws, P.o_hist),
+                           nullptr, at<uint8_t>(ws, P.o_casc), s);
     }));
     HOG_TRY(timed("feat", s, [&] {
         return launch_feat(T, P.n, at<float>(ws, P.o_hist), at<float>(ws, P.o_feat), packed, s);
@@ -316,10 +403,12 @@ struct FrameBufs {
     unsigned char* state8;
     hog_det* dets;
     int* n_dets;
+    const hog_region* regions;   // search regions of the group's frames, or nullptr
+    uint8_t* casc;               // the group's level images of the recursive pyramid
 };
 
 FrameBufs frame_bufs(const Plan& P, void* ws, const uint8_t* frames, long long fstride, hog_det* dets, int cap,
-                     int* n_dets, int lo) {
+                     int* n_dets, int lo, const hog_region* regions = nullptr) {
     const LevelTable& T = P.T;
     const long long pos = T.pos_frame;
     FrameBufs b;
@@ -334,6 +423,8 @@ FrameBufs frame_bufs(const Plan& P, void* ws, const uint8_t* frames, long long f
     b.state8 = at<unsigned char>(ws, P.o_state8) + lo * pos;
     b.dets = dets + (long long)lo * cap;
     b.n_dets = n_dets + lo;
+    b.regions = regions ? regions + lo : nullptr;
+    b.casc = at<uint8_t>(ws, P.o_casc) + (long long)lo * T.casc_frame;
     return b;
 }
 
@@ -403,20 +494,21 @@ struct Bank {
 
 // Window scores of m frames into dense maps and / or keys.
 int score_stage(const Plan& P, int m, const float* feat, const Bank& bank, float thresh, float* dense,
-                unsigned long long* keys, int score_rows, void* ws, hipStream_t s) {
+                unsigned long long* keys, int score_rows, void* ws, hipStream_t s,
+                const hog_region* regions = nullptr) {
     const LevelTable& T = P.T;
     const bool multi = P.groups > 1;
     return timed("score", s, [&] {
         if (bank.rank == 0) {
             const int rows = score_rows ? score_rows : score_rows_auto(T, m, P.nf, compute_units());
             return launch_score(T, m, feat, at<float4>(ws, P.o_bpack), bank.bias, P.nf, thresh, dense, keys,
-                                keys && multi, rows, s);
+                                keys && multi, rows, regions, s);
         }
         const int rows = score_rows == SCORE_SMALL_ROWS ? SCORE_SMALL_ROWS
                          : score_rows ? SEP_ROWS
                                       : sep_rows_auto(T, m, P.nf, compute_units());
         return launch_score_sep(T, m, feat, bank.row, bank.col, bank.rank, bank.bias, P.nf, thresh, dense, keys,
-                                keys && multi, rows, s);
+                                keys && multi, rows, regions, s);
     });
 }
 
@@ -424,23 +516,26 @@ int score_stage(const Plan& P, int m, const float* feat, const Bank& bank, float
 int staged_chain(const Plan& P, int m, const FrameBufs& b, long long fstride, int pitch, const hog_params* prm,
                  const Bank& bank, int cap, int rounds, int score_rows, void* ws, hipStream_t s) {
     const LevelTable& T = P.T;
+    HOG_TRY(run_cascade(P, m, b.frames, fstride, pitch, b.casc, s));
     HOG_TRY(timed("hist", s, [&] {
-        return launch_hist(T, b.frames, fstride, pitch, m, at<int4>(ws, P.o_taps), b.hist, s);
+        return launch_hist(T, b.frames, fstride, pitch, m, at<int4>(ws, P.o_taps), b.hist, b.regions, b.casc, s);
     }));
     HOG_TRY(timed("feat", s, [&] { return launch_feat(T, m, b.hist, b.feat, nullptr, s); }));
-    HOG_TRY(score_stage(P, m, b.feat, bank, prm->thresh, nullptr, b.keys, score_rows, ws, s));
+    HOG_TRY(score_stage(P, m, b.feat, bank, prm->thresh, nullptr, b.keys, score_rows, ws, s, b.regions));
     return nms_chain(P, m, b, prm, cap, nullptr, rounds, ws, s);
 }
 
 int detect_sequence(const Plan& P, const hog_params* prm, const uint8_t* frames, long long fstride, int pitch,
                     const Bank& bank, hog_det* dets, int cap, int* n_dets, void* ws, const hog_tuning& tune_in,
                     hipStream_t s) {
-    // separable filters run the per-stage schedule
+    // separable filters, search regions and the recursive pyramid run the
+    // per-stage schedule
     hog_tuning tune = tune_in;
-    if (bank.rank != 0 && tune.fused) {
+    if ((bank.rank != 0 || prm->regions || P.cascade) && tune.fused) {
         tune.fused = 0;
         tune.split = 1;
     }
+    const hog_region* regions = prm->regions;
     const float* filters = bank.W;
     const float* bias = bank.bias;
     const LevelTable& T = P.T;
@@ -472,8 +567,8 @@ int detect_sequence(const Plan& P, const hog_params* prm, const uint8_t* frames,
     }
     const int parts = std::min(std::max(tune.split, 1), P.n);
     if (parts == 1)
-        return staged_chain(P, P.n, frame_bufs(P, ws, frames, fstride, dets, cap, n_dets, 0), fstride, pitch, prm,
-                            bank, cap, tune.nms_rounds, tune.score_rows, ws, s);
+        return staged_chain(P, P.n, frame_bufs(P, ws, frames, fstride, dets, cap, n_dets, 0, regions), fstride,
+                            pitch, prm, bank, cap, tune.nms_rounds, tune.score_rows, ws, s);
     // the frames in `parts` groups on forked streams: one group's NMS
     // overlaps another's histograms and scores.  Without the calling
     // thread's helper streams (hog_init) the groups run one after another
@@ -482,8 +577,8 @@ int detect_sequence(const Plan& P, const hog_params* prm, const uint8_t* frames,
     if (!r) {
         for (int j = 0; j < parts; ++j) {
             const int lo = (int)((long long)j * P.n / parts), hi = (int)((long long)(j + 1) * P.n / parts);
-            HOG_TRY(staged_chain(P, hi - lo, frame_bufs(P, ws, frames, fstride, dets, cap, n_dets, lo), fstride,
-                                 pitch, prm, bank, cap, tune.nms_rounds, tune.score_rows, ws, s));
+            HOG_TRY(staged_chain(P, hi - lo, frame_bufs(P, ws, frames, fstride, dets, cap, n_dets, lo, regions),
+                                 fstride, pitch, prm, bank, cap, tune.nms_rounds, tune.score_rows, ws, s));
         }
         return HOG_OK;
     }
@@ -493,8 +588,8 @@ int detect_sequence(const Plan& P, const hog_params* prm, const uint8_t* frames,
     int st = HOG_OK;
     for (int j = 0; j < parts && st == HOG_OK; ++j) {
         const int lo = (int)((long long)j * P.n / parts), hi = (int)((long long)(j + 1) * P.n / parts);
-        st = staged_chain(P, hi - lo, frame_bufs(P, ws, frames, fstride, dets, cap, n_dets, lo), fstride, pitch,
-                          prm, bank, cap, tune.nms_rounds, tune.score_rows, ws, j == 0 ? s : r->st[j - 1]);
+        st = staged_chain(P, hi - lo, frame_bufs(P, ws, frames, fstride, dets, cap, n_dets, lo, regions), fstride,
+                          pitch, prm, bank, cap, tune.nms_rounds, tune.score_rows, ws, j == 0 ? s : r->st[j - 1]);
     }
     // join (also after an error, so that no forked stream is left behind a capture)
     for (int j = 1; j < parts; ++j) {
@@ -570,6 +665,7 @@ int check_detect_args(const hog_params* prm, const void* frames, int pitch, int 
     if (cap < 1 || cap > MAX_DETS) return HOG_E_CAP;
     if (!(prm->iou >= 0.5f && prm->iou < 1.f)) return HOG_E_INVAL;
     if (prm->thresh != prm->thresh) return HOG_E_INVAL;
+    if (prm->min_face < 0 || prm->min_face > MAX_MIN_FACE) return HOG_E_INVAL;
     return HOG_OK;
 }
 
@@ -698,7 +794,7 @@ int hog_detect_batch_bank(const hog_params* prm, const uint8_t* frames, int n, i
                               n_dets));
     if (n < 1 || (n > 1 && frame_stride < (int64_t)pitch * h)) return HOG_E_INVAL;
     Plan P;
-    HOG_TRY(make_plan(h, w, prm->upsample, n, fb->nf, &P));
+    HOG_TRY(make_plan(h, w, prm->upsample, n, fb->nf, &P, 0, prm->min_face));
     HOG_TRY(check_ws(P, ws, ws_bytes));
     const hog_tuning tune = lookup_tuning(h, w, prm->upsample, n, fb->nf);
     return detect_sequence(P, prm, frames, frame_stride, pitch, bank_of(fb), dets, cap, n_dets, ws, tune,
@@ -720,7 +816,7 @@ int hog_detect_batch_static(const hog_params* prm, const uint8_t* frames, int n,
     HOG_TRY(check_detect_args(prm, frames, pitch, w, filters, bias, nf, dets, cap, n_dets));
     if (n < 1 || (n > 1 && frame_stride < (int64_t)pitch * h)) return HOG_E_INVAL;
     Plan P;
-    HOG_TRY(make_plan(h, w, prm->upsample, n, nf, &P));
+    HOG_TRY(make_plan(h, w, prm->upsample, n, nf, &P, 0, prm->min_face));
     if (P.total > (size_t)HOG_STATIC_SCRATCH_BYTES) return HOG_E_SCRATCH;
     void* ws = nullptr;
     HOG_TRY(static_scratch(&ws));
@@ -747,7 +843,7 @@ int hog_graph_create_bank(hog_graph** out, const hog_params* prm, const uint8_t*
                               n_dets));
     if (n < 1 || (n > 1 && frame_stride < (int64_t)pitch * h)) return HOG_E_INVAL;
     Plan P;
-    HOG_TRY(make_plan(h, w, prm->upsample, n, fb->nf, &P));
+    HOG_TRY(make_plan(h, w, prm->upsample, n, fb->nf, &P, 0, prm->min_face));
     HOG_TRY(check_ws(P, ws, ws_bytes));
     hipStream_t cs = (hipStream_t)stream;
     bool own = false;
@@ -809,6 +905,16 @@ int hog_tuning_get(int h, int w, int upsample, int n, int nf, hog_tuning* out) {
     return found ? 1 : 0;
 }
 
+int hog_track_regions(const hog_det* dets, const int* n_dets, int n, int cap, int h, int w, int margin, int span,
+                      hog_region* regions, void* stream) {
+    if (!dets || !n_dets || !regions || n < 1 || cap < 1 || cap > MAX_DETS) return HOG_E_INVAL;
+    if (h < 1 || w < 1 || h > MAX_SIDE || w > MAX_SIDE) return HOG_E_INVAL;
+    if (margin < 0 || margin > MAX_MIN_FACE || span < 0 || span > MAX_LEVELS) return HOG_E_INVAL;
+    return timed("track", (hipStream_t)stream, [&] {
+        return launch_track(dets, n_dets, n, cap, h, w, margin, span, regions, (hipStream_t)stream);
+    });
+}
+
 int hog_init(void) {
     HOG_TRY(init_split_resources());
     void* p = nullptr;
@@ -834,7 +940,7 @@ int hog_autotune(const hog_params* prm, const uint8_t* frames, int n, int h, int
     if (!best || !best_ms || reps < 1 || reps > 1000) return HOG_E_INVAL;
     if (n < 1 || (n > 1 && frame_stride < (int64_t)pitch * h)) return HOG_E_INVAL;
     Plan P;
-    HOG_TRY(make_plan(h, w, prm->upsample, n, nf, &P));
+    HOG_TRY(make_plan(h, w, prm->upsample, n, nf, &P, 0, prm->min_face));
     HOG_TRY(check_ws(P, ws, ws_bytes));
     const int cus = compute_units();
     if (cus < 1) return HOG_E_HIP;
@@ -924,14 +1030,17 @@ int hog_level_maps(const uint8_t* frame, int h, int w, int pitch, int upsample, 
     HOG_TRY(timed("geom", s, [&] {
         return launch_setup(T, at<int4>(ws, P.o_taps), at<int2>(ws, P.o_boxes), nullptr, 0, nullptr, nullptr, 0, nullptr, 0, s);
     }));
+    uint8_t* casc = at<uint8_t>(ws, P.o_casc);
+    HOG_TRY(run_cascade(P, 1, frame, 0, pitch, casc, s));
     if (level_px || bins) {
         HOG_TRY(timed("maps", s, [&] {
-            return launch_level_maps(T, level, frame, pitch, at<int4>(ws, P.o_taps), level_px, bins, s);
+            return launch_level_maps(T, level, frame, pitch, at<int4>(ws, P.o_taps), level_px, bins, casc, s);
         }));
     }
     if (hist) {
         HOG_TRY(timed("hist", s, [&] {
-            return launch_hist(T, frame, 0, pitch, 1, at<int4>(ws, P.o_taps), at<float>(ws, P.o_hist), s);
+            return launch_hist(T, frame, 0, pitch, 1, at<int4>(ws, P.o_taps), at<float>(ws, P.o_hist), nullptr, casc,
+                               s);
         }));
         const DevLevel& L = T.L[level];
         const float* src = at<float>(ws, P.o_hist) + (size_t)L.hist_off * HSTRIDE;
@@ -982,7 +1091,8 @@ int hog_topk_windows(const uint8_t* frames, int n, int h, int w, int pitch, int6
     HOG_TRY(run_pixels(P, frames, frame_stride, pitch, ws, nullptr, filters, s, false));
     HOG_TRY(timed("score", s, [&] {
         return launch_score(P.T, n, at<float>(ws, P.o_feat), at<float4>(ws, P.o_bpack), bias, nf, 0.f,
-                            at<float>(ws, P.o_dense), nullptr, false, score_rows_auto(P.T, n, nf, compute_units()), s);
+                            at<float>(ws, P.o_dense), nullptr, false, score_rows_auto(P.T, n, nf, compute_units()),
+                            nullptr, s);
     }));
     return timed("topk", s, [&] {
         return launch_topk(P.T, n, at<float>(ws, P.o_dense), P.T.dense_frame, nf, k, windows, scores, s);
@@ -995,6 +1105,9 @@ int hog_filter_backward(const uint8_t* frames, int n, int h, int w, int pitch, i
     if (!frames || !filters || !windows || !dscore || !dfilters || pitch < w || pitch > MAX_PITCH) return HOG_E_INVAL;
     if (n < 1 || nf < 1 || n_windows < 0 || (n > 1 && frame_stride < (int64_t)pitch * h)) return HOG_E_INVAL;
     if (nf > MAX_FILTERS) return HOG_E_TOO_LARGE;
+    // the recursive pyramid rounds every level to grey levels: no pixel
+    // gradient; the backward recomputes levels from the frame directly
+    if (upsample & HOG_PYRAMID_CASCADE) return HOG_E_NOTIMPL;
     Plan P;
     HOG_TRY(make_plan(h, w, upsample, n, nf, &P, std::max(n_windows, 1)));
     HOG_TRY(check_ws(P, ws, ws_bytes));

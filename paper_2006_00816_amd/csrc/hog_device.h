@@ -112,14 +112,6 @@ static __device__ inline unsigned vote_magnitude(int gxi, int gyi) {
     return (unsigned)(mag * 64.0f + 0.5f);
 }
 
-// The same integer magnitude as a float64 (exact): floor(|g| 2^6 + 1/2)
-// of the float32 value, which is already an integer from 2^23 on.
-static __device__ inline double vote_magnitude_f64(int gxi, int gyi) {
-    const float fx = (float)gxi, fy = (float)gyi;
-    const float mag = __builtin_amdgcn_sqrtf(fmaf(fx, fx, fy * fy));
-    return (double)floorf(fmaf(mag, 64.0f, 0.5f));
-}
-
 // Fixed-point resampling tap: returns {i0, i1, a8, 0} for output index i
 // of an axis with n_in source samples at inverse scale sig (40 fractional
 // bits): source coordinate ((2i+1) sig - 2^40) / 2^41, weight a8/256 on
@@ -143,8 +135,56 @@ __device__ __forceinline__ void wave_lds_order() {
 }
 
 // Frame-pixel edge of level-pixel coordinate v: round(v * sig / 2^40).
-static __device__ inline int box_edge(long long v, long long sig) {
+static __host__ __device__ inline int box_edge(long long v, long long sig) {
     return (int)((v * sig + (1LL << (SIG_BITS - 1))) >> SIG_BITS);
+}
+
+// Search region of a frame (hog_region): the windows of table level L
+// (pyramid level k_true) whose frame-pixel boxes lie inside the region's
+// rectangle, as anchor ranges [r_lo, r_hi] x [c_lo, c_hi] (empty when
+// r_lo > r_hi or c_lo > c_hi, or when k_true is outside [k_lo, k_hi]).
+// Box edges grow with the anchor, so the windows inside form exactly this
+// product of ranges.  The first guesses invert the edge map up to a unit;
+// the loops then settle the exact bounds.
+struct RegionRange {
+    int r_lo, r_hi, c_lo, c_hi;
+    __host__ __device__ bool empty() const { return r_lo > r_hi || c_lo > c_hi; }
+};
+
+// Region coordinates are clamped to [0, 2^20] (beyond any frame side), so
+// the shifted values below stay inside 64 bits.
+static __host__ __device__ inline int region_lo(int lo_px, long long sig, int n) {
+    // smallest a in [0, n] with box_edge(8a) >= lo_px (n: none)
+    lo_px = min(max(lo_px, 0), 1 << 20);
+    const long long g = ((((long long)lo_px << SIG_BITS) / sig) >> 3) - 1;
+    int a = (int)min(max(g, 0LL), (long long)n);
+    while (a < n && box_edge(8LL * a, sig) < lo_px) ++a;
+    while (a > 0 && box_edge(8LL * (a - 1), sig) >= lo_px) --a;
+    return a;
+}
+
+static __host__ __device__ inline int region_hi(int hi_px, long long sig, int n) {
+    // largest a in [-1, n - 1] with box_edge(8a + 80) <= hi_px (-1: none)
+    hi_px = min(max(hi_px, 0), 1 << 20);
+    const long long g = ((((long long)hi_px << SIG_BITS) / sig) - 80) >> 3;
+    int a = (int)min(max(g + 1, -1LL), (long long)(n - 1));
+    while (a >= 0 && box_edge(8LL * a + 80, sig) > hi_px) --a;
+    while (a + 1 < n && box_edge(8LL * (a + 1) + 80, sig) <= hi_px) ++a;
+    return a;
+}
+
+static __host__ __device__ inline RegionRange region_range(const DevLevel& L, int k_true, const hog_region& g) {
+    RegionRange R;
+    if (k_true < g.k_lo || k_true > g.k_hi || L.rows <= 0 || L.cols <= 0) {
+        R.r_lo = R.c_lo = 1;
+        R.r_hi = R.c_hi = 0;
+        return R;
+    }
+    R.r_lo = region_lo(g.y0, L.sig, L.rows);
+    R.r_hi = region_hi(g.y1, L.sig, L.rows);
+    R.c_lo = region_lo(g.x0, L.sig, L.cols);
+    R.c_hi = region_hi(g.x1, L.sig, L.cols);
+    return R;
 }
 
 }  // namespace hog

@@ -16,6 +16,7 @@ constexpr int NFEAT = 31;      // features per cell
 constexpr int FPAD = 32;       // features per cell in the internal layout (31 + zero)
 constexpr int HSTRIDE = 20;    // internal histogram record: 18 bins, energy, zero
 constexpr int MIN_SIDE = 80;
+constexpr int SCALE_NUM = 5, SCALE_DEN = 6;   // pyramid step 5/6
 constexpr int SIG_BITS = 40;   // fractional bits of the fixed-point inverse scale
 constexpr int MAX_LEVELS = 28;
 constexpr int MAX_SIDE = 4096;
@@ -75,7 +76,9 @@ constexpr int NMS_LIST = 128;       // neighbour-list record per window position
 
 struct DevLevel {
     int h, w, cy, cx;
-    int rows, cols, k, pad0;
+    int rows, cols, k;
+    int src;                      // 0: sampled from the frame through the taps; 1: an 8-bit level image
+                                  // of the recursive pyramid at src_off (pitch w, identity taps)
     long long sig;                // inverse scale, 40 fractional bits
     int tap_y, tap_x;             // offsets (int4 units) of the row / column taps
     int box_r, box_c;             // offsets (int2 units) of the row / column box edges
@@ -88,6 +91,8 @@ struct DevLevel {
     int row_off;                  // first window row of this level in the frame's list of window rows
     int nms_klo, nms_khi;         // levels whose boxes can overlap this level's boxes with IoU > 1/2
     int wmin, wmax, hmin, hmax;   // bounds of this level's box widths / heights (frame px)
+    int src_off;                  // byte offset of the level image in a frame's block (src = 1)
+    int ident;                    // the taps are the identity (a copy of the source, zero weights)
 };
 
 struct LevelTable {
@@ -101,6 +106,8 @@ struct LevelTable {
     int taps_total, boxes_total;  // geometry table entries
     int h, w, upsample;
     int dense_frame;              // floats of dense scores per frame: sum over levels of nf * rows * cols
+    int k_base;                   // pyramid level of table entry 0 (levels below it are not analysed)
+    long long casc_frame;         // bytes of 8-bit level images per frame (recursive pyramid), else 0
     DevLevel L[MAX_LEVELS];
 };
 
@@ -143,7 +150,16 @@ hipError_t launch_setup(const LevelTable& T, int4* taps, int2* boxes,
                         unsigned long long* poskey_zero, long long poskey_count, unsigned* sync_zero,
                         int sync_count, hipStream_t s);
 hipError_t launch_hist(const LevelTable& T, const uint8_t* frames, long long fstride, int pitch,
-                       int n, const int4* taps, float* hist, hipStream_t s);
+                       int n, const int4* taps, float* hist, const hog_region* regions, const uint8_t* casc,
+                       hipStream_t s);
+// One level of the recursive pyramid for n frames: the 8-bit image
+// [h_out][w_out] at dst_off of each frame's block of `casc`, scaled down by
+// 5/6 from the level image [h_in][w_in] at src_off (src_off < 0: the frame
+// itself), or (sig > 0) the level sampled from the frame at inverse scale
+// sig (the 2x level 0), rounded to grey levels.
+hipError_t launch_cascade(const uint8_t* frames, long long fstride, int pitch, int n, uint8_t* casc,
+                          long long casc_frame, int h_out, int w_out, int dst_off, int h_in, int w_in, int src_off,
+                          long long sig, hipStream_t s);
 hipError_t launch_feat(const LevelTable& T, int n, const float* hist, float* feat,
                        float* packed, hipStream_t s);
 int fused_sync_words(int n);
@@ -159,12 +175,19 @@ int score_rows_auto(const LevelTable& T, int n, int nf, int cus);
 int sep_rows_auto(const LevelTable& T, int n, int nf, int cus);
 hipError_t launch_score(const LevelTable& T, int n, const float* feat, const float4* bpack,
                         const float* bias, int nf, float thresh, float* dense,
-                        unsigned long long* poskey, bool atomic_key, int rows, hipStream_t s);
+                        unsigned long long* poskey, bool atomic_key, int rows, const hog_region* regions,
+                        hipStream_t s);
 constexpr int SEP_MAX_RANK = 4;   // row / column filter pairs per channel of a separable filter
 constexpr int SEP_ROWS = 8;       // window rows per separable scoring item (256 VGPRs per lane at 512 threads)
 hipError_t launch_score_sep(const LevelTable& T, int n, const float* feat, const float* row, const float* col,
                             int rank, const float* bias, int nf, float thresh, float* dense,
-                            unsigned long long* poskey, bool atomic_key, int rows, hipStream_t s);
+                            unsigned long long* poskey, bool atomic_key, int rows, const hog_region* regions,
+                            hipStream_t s);
+// Search regions of the next frames from the detections of these (one per
+// frame): the best detection's box grown by margin px and its levels
+// +- span, or the whole frame where a frame has no detection.
+hipError_t launch_track(const hog_det* dets, const int* n_dets, int n, int cap, int h, int w, int margin, int span,
+                        hog_region* regions, hipStream_t s);
 // NMS records hold 32-bit position indices when a frame has 65536 window
 // positions or more, else 16-bit ones.
 inline bool nms_wide_lists(long long positions) { return positions > 65535; }
@@ -176,7 +199,7 @@ hipError_t launch_nms(const LevelTable& T, int n, const unsigned long long* posk
                       unsigned* gstate, int* work, const unsigned char* state8, const unsigned* upstream,
                       FusedNeed need, int frame_base, hipStream_t s);
 hipError_t launch_level_maps(const LevelTable& T, int level, const uint8_t* frame, int pitch,
-                             const int4* taps, float* level_px, uint8_t* bins, hipStream_t s);
+                             const int4* taps, float* level_px, uint8_t* bins, const uint8_t* casc, hipStream_t s);
 hipError_t launch_orient(const int32_t* gx, const int32_t* gy, long long n, uint8_t* bins,
                          hipStream_t s);
 hipError_t launch_fill(int* p, int n, int v, hipStream_t s);

@@ -473,6 +473,12 @@ constexpr int RESOLVE_BATCH = 2;   // worklist items per thread whose records ar
 // cached-candidate indices (the first also the rank order), then the
 // cached candidates' keys.
 constexpr int RC_MAXI = 2048;
+// Cached candidates decided in rank order by one wave.  Up to this many
+// the single-wave pass is the shorter chain; above it (many undecided
+// after few parallel rounds) its 64-lane blocks run one after another and
+// parallel passes over the cache are faster (one 64-frame clip after 3
+// rounds: 221 us with 2048 here, 108 us with 256).
+constexpr int RANK_DECIDE_MAX = 256;
 constexpr int RC_CHUNKS = 1536;
 constexpr int RC_BYTES = RC_CHUNKS * 64 + RC_MAXI * (4 + 2 + 2 + 2 + 8);
 static_assert(RC_CHUNKS * 64 >= SORT_CAP * 8, "sort buffer aliases the chunk cache");
@@ -580,14 +586,16 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
                 cached = true;
                 cur = 0;
                 __syncthreads();
-                // The cached candidates in rank order (a candidate's place
-                // is the number of larger keys; keys are distinct), then
-                // decided in that order by the first wave, 64 at a time.
+                // Up to RANK_DECIDE_MAX cached candidates: in rank order (a
+                // candidate's place is the number of larger keys; keys are
+                // distinct), then decided in that order by the first wave,
+                // 64 at a time.  More: parallel passes over the cache.
                 // Every listed neighbour of a candidate ranks better, so it
                 // is decided in an earlier block or is an earlier lane of
                 // this block; the earliest undecided lane can therefore
                 // always decide, and each step of a block decides at least
                 // one lane.  The result is the sequential greedy pass.
+                if (n_in > RANK_DECIDE_MAX) continue;
                 for (int i = tid; i < n_in; i += NMS_THREADS) rc_key[i] = keys[rc_pos[i]];
                 __syncthreads();
                 for (int i = tid; i < n_in; i += NMS_THREADS) {
@@ -788,7 +796,7 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
         decode(kk, f, k, r, c);
         const Box b = window_box(T.L[k], boxes, r, c);
         hog_det d;
-        d.frame = frame_base + frame; d.filter = f; d.level = k; d.row = r; d.col = c;
+        d.frame = frame_base + frame; d.filter = f; d.level = T.k_base + k; d.row = r; d.col = c;
         d.x0 = b.x0; d.y0 = b.y0; d.x1 = b.x1; d.y1 = b.y1;
         d.score = score_from_order((unsigned int)(kk >> 32));
         dets[(long long)frame * cap + e] = d;

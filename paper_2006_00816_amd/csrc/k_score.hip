@@ -55,7 +55,8 @@ template <int ROWS>
 __global__ __launch_bounds__(ROWS * 64) void hog_score_kernel(
     LevelTable T, ScoreOrder ord, int groups, int per_frame, int units, int halves, const float* __restrict__ feat,
     const float4* __restrict__ bpack, const float* __restrict__ bias, int nf, float thresh,
-    float* __restrict__ dense, unsigned long long* __restrict__ poskey, int atomic_key) {
+    float* __restrict__ dense, unsigned long long* __restrict__ poskey, int atomic_key,
+    const hog_region* __restrict__ regions) {
     __shared__ ScoreSmemT<ROWS> sm;
     int unit, it;
     if (!score_slot(ord, per_frame, units, &unit, &it)) return;
@@ -66,7 +67,7 @@ __global__ __launch_bounds__(ROWS * 64) void hog_score_kernel(
     __syncthreads();
     // halves = 2: slot it runs one half of the tiles of row block it / 2
     score_item<ROWS>(T, frame, grp, halves == 2 ? it >> 1 : it, sm, sm.P[tid >> 6], feat, nf, bias, thresh, dense,
-                     poskey, atomic_key, tid, halves == 2 ? it & 1 : -1);
+                     poskey, atomic_key, tid, halves == 2 ? it & 1 : -1, regions);
 }
 
 // The same work items and dispatch with separable filters (row and column
@@ -75,7 +76,8 @@ template <int ROWS, int RANK>
 __global__ __launch_bounds__(ROWS * 64) void hog_sep_score_kernel(
     LevelTable T, ScoreOrder ord, int groups, int per_frame, int units, int halves, const float* __restrict__ feat,
     const float* __restrict__ row, const float* __restrict__ col, const float* __restrict__ bias, int nf,
-    float thresh, float* __restrict__ dense, unsigned long long* __restrict__ poskey, int atomic_key) {
+    float thresh, float* __restrict__ dense, unsigned long long* __restrict__ poskey, int atomic_key,
+    const hog_region* __restrict__ regions) {
     __shared__ SepSmemT<ROWS, RANK> sm;
     int unit, it;
     if (!score_slot(ord, per_frame, units, &unit, &it)) return;
@@ -85,7 +87,7 @@ __global__ __launch_bounds__(ROWS * 64) void hog_sep_score_kernel(
     load_sep(sm, row, col, nf, grp, tid);
     __syncthreads();
     score_item_sep<ROWS, RANK>(T, frame, grp, halves == 2 ? it >> 1 : it, sm, sm.P[tid >> 6], feat, nf, bias, thresh,
-                               dense, poskey, atomic_key, tid, halves == 2 ? it & 1 : -1);
+                               dense, poskey, atomic_key, tid, halves == 2 ? it & 1 : -1, regions);
 }
 
 namespace {
@@ -209,14 +211,15 @@ bool score_grid(const LevelTable& T, int n, int nf, int rows, ScoreGrid* g) {
 
 hipError_t launch_score_sep(const LevelTable& T, int n, const float* feat, const float* row, const float* col,
                             int rank, const float* bias, int nf, float thresh, float* dense,
-                            unsigned long long* poskey, bool atomic_key, int rows, hipStream_t s) {
+                            unsigned long long* poskey, bool atomic_key, int rows, const hog_region* regions,
+                            hipStream_t s) {
     ScoreGrid g;
     if (T.rows_total <= 0 || n <= 0) return hipSuccess;
     if (!score_grid(T, n, nf, rows, &g)) return hipErrorInvalidValue;
     const int ak = atomic_key ? 1 : 0;
 #define HOG_SEP_LAUNCH(R, K)                                                                                      \
     hipLaunchKernelGGL((hog_sep_score_kernel<R, K>), dim3(g.blocks), dim3(R * 64), 0, s, T, g.ord, g.groups,      \
-                       g.per_frame, g.units, g.halves, feat, row, col, bias, nf, thresh, dense, poskey, ak)
+                       g.per_frame, g.units, g.halves, feat, row, col, bias, nf, thresh, dense, poskey, ak, regions)
     if (rows == SCORE_SMALL_ROWS) {
         switch (rank) {
             case 1: HOG_SEP_LAUNCH(SCORE_SMALL_ROWS, 1); break;
@@ -252,18 +255,18 @@ int score_rows_auto(const LevelTable& T, int n, int nf, int cus) {
 
 hipError_t launch_score(const LevelTable& T, int n, const float* feat, const float4* bpack, const float* bias,
                         int nf, float thresh, float* dense, unsigned long long* poskey, bool atomic_key, int rows,
-                        hipStream_t s) {
+                        const hog_region* regions, hipStream_t s) {
     ScoreGrid g;
     if (T.rows_total <= 0 || n <= 0) return hipSuccess;
     if (!score_grid(T, n, nf, rows, &g)) return hipErrorInvalidValue;
     if (rows == SCORE_SMALL_ROWS)
         hipLaunchKernelGGL(hog_score_kernel<SCORE_SMALL_ROWS>, dim3(g.blocks), dim3(SCORE_SMALL_ROWS * 64), 0, s, T,
                            g.ord, g.groups, g.per_frame, g.units, g.halves, feat, bpack, bias, nf, thresh, dense,
-                           poskey, atomic_key ? 1 : 0);
+                           poskey, atomic_key ? 1 : 0, regions);
     else if (rows == ROWS_PER_ITEM)
         hipLaunchKernelGGL(hog_score_kernel<ROWS_PER_ITEM>, dim3(g.blocks), dim3(ROWS_PER_ITEM * 64), 0, s, T, g.ord,
                            g.groups, g.per_frame, g.units, g.halves, feat, bpack, bias, nf, thresh, dense, poskey,
-                           atomic_key ? 1 : 0);
+                           atomic_key ? 1 : 0, regions);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

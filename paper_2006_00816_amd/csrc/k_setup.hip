@@ -27,12 +27,15 @@ __global__ __launch_bounds__(256) void hog_setup_kernel(
         if (e < T.taps_total) {
             for (int k = 0; k < T.n; ++k) {
                 const DevLevel& L = T.L[k];
+                // a level image of the recursive pyramid is read as is
                 if (e >= L.tap_y && e < L.tap_y + L.h) {
-                    taps[e] = axis_tap((int)(e - L.tap_y), T.h, L.sig);
+                    const int i = (int)(e - L.tap_y);
+                    taps[e] = L.src ? make_int4(i, min(i + 1, L.h - 1), 0, 0) : axis_tap(i, T.h, L.sig);
                     return;
                 }
                 if (e >= L.tap_x && e < L.tap_x + L.w) {
-                    taps[e] = axis_tap((int)(e - L.tap_x), T.w, L.sig);
+                    const int i = (int)(e - L.tap_x);
+                    taps[e] = L.src ? make_int4(i, min(i + 1, L.w - 1), 0, 0) : axis_tap(i, T.w, L.sig);
                     return;
                 }
             }
@@ -109,6 +112,45 @@ __global__ __launch_bounds__(256) void hog_fill_kernel(int* __restrict__ p, int 
 hipError_t launch_fill(int* p, int n, int v, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(hog_fill_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+// Search region of the next frame of each stream from this frame's
+// detections (Sec. VII: faces move little between consecutive frames, so
+// the locations and scales searched can be limited): the best detection's
+// box (the first, in rank order) grown by `margin` px on every side and
+// clipped to the frame, with its level +- span (clipped at 0); the whole
+// frame at every level where the frame has no valid detection.
+__global__ __launch_bounds__(256) void hog_track_kernel(const hog_det* __restrict__ dets,
+                                                         const int* __restrict__ n_dets, int n, int cap, int h, int w,
+                                                         int margin, int span, hog_region* __restrict__ regions) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    hog_region g;
+    if (n_dets[i] > 0) {
+        const hog_det d = dets[(long long)i * cap];
+        g.x0 = max(d.x0 - margin, 0);
+        g.y0 = max(d.y0 - margin, 0);
+        g.x1 = min(d.x1 + margin, w);
+        g.y1 = min(d.y1 + margin, h);
+        g.k_lo = max(d.level - span, 0);
+        g.k_hi = d.level + span;
+    } else {
+        g.x0 = 0;
+        g.y0 = 0;
+        g.x1 = w;
+        g.y1 = h;
+        g.k_lo = 0;
+        g.k_hi = HOG_ALL_LEVELS;
+    }
+    regions[i] = g;
+}
+
+hipError_t launch_track(const hog_det* dets, const int* n_dets, int n, int cap, int h, int w, int margin, int span,
+                        hog_region* regions, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(hog_track_kernel, dim3((n + 255) / 256), dim3(256), 0, s, dets, n_dets, n, cap, h, w, margin,
+                       span, regions);
     return hipGetLastError();
 }
 

@@ -20,7 +20,7 @@ constexpr int CS = NBINS + 1;                     // u64 words per local cell (o
 // LDS of one histogram tile (64 KB).
 struct HistSmem {
     int4 Ty[TPY], Tx[TPX];                        // row / column taps of the tile
-    double H[LC_H * LC_W * CS];                   // cell histograms, integer-valued (see quad_votes)
+    unsigned long long H[LC_H * LC_W * CS];       // fixed-point cell histograms (see quad_votes)
     int V[64 * PLANE];                            // swizzled level pixels (value * 2^16)
 };
 
@@ -40,13 +40,13 @@ __host__ __device__ constexpr int qoff(int ty, int tx) {
 //
 // A vote is the integer M w, M = round(|g| 2^6) (|g| in units of 2^-16)
 // below 2^31 and w the integer weight product (at most 225), so below
-// 2^39; it is formed and summed in float64, where every partial sum of a
-// cell (at most 256 votes, below 2^47) is an exact integer.  The sums are
-// therefore the exact fixed-point totals whatever the order of the
-// additions (LDS float64 atomics), and float64 multiplies run at the full
-// vector rate where 64-bit integer products do not.
+// 2^39; a cell's sum of at most 256 votes stays below 2^47.  The votes
+// are summed with 64-bit integer LDS atomics, so the sums are the exact
+// fixed-point totals whatever the order of the additions.  (Forming and
+// summing them as float64, exact as well, made the kernel 0.29 -> 0.37 ms
+// per 64-frame clip: the float64 LDS atomics are the slower path.)
 template <int Q, bool CHECK>
-__device__ __forceinline__ void quad_votes(const int* __restrict__ sV, int lb, double* __restrict__ h00,
+__device__ __forceinline__ void quad_votes(const int* __restrict__ sV, int lb, unsigned long long* __restrict__ h00,
                                            int ylb, int xlb, int ylim, int xlim) {
     // the two pixel rows 2Q, 2Q + 1 of the quad block and their central
     // differences need level rows 2Q .. 2Q + 3 (tile coordinates, one-pixel
@@ -71,16 +71,16 @@ __device__ __forceinline__ void quad_votes(const int* __restrict__ sV, int lb, d
         const int gy = V[di + 2][ox + 1] - V[di][ox + 1];
         if ((gx | gy) == 0) continue;
         const int bin = orient_bin(gx, gy);
-        const double M = vote_magnitude_f64(gx, gy);
-        atomicAdd(h00 + bin, M * (double)((15 - 2 * oy) * (15 - 2 * ox)));
-        atomicAdd(h00 + CS + bin, M * (double)((15 - 2 * oy) * (2 * ox + 1)));
-        atomicAdd(h00 + LC_W * CS + bin, M * (double)((2 * oy + 1) * (15 - 2 * ox)));
-        atomicAdd(h00 + (LC_W + 1) * CS + bin, M * (double)((2 * oy + 1) * (2 * ox + 1)));
+        const unsigned long long M = vote_magnitude(gx, gy);
+        atomicAdd(h00 + bin, M * (unsigned)((15 - 2 * oy) * (15 - 2 * ox)));
+        atomicAdd(h00 + CS + bin, M * (unsigned)((15 - 2 * oy) * (2 * ox + 1)));
+        atomicAdd(h00 + LC_W * CS + bin, M * (unsigned)((2 * oy + 1) * (15 - 2 * ox)));
+        atomicAdd(h00 + (LC_W + 1) * CS + bin, M * (unsigned)((2 * oy + 1) * (2 * ox + 1)));
     }
 }
 
 template <bool CHECK>
-__device__ __forceinline__ void quad_votes_q(int q, const int* sV, int lb, double* h00, int ylb, int xlb,
+__device__ __forceinline__ void quad_votes_q(int q, const int* sV, int lb, unsigned long long* h00, int ylb, int xlb,
                                              int ylim, int xlim) {
     switch (q) {
         case 0: quad_votes<0, CHECK>(sV, lb, h00, ylb, xlb, ylim, xlim); break;
@@ -156,9 +156,10 @@ __device__ __forceinline__ void resample_tile(const int4* __restrict__ sTy, cons
 // only takes part in them (a workgroup running two tiles side by side).
 __device__ __forceinline__ void hist_tile(const LevelTable& T, const uint8_t* __restrict__ frames, long long fstride,
                                           int pitch, const int4* __restrict__ taps, float* __restrict__ hist,
-                                          int frame, int tile, int tid, HistSmem& sm) {
+                                          int frame, int tile, int tid, HistSmem& sm,
+                                          const uint8_t* __restrict__ casc = nullptr) {
     int* __restrict__ sV = sm.V;
-    double* __restrict__ sH = sm.H;
+    unsigned long long* __restrict__ sH = sm.H;
     int4* __restrict__ sTy = sm.Ty;
     int4* __restrict__ sTx = sm.Tx;
     const bool on = tile >= 0;
@@ -168,17 +169,25 @@ __device__ __forceinline__ void hist_tile(const LevelTable& T, const uint8_t* __
     const int tiles_x = (L.cx + TCX - 1) / TCX;
     const int i0 = (t / tiles_x) * TCY, j0 = (t % tiles_x) * TCX;
     const int ybase = 8 * i0 - 5, xbase = 8 * j0 - 5;   // level coords of tile pixel (0, 0)
+    // the level's source: the frame (sampled through the taps), or its
+    // 8-bit image of the recursive pyramid (identity taps)
+    const bool own = on && L.src && casc != nullptr;
     const uint8_t* __restrict__ U = frames + (long long)frame * fstride;
+    int spitch = pitch;
+    if (own) {
+        U = casc + (long long)frame * T.casc_frame + L.src_off;
+        spitch = L.w;
+    }
 
     if (on) {
-        for (int e = tid; e < LC_H * LC_W * CS; e += HIST_THREADS) sH[e] = 0.0;
+        for (int e = tid; e < LC_H * LC_W * CS; e += HIST_THREADS) sH[e] = 0ull;
         for (int e = tid; e < TPY + TPX; e += HIST_THREADS) {
             if (e < TPY) {
                 const int y = ybase + e;
                 int4 a = make_int4(0, 0, 0, -1);
                 if (y >= 0 && y < L.h) {
                     const int4 tp = taps[L.tap_y + y];
-                    a = make_int4(tp.x * pitch, tp.y * pitch, tp.z, 0);   // row byte offsets
+                    a = make_int4(tp.x * spitch, tp.y * spitch, tp.z, 0);   // row byte offsets
                 }
                 sTy[e] = a;
             } else {
@@ -189,10 +198,10 @@ __device__ __forceinline__ void hist_tile(const LevelTable& T, const uint8_t* __
     }
     __syncthreads();
 
-    // 1. resample (a level at scale 1 copies the frame: its taps have zero
-    // weights on the second sample)
+    // 1. resample (a level at scale 1, or a level image, is a copy of its
+    // source: its taps have zero weights on the second sample)
     if (on) {
-        if (L.sig == (1LL << SIG_BITS)) resample_tile<true>(sTy, sTx, U, sV, tid);
+        if (L.ident) resample_tile<true>(sTy, sTx, U, sV, tid);
         else resample_tile<false>(sTy, sTx, U, sV, tid);
     }
     __syncthreads();
@@ -204,7 +213,7 @@ __device__ __forceinline__ void hist_tile(const LevelTable& T, const uint8_t* __
         const int qb = lane & 15;                         // quad-block column 0..15
         const int q = wave >> 1;                          // quarter of the 64 pixel offsets
         const int lb = qa * PL_W + qb;                    // swizzled base of the quad block
-        double* h00 = &sH[(qa * LC_W + qb) * CS];
+        unsigned long long* h00 = &sH[(qa * LC_W + qb) * CS];
         // valid pixels: 1 <= y <= min(8 cy - 1, h - 2), same for x
         const int ylim = min(8 * L.cy - 1, L.h - 2), xlim = min(8 * L.cx - 1, L.w - 2);
         const bool inner =
@@ -220,10 +229,10 @@ __device__ __forceinline__ void hist_tile(const LevelTable& T, const uint8_t* __
         const int li = tid / TCX, lj = tid - li * TCX;
         const int gi = i0 + li, gj = j0 + lj;
         if (gi < L.cy && gj < L.cx) {
-            const double* src = &sH[((li + 1) * LC_W + lj + 1) * CS];
+            const unsigned long long* src = &sH[((li + 1) * LC_W + lj + 1) * CS];
             float h[NBINS];
 #pragma unroll
-            for (int b = 0; b < NBINS; ++b) h[b] = (float)(src[b] * 0x1p-30);
+            for (int b = 0; b < NBINS; ++b) h[b] = (float)((double)src[b] * 0x1p-30);
             float E = 0.f;
 #pragma unroll
             for (int o = 0; o < NORIENT; ++o) {

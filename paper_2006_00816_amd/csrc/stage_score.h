@@ -38,7 +38,7 @@ __device__ __forceinline__ void tile_windows(const DevLevel& L, int k, int r, in
                                              const float* __restrict__ ring, float& carry0, float& carry1, int g4,
                                              int j, int f0, int f1, bool f0ok, bool f1ok, float b0, float b1,
                                              float thresh, float* __restrict__ D, unsigned long long* __restrict__ PK,
-                                             int atomic_key) {
+                                             int atomic_key, int c_lo, int c_hi) {
     // Window c = 16 t - 9 + j takes P[c + dc] for dc >= 9 - j (cells of
     // this tile) and window c + 16 starts its carry with the cells
     // 7 + j + dc <= 15 of this tile; both are cell (7 + j + dc) mod 16,
@@ -65,6 +65,8 @@ __device__ __forceinline__ void tile_windows(const DevLevel& L, int k, int r, in
 
     const int c = 16 * t - (WIN - 1) + j;
     const bool cok = c >= 0 && c < L.cols;
+    // only windows inside the search region become candidates
+    const bool cin = c >= c_lo && c <= c_hi;
     unsigned long long key = 0ull;
     if (cok) {
         s0 += b0;
@@ -73,6 +75,8 @@ __device__ __forceinline__ void tile_windows(const DevLevel& L, int k, int r, in
             if (f0ok) D[((long long)f0 * L.rows + r) * L.cols + c] = s0;
             if (f1ok) D[((long long)f1 * L.rows + r) * L.cols + c] = s1;
         }
+    }
+    if (cok && cin) {
         if (f0ok && s0 > thresh)
             key = ((unsigned long long)score_order(s0) << 32) | (unsigned long long)(~pack_window(f0, k, r, c));
         if (f1ok && s1 > thresh) {
@@ -94,6 +98,39 @@ __device__ __forceinline__ void tile_windows(const DevLevel& L, int k, int r, in
             PK[c] = key;
         }
     }
+}
+
+// Search region of one window row (wave-uniform): narrows the tiles
+// [tb, te) of the row to those holding windows inside the frame's region
+// (empty if the row has none) and returns the region's window columns
+// [c_lo, c_hi].  Positions of [tb, te) outside the narrowed tiles get key 0
+// here (the tile walk writes the others), unless keys merge by atomic max,
+// which start at zero.  Without a region nothing changes.
+__device__ __forceinline__ void region_row(const LevelTable& T, const DevLevel& L, int k, int r,
+                                           const hog_region* __restrict__ reg, unsigned long long* __restrict__ PKfr,
+                                           int atomic_key, int lane, int& tb, int& te, int& c_lo, int& c_hi) {
+    c_lo = 0;
+    c_hi = L.cols - 1;
+    if (!reg) return;
+    const RegionRange R = region_range(L, k + T.k_base, *reg);
+    int nb = te, ne = te;
+    if (!R.empty() && r >= R.r_lo && r <= R.r_hi) {
+        c_lo = R.c_lo;
+        c_hi = R.c_hi;
+        // window c = 16 t - 9 + j lies in tile (c + 9) / 16
+        nb = max(tb, (R.c_lo + WIN - 1) >> 4);
+        ne = min(te, ((R.c_hi + WIN - 1) >> 4) + 1);
+        if (nb >= ne) nb = ne = te;
+    }
+    if (PKfr && !atomic_key) {
+        unsigned long long* __restrict__ PK = PKfr + L.pos_off + (long long)r * L.cols;
+        const int a0 = max(16 * tb - (WIN - 1), 0), a1 = min(16 * nb - (WIN - 1), L.cols);
+        for (int c = a0 + lane; c < a1; c += 64) PK[c] = 0ull;
+        const int b0 = max(16 * ne - (WIN - 1), 0), b1 = min(16 * te - (WIN - 1), L.cols);
+        for (int c = b0 + lane; c < b1; c += 64) PK[c] = 0ull;
+    }
+    tb = nb;
+    te = ne;
 }
 
 // The score of filter f at window (r, c) is bias_f plus the 3100-term dot
@@ -127,7 +164,7 @@ __device__ __forceinline__ void score_row(const DevLevel& L, int k, int r, const
                                           const ScoreSmemT<ROWS>& sm, float* __restrict__ ring, int grp, int nf,
                                           const float* __restrict__ bias, float thresh, float* __restrict__ Dfr,
                                           unsigned long long* __restrict__ PKfr, int atomic_key, int lane,
-                                          int t_begin, int t_end) {
+                                          int t_begin, int t_end, int c_lo, int c_hi) {
     const int g4 = lane >> 4, j = lane & 15;
     const int pitch = (L.cx + 2) * FPAD;
     const float* __restrict__ Fr = Ffr + L.feat_off + (long long)r * pitch + 4 * g4;
@@ -222,7 +259,7 @@ __device__ __forceinline__ void score_row(const DevLevel& L, int k, int r, const
         wave_lds_order();
 
         tile_windows<XTRA>(L, k, r, t, t_begin, ring, carry0, carry1, g4, j, f0, f1, f0ok, f1ok, b0, b1, thresh, D,
-                           PK, atomic_key);
+                           PK, atomic_key, c_lo, c_hi);
     }
 }
 
@@ -237,7 +274,7 @@ __device__ __forceinline__ void score_item(const LevelTable& T, int frame, int g
                                            float* __restrict__ ring, const float* __restrict__ feat, int nf,
                                            const float* __restrict__ bias, float thresh, float* __restrict__ dense,
                                            unsigned long long* __restrict__ poskey, int atomic_key, int tid,
-                                           int half = -1) {
+                                           int half = -1, const hog_region* __restrict__ regions = nullptr) {
     // the wave's row, made wave-uniform so that the level's fields live in
     // scalar registers
     const int q = item * ROWS + __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -258,17 +295,21 @@ __device__ __forceinline__ void score_item(const LevelTable& T, int frame, int g
         te = half ? ntiles : mid;
         if (tb >= te) return;
     }
+    int c_lo, c_hi;
+    region_row(T, L, k, r, regions ? regions + frame : nullptr, PKfr, atomic_key, lane, tb, te, c_lo, c_hi);
+    if (tb >= te) return;
     if (fg == 5)
-        score_row<3, true, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane, tb, te);
+        score_row<3, true, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane, tb, te,
+                                 c_lo, c_hi);
     else if (fg == 4)
         score_row<3, false, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane, tb,
-                                  te);
+                                  te, c_lo, c_hi);
     else if (fg >= 2)
         score_row<2, false, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane, tb,
-                                  te);
+                                  te, c_lo, c_hi);
     else
         score_row<1, false, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane, tb,
-                                  te);
+                                  te, c_lo, c_hi);
 }
 
 // ------------------------------------------- separable (row / column) filters
@@ -330,7 +371,8 @@ __device__ __forceinline__ void score_row_sep(const DevLevel& L, int k, int r, c
                                               const SepSmemT<ROWS, RANK>& sm, float* __restrict__ ring, int grp,
                                               int nf, const float* __restrict__ bias, float thresh,
                                               float* __restrict__ Dfr, unsigned long long* __restrict__ PKfr,
-                                              int atomic_key, int lane, int t_begin, int t_end) {
+                                              int atomic_key, int lane, int t_begin, int t_end, int c_lo,
+                                              int c_hi) {
     const int g4 = lane >> 4, j = lane & 15;
     const int pitch = (L.cx + 2) * FPAD;
     const float* __restrict__ Fr = Ffr + L.feat_off + (long long)r * pitch + 4 * g4;
@@ -387,7 +429,7 @@ __device__ __forceinline__ void score_row_sep(const DevLevel& L, int k, int r, c
                     make_float4(acc[f][0], acc[f][1], acc[f][2], acc[f][3]);
         wave_lds_order();
         tile_windows<XTRA>(L, k, r, t, t_begin, ring, carry0, carry1, g4, j, f0, f1, f0ok, f1ok, b0, b1, thresh, D,
-                           PK, atomic_key);
+                           PK, atomic_key, c_lo, c_hi);
     }
 }
 
@@ -398,7 +440,7 @@ __device__ __forceinline__ void score_item_sep(const LevelTable& T, int frame, i
                                                const float* __restrict__ feat, int nf, const float* __restrict__ bias,
                                                float thresh, float* __restrict__ dense,
                                                unsigned long long* __restrict__ poskey, int atomic_key, int tid,
-                                               int half = -1) {
+                                               int half = -1, const hog_region* __restrict__ regions = nullptr) {
     const int q = item * ROWS + __builtin_amdgcn_readfirstlane(tid >> 6);
     if (q >= T.rows_total) return;
     const int k = HOG_FIND_LEVEL(T, q, row_off);
@@ -417,12 +459,15 @@ __device__ __forceinline__ void score_item_sep(const LevelTable& T, int frame, i
         te = half ? ntiles : mid;
         if (tb >= te) return;
     }
+    int c_lo, c_hi;
+    region_row(T, L, k, r, regions ? regions + frame : nullptr, PKfr, atomic_key, lane, tb, te, c_lo, c_hi);
+    if (tb >= te) return;
     if (fg == FGROUP)
         score_row_sep<RANK, true, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane,
-                                        tb, te);
+                                        tb, te, c_lo, c_hi);
     else
         score_row_sep<RANK, false, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key,
-                                         lane, tb, te);
+                                         lane, tb, te, c_lo, c_hi);
 }
 
 }  // namespace hog

@@ -27,7 +27,20 @@ class HogError(RuntimeError):
 
 
 class hog_params(ctypes.Structure):
-    _fields_ = [("upsample", ctypes.c_int32), ("thresh", ctypes.c_float), ("iou", ctypes.c_float)]
+    _fields_ = [("upsample", ctypes.c_int32), ("thresh", ctypes.c_float), ("iou", ctypes.c_float),
+                ("min_face", ctypes.c_int32), ("regions", ctypes.c_void_p)]
+
+
+ALL_LEVELS = 1 << 30
+CASCADE = 0x100   # recursive pyramid, or-ed into upsample
+
+
+def region_tensor(regions, device="cuda"):
+    """Search regions as the int32 [n][6] device tensor the library reads:
+    rows (x0, y0, x1, y1, k_lo, k_hi) in frame pixels (half-open) and
+    pyramid levels (inclusive)."""
+    t = torch.as_tensor(regions, dtype=torch.int32).reshape(-1, 6)
+    return t.to(device).contiguous()
 
 
 class hog_tuning(ctypes.Structure):
@@ -112,6 +125,11 @@ def lib():
         "hog_detect": ([vp, vp, i32, i32, i32, vp, vp, i32, vp, i32, vp, vp, sz, vp], i32),
         "hog_detect_batch": ([vp, vp, i32, i32, i32, i32, i64, vp, vp, i32, vp, i32, vp, vp, sz, vp], i32),
         "hog_detect_batch_static": ([vp, vp, i32, i32, i32, i32, i64, vp, vp, i32, vp, i32, vp, vp], i32),
+        "hog_track_regions": ([vp, vp, i32, i32, i32, i32, i32, i32, vp, vp], i32),
+        "hog_pipeline_create": ([vp, vp, vp, vp, vp, i32], i32),
+        "hog_pipeline_submit": ([vp, vp, i32, i64], i32),
+        "hog_pipeline_drain": ([vp], i32),
+        "hog_pipeline_destroy": ([vp], i32),
         "hog_graph_create": ([vp, vp, vp, i32, i32, i32, i32, i64, vp, vp, i32, vp, i32, vp, vp, sz, vp], i32),
         "hog_graph_launch": ([vp, vp], i32),
         "hog_graph_destroy": ([vp], i32),
@@ -295,20 +313,32 @@ def detect_batch_bank(frames: torch.Tensor, bank: FilterBank, thresh=0.0, iou=0.
     return dets_to_numpy(dets, nd)
 
 
-def _params(thresh, iou, upsample):
-    return hog_params(upsample, thresh, iou)
+def _params(thresh, iou, upsample, min_face=0, regions=None, n=None):
+    """hog_params; `regions` is an int32 [n][6] device tensor (see
+    region_tensor) or None."""
+    rp = None
+    if regions is not None:
+        if regions.dtype != torch.int32 or regions.dim() != 2 or regions.shape[1] != 6:
+            raise HogError("regions must be an int32 [n][6] device tensor")
+        if n is not None and regions.shape[0] < n:
+            raise HogError(f"{regions.shape[0]} regions for {n} frames")
+        rp = _ptr(regions).value
+    return hog_params(upsample, thresh, iou, int(min_face), rp)
 
 
 def detect_batch_into(frames: torch.Tensor, W: torch.Tensor, b: torch.Tensor, dets: torch.Tensor,
-                      n_dets: torch.Tensor, thresh: float = 0.0, iou: float = 0.5, upsample: int = 1, ws=None):
+                      n_dets: torch.Tensor, thresh: float = 0.0, iou: float = 0.5, upsample: int = 1, ws=None,
+                      min_face: int = 0, regions: torch.Tensor = None):
     """Enqueue hog_detect_batch into caller-provided outputs: dets int32
-    [n][cap][10] (hog_det records), n_dets int32 [n]."""
+    [n][cap][10] (hog_det records), n_dets int32 [n].  min_face skips the
+    levels whose window spans fewer frame pixels; regions (int32 [n][6],
+    device) restricts each frame's search."""
     if frames.dtype != torch.uint8 or frames.dim() != 3:
         raise HogError("frames must be a uint8 [n][h][w] device tensor")
     n, h, w = (int(v) for v in frames.shape)
     cap = int(dets.shape[1])
     nf = int(W.shape[0])
-    prm = _params(thresh, iou, upsample)
+    prm = _params(thresh, iou, upsample, min_face, regions, n)
     wp, wn = _ws(ws, workspace_bytes(h, w, upsample, n, nf))
     _check(lib().hog_detect_batch(ctypes.byref(prm), _fptr(frames), n, h, w, int(frames.stride(1)),
                                   int(frames.stride(0)), _ptr(W), _ptr(b), nf, _ptr(dets), cap, _ptr(n_dets),
@@ -358,10 +388,22 @@ def detect(frame: torch.Tensor, W, b, thresh=0.0, iou=0.5, upsample=1, cap=MAX_D
     return out[0], int(cnt[0])
 
 
-def detect_batch(frames: torch.Tensor, W, b, thresh=0.0, iou=0.5, upsample=1, cap=MAX_DETS, ws=None):
+def detect_batch(frames: torch.Tensor, W, b, thresh=0.0, iou=0.5, upsample=1, cap=MAX_DETS, ws=None, min_face=0,
+                 regions=None):
     dets, nd = alloc_dets(int(frames.shape[0]), cap, frames.device)
-    detect_batch_into(frames, W, b, dets, nd, thresh, iou, upsample, ws)
+    detect_batch_into(frames, W, b, dets, nd, thresh, iou, upsample, ws, min_face, regions)
     return dets_to_numpy(dets, nd)
+
+
+def track_regions(dets: torch.Tensor, n_dets: torch.Tensor, h: int, w: int, margin: int, span: int,
+                  regions: torch.Tensor):
+    """Enqueue hog_track_regions: the next frames' search regions (int32
+    [n][6], written in place) from the detections of these frames."""
+    n, cap = int(dets.shape[0]), int(dets.shape[1])
+    if regions.dtype != torch.int32 or tuple(regions.shape) != (n, 6):
+        raise HogError("regions must be an int32 [n][6] device tensor")
+    _check(lib().hog_track_regions(_ptr(dets), _ptr(n_dets), n, cap, h, w, margin, span, _ptr(regions), _stream()),
+           "hog_track_regions")
 
 
 def tuning_get(h: int, w: int, upsample: int, n: int, nf: int):
@@ -441,15 +483,15 @@ class DetectGraph:
     FilterBank) takes the place of W and b when given."""
 
     def __init__(self, frames: torch.Tensor, W=None, b=None, cap=MAX_DETS, thresh=0.0, iou=0.5, upsample=1,
-                 bank: FilterBank = None):
+                 bank: FilterBank = None, min_face: int = 0, regions: torch.Tensor = None):
         n, h, w = (int(v) for v in frames.shape)
         if bank is None:
             bank = FilterBank(b, W=W)
         nf = bank.nf
-        self.frames, self.bank = frames, bank
+        self.frames, self.bank, self.regions = frames, bank, regions
         self.dets, self.n_dets = alloc_dets(n, cap, frames.device)
         self.ws = torch.empty(workspace_bytes(h, w, upsample, n, nf), dtype=torch.uint8, device=frames.device)
-        self.prm = _params(thresh, iou, upsample)
+        self.prm = _params(thresh, iou, upsample, min_face, regions, n)
         self.stream = torch.cuda.Stream(device=frames.device)
         self.handle = ctypes.c_void_p()
         torch.cuda.synchronize(frames.device)
@@ -654,3 +696,73 @@ def profile_read(kernel: str):
     cnt = ctypes.c_int64(0)
     _check(lib().hog_profile_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(cnt)), "hog_profile_read")
     return ms.value, cnt.value
+
+
+# ----------------------------------------------------------- host pipeline
+CONSUMER_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                               ctypes.c_int)
+
+
+class hog_pipeline_config(ctypes.Structure):
+    _fields_ = [("h", ctypes.c_int32), ("w", ctypes.c_int32), ("batch", ctypes.c_int32), ("depth", ctypes.c_int32),
+                ("cap", ctypes.c_int32), ("consumer_threads", ctypes.c_int32), ("staging", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("consumer", CONSUMER_FN), ("user", ctypes.c_void_p)]
+
+
+class Pipeline:
+    """hog_pipeline: frames from host memory through the detector to a
+    consumer called on the library's consumer threads with each batch's
+    detections.  consumer(first_frame, dets, n_dets) receives numpy copies
+    (DET_DTYPE records [n][cap], int32 [n]); None keeps only counts."""
+
+    def __init__(self, W: torch.Tensor, b: torch.Tensor, h: int, w: int, batch: int, depth: int = 3, cap: int = 64,
+                 consumer_threads: int = 1, staging: bool = True, consumer=None, thresh: float = 0.0,
+                 iou: float = 0.5, upsample: int = 1, min_face: int = 0):
+        self.W, self.b, self.user_fn = W, b, consumer
+        self.frames_done = 0
+
+        def _cb(user, first, n, dets, n_dets, cap_):
+            nd = np.ctypeslib.as_array(ctypes.cast(n_dets, ctypes.POINTER(ctypes.c_int32)), (n,)).copy()
+            self.frames_done += n
+            if self.user_fn is not None:
+                raw = np.ctypeslib.as_array(ctypes.cast(dets, ctypes.POINTER(ctypes.c_int32)), (n, cap_, 10)).copy()
+                self.user_fn(int(first), raw.view(DET_DTYPE).reshape(n, cap_), nd)
+
+        self._cb = CONSUMER_FN(_cb)
+        self.cfg = hog_pipeline_config(h, w, batch, depth, cap, consumer_threads, 1 if staging else 0, 0, self._cb,
+                                       None)
+        self.prm = _params(thresh, iou, upsample, min_face)
+        self.handle = ctypes.c_void_p()
+        _check(lib().hog_pipeline_create(ctypes.byref(self.handle), ctypes.byref(self.prm), ctypes.byref(self.cfg),
+                                         _ptr(W), _ptr(b), int(W.shape[0])), "hog_pipeline_create")
+
+    def submit(self, frames, first_frame: int):
+        """frames: host uint8 [n][h][w], a C-contiguous numpy array or a CPU
+        tensor (pinned or not)."""
+        if isinstance(frames, torch.Tensor):
+            if frames.is_cuda or frames.dtype != torch.uint8 or not frames.is_contiguous():
+                raise HogError("frames must be a contiguous host uint8 tensor")
+            ptr, n = ctypes.c_void_p(frames.data_ptr()), int(frames.shape[0])
+        else:
+            if frames.dtype != np.uint8 or not frames.flags.c_contiguous:
+                raise HogError("frames must be a C-contiguous uint8 array")
+            ptr, n = ctypes.c_void_p(frames.ctypes.data), int(frames.shape[0])
+        if tuple(frames.shape[1:]) != (self.cfg.h, self.cfg.w):
+            raise HogError("frame size differs from the pipeline's")
+        _check(lib().hog_pipeline_submit(self.handle, ptr, n, int(first_frame)), "hog_pipeline_submit")
+
+    def drain(self):
+        _check(lib().hog_pipeline_drain(self.handle), "hog_pipeline_drain")
+
+    def close(self):
+        if self.handle:
+            st = lib().hog_pipeline_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+            _check(st, "hog_pipeline_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

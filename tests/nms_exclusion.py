@@ -111,12 +111,13 @@ def check_ranking(c, conf, cand_gpu, near):
     return pairs
 
 
-def check_kept(frame, W, b, upsample, dets, thresh=0.0, iou=0.5, near=1e-4, cand_gpu=None):
+def check_kept(frame, W, b, upsample, dets, thresh=0.0, iou=0.5, near=1e-4, cand_gpu=None, min_face=0, region=None):
     """End-to-end check of a frame's GPU detections against the oracle:
     every window whose decision is sure must be kept or dropped on the GPU
     exactly as by the oracle; with the GPU's candidates, also their rank
-    order (check_ranking).  Returns statistics of the comparison."""
-    allw = oracle.candidates(frame, W, b, thresh - near, upsample)
+    order (check_ranking).  min_face and region restrict the windows as in
+    the detection.  Returns statistics of the comparison."""
+    allw = oracle.candidates(frame, W, b, thresh - near, upsample, min_face=min_face, region=region)
     c, st, conf = decisions_with_conflicts(allw, thresh, iou, near)
     key = list(zip(c["f"].tolist(), c["k"].tolist(), c["r"].tolist(), c["c"].tolist()))
     index = {k: i for i, k in enumerate(key)}

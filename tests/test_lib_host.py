@@ -65,6 +65,23 @@ def test_pyramid_matches_oracle(L, h, w, u):
         assert g["rows"] == g["cy"] - 9 and g["cols"] == g["cx"] - 9
 
 
+@pytest.mark.parametrize("h,w,u", [(480, 640, 1), (240, 320, 2), (97, 331, 1), (1080, 1920, 2), (80, 80, 1)])
+def test_cascade_pyramid_matches_oracle(L, h, w, u):
+    """Recursive pyramid sizes (floor(5x/6) of the previous level) and the
+    same nominal inverse scales as the direct pyramid."""
+    from paper_2006_00816_amd import hog355
+    got = hog355.pyramid(h, w, u | hog355.CASCADE, 5)
+    want = oracle.pyramid_cascade(h, w, u)
+    assert [(g["h"], g["w"]) for g in got] == [(l.h, l.w) for l in want]
+    assert [g["sig"] for g in got] == [oracle.inverse_scale_fixed(l) for l in want]
+    # level images of every level but a level 0 that is the frame itself
+    # (the other regions shrink a little with the smaller recursive sizes)
+    if len(want) > 1 or u == 2:
+        assert hog355.workspace_bytes(h, w, u | hog355.CASCADE, 2, 5) > hog355.workspace_bytes(h, w, u, 2, 5)
+    assert L.hog_workspace_bytes(h, w, u | 0x200, 1, 5) == 0
+    assert L.hog_workspace_bytes(h, w, 3 | hog355.CASCADE, 1, 5) == 0
+
+
 def test_workspace_bytes(L):
     from paper_2006_00816_amd import hog355
     a = hog355.workspace_bytes(480, 640, 1, 1, 5)
@@ -119,6 +136,49 @@ def test_static_entry_point_checks_before_launch(L):
     assert call(1, 480, 640, nf=0) == -1
     assert call(0, 480, 640) == -1
     assert L.hog_strerror(-8) == b"the call needs more workspace than the library's fixed scratch array"
+
+
+def test_region_and_level_arguments_checked_before_launch(L):
+    """min_face out of range and bad hog_track_regions arguments are
+    rejected on the host (dummy pointers, no GPU); hog_params has the
+    header's layout."""
+    from paper_2006_00816_amd import hog355
+    assert ctypes.sizeof(hog355.hog_params) == 24 and hog355.hog_params.regions.offset == 16
+    v = ctypes.c_void_p
+    for mf, want in ((-1, -1), (65537, -1)):
+        p = hog355.hog_params(1, 0.0, 0.5, mf, None)
+        assert L.hog_detect(ctypes.byref(p), v(1), 240, 320, 320, v(1), v(1), 1, v(1), 16, v(1), v(1), 1 << 40,
+                            None) == want
+    ok = dict(dets=v(1), nd=v(1), n=2, cap=16, h=480, w=640, margin=8, span=1, regs=v(1))
+
+    def track(**kw):
+        a = {**ok, **kw}
+        return L.hog_track_regions(a["dets"], a["nd"], a["n"], a["cap"], a["h"], a["w"], a["margin"], a["span"],
+                                   a["regs"], None)
+    for bad in (dict(dets=None), dict(nd=None), dict(regs=None), dict(n=0), dict(cap=0), dict(cap=5000),
+                dict(h=0), dict(w=5000), dict(margin=-1), dict(span=-1), dict(span=29)):
+        assert track(**bad) == -1, bad
+
+
+def test_pipeline_config_checked_before_any_allocation(L):
+    """Invalid pipeline configurations are rejected before the library
+    touches the GPU or allocates (dummy pointers)."""
+    from paper_2006_00816_amd import hog355
+    v = ctypes.c_void_p
+    prm = hog355.hog_params(1, 0.0, 0.5, 0, None)
+    good = dict(h=480, w=640, batch=4, depth=2, cap=16, consumer_threads=1, staging=1)
+    for bad in (dict(batch=0), dict(batch=2000), dict(depth=0), dict(depth=17), dict(cap=0), dict(cap=5000),
+                dict(consumer_threads=0), dict(staging=2), dict(h=5000), dict(w=0)):
+        c = {**good, **bad}
+        cfg = hog355.hog_pipeline_config(c["h"], c["w"], c["batch"], c["depth"], c["cap"], c["consumer_threads"],
+                                         c["staging"], 0, hog355.CONSUMER_FN(), None)
+        out = v()
+        assert L.hog_pipeline_create(ctypes.byref(out), ctypes.byref(prm), ctypes.byref(cfg), v(1), v(1), 5) == -1, bad
+        assert not out.value
+    cfg = hog355.hog_pipeline_config(480, 640, 4, 2, 16, 1, 1, 0, hog355.CONSUMER_FN(), None)
+    prm_r = hog355.hog_params(1, 0.0, 0.5, 0, 1)   # regions are not supported by the pipeline
+    assert L.hog_pipeline_create(ctypes.byref(v()), ctypes.byref(prm_r), ctypes.byref(cfg), v(1), v(1), 5) == -1
+    assert L.hog_pipeline_submit(None, v(1), 1, 0) == -1 and L.hog_pipeline_drain(None) == -1
 
 
 def test_level_table_limits(L):

@@ -516,3 +516,199 @@ def test_separable_two_pass_equals_filter_scores():
                                    for y in range(r, r + 10)]
                         tot += sum(col[f, i, dr, ch] * scratch[dr] for dr in range(10))
                 assert abs(S[f, r, c] - tot) < 1e-12
+
+
+# ------------------------------------- analysed levels and search regions
+def test_level_skipping_worked_example():
+    """Sec. V-A: 640x480 frames with faces of at least 20 % of the image
+    skip the largest scale.  The minimum face (20 % of each side) and its
+    size one 5/6 step down are the paper's numbers; the levels kept by
+    face_levels at that minimum are every level but the first."""
+    g = _gold("level_skipping.json")
+    w, h = g["frame_wh"]["value"]
+    frac = g["min_face_fraction"]["value"]
+    fw, fh = round(frac * w), round(frac * h)
+    assert [fw, fh] == g["min_face_wh_level0"]["value"]
+    assert [round(fw * 5 / 6), round(fh * 5 / 6)] == g["min_face_wh_level1"]["value"]
+    levels = hog.pyramid(h, w)
+    kept = [lv.k for lv in hog.face_levels(levels, min(fw, fh))]
+    skipped = sorted(set(lv.k for lv in levels) - set(kept))
+    assert skipped == g["skipped_levels"]["value"]
+    # the smallest face spans exactly one window at the first kept level
+    assert round(min(fw, fh) * levels[kept[0]].p / levels[kept[0]].q) == hog.WIN * hog.CELL
+
+
+def test_level_skipping_keeps_analysed_work_flat():
+    """Sec. VI (scalability): with the face at least 20 % of the frame
+    height, the skipped scales grow with the frame, and the analysed
+    pyramid of 1280x960 and 2560x1920 frames stays near the 640x480 one
+    (the paper reports feature and classifier time independent
+    of the frame size).  The first kept level lands within one 5/6 step
+    of the scale at which the smallest face is window-sized, so the
+    analysed pyramids stay within a factor (6/5)^2 of each other; without
+    skipping they grow about 4x per step."""
+    sizes = [(480, 640), (960, 1280), (1920, 2560)]
+    px = []
+    full = []
+    for h, w in sizes:
+        lv = hog.pyramid(h, w)
+        px.append(sum(l.h * l.w for l in hog.face_levels(lv, h // 5)))
+        full.append(sum(l.h * l.w for l in lv))
+    assert max(px) < 1.44 * min(px), px
+    assert full[1] > 3.5 * full[0] and full[2] > 3.5 * full[1]
+
+
+def test_level_skipping_boundary_is_exact():
+    """A level is kept exactly when its window spans min_face frame px or
+    more: 80 * (6/5)^k >= min_face.  At 640x480: 80 keeps level 0, 81
+    skips it; 96 keeps level 1 (96 px window), 97 skips it too."""
+    lv = hog.pyramid(480, 640)
+    assert [l.k for l in hog.face_levels(lv, 0)] == list(range(10))
+    assert hog.face_levels(lv, 80)[0].k == 0
+    assert hog.face_levels(lv, 81)[0].k == 1
+    assert hog.face_levels(lv, 96)[0].k == 1
+    assert hog.face_levels(lv, 97)[0].k == 2
+    # at 2x upsampling the first level's window spans 40 frame px
+    lv2 = hog.pyramid(240, 320, 2)
+    assert hog.face_levels(lv2, 40)[0].k == 0 and hog.face_levels(lv2, 41)[0].k == 1
+
+
+def _cands_clip(seed=5):
+    from paper_2006_00816_amd import synth
+    wl = synth.config1(seed=seed, n=1)
+    return wl.frames[0], wl.W, wl.b
+
+
+def test_region_whole_frame_is_no_region():
+    U, W, b = _cands_clip()
+    U = U[::2, ::2].copy()   # 240x320 keeps the float64 oracle quick
+    a = hog.candidates(U, W, b)
+    c = hog.candidates(U, W, b, region=(0, 0, 320, 240, 0, hog.HUGE_LEVEL))
+    assert len(a) > 100 and np.array_equal(a, c)
+    assert len(hog.candidates(U, W, b, region=(0, 0, 0, 0, 0, hog.HUGE_LEVEL))) == 0
+    assert len(hog.candidates(U, W, b, region=(0, 0, 320, 240, 99, 99))) == 0
+
+
+def test_region_hand_cases():
+    """Level-0 window (0, 0) of a 240x320 frame covers frame pixels
+    [0, 80) x [0, 80); every box of a later level is at least 96 px wide,
+    and the level-0 window (0, 1) starts at x = 8.  So the region
+    [0, 80) x [0, 80) searches exactly window (0, 0) of level 0, and
+    [0, 88) x [0, 80) adds window (0, 1)."""
+    lv = hog.pyramid(240, 320)
+    assert hog.window_box(lv[0], 0, 0) == (0, 0, 80, 80)
+    assert hog.window_box(lv[0], 0, 1) == (8, 0, 88, 80)
+    assert all(int(hog.window_box(l, 0, 0)[2]) >= 96 for l in lv[1:])
+    m = [hog.window_in_region(l, *np.meshgrid(np.arange(l.rows), np.arange(l.cols), indexing="ij"),
+                              (0, 0, 80, 80, 0, 99)) for l in lv]
+    assert m[0][0, 0] and m[0].sum() == 1 and all(x.sum() == 0 for x in m[1:])
+    m = hog.window_in_region(lv[0], *np.meshgrid(np.arange(lv[0].rows), np.arange(lv[0].cols), indexing="ij"),
+                             (0, 0, 88, 80, 0, 0))
+    assert sorted(zip(*np.nonzero(m))) == [(0, 0), (0, 1)]
+
+
+def test_region_monotone_and_inside():
+    """A region inside another searches a subset of its windows; every
+    candidate's box lies inside its region and level range."""
+    U, W, b = _cands_clip(6)
+    U = U[::2, ::2].copy()
+    big = (40, 20, 300, 230, 0, 4)
+    small = (90, 50, 250, 200, 1, 3)
+    A = hog.candidates(U, W, b, region=big)
+    B = hog.candidates(U, W, b, region=small)
+    key = lambda a: set(zip(a["f"], a["k"], a["r"], a["c"]))
+    assert 0 < len(B) < len(A) and key(B) <= key(A)
+    for a, reg in ((A, big), (B, small)):
+        assert np.all(a["x0"] >= reg[0]) and np.all(a["y0"] >= reg[1])
+        assert np.all(a["x1"] <= reg[2]) and np.all(a["y1"] <= reg[3])
+        assert np.all(a["k"] >= reg[4]) and np.all(a["k"] <= reg[5])
+
+
+def test_min_face_equals_dropping_levels():
+    """Skipping levels removes exactly the candidates of the skipped
+    levels and keeps the others bit for bit."""
+    U, W, b = _cands_clip(7)
+    U = U[::2, ::2].copy()
+    a = hog.candidates(U, W, b)
+    c = hog.candidates(U, W, b, min_face=61)     # 240x320: 80 (6/5)^k >= 61 keeps all; 81 drops level 0
+    assert np.array_equal(a, c)
+    d = hog.candidates(U, W, b, min_face=81)
+    assert np.array_equal(d, a[a["k"] >= 1])
+
+
+def test_track_region_hand_cases():
+    kept = np.zeros(2, hog.CAND_DTYPE)
+    kept["x0"], kept["y0"], kept["x1"], kept["y1"], kept["k"] = (100, 300), (50, 10), (196, 396), (146, 106), (2, 0)
+    assert hog.track_region(kept, 480, 640, 16, 1) == (84, 34, 212, 162, 1, 3)
+    kept["x0"][0], kept["y0"][0], kept["x1"][0], kept["y1"][0], kept["k"][0] = 5, 3, 635, 470, 0
+    assert hog.track_region(kept, 480, 640, 16, 2) == (0, 0, 640, 480, 0, 2)
+    assert hog.track_region(kept[:0], 480, 640, 16, 2) == (0, 0, 640, 480, 0, hog.HUGE_LEVEL)
+
+
+# -------------------------------------------------- recursive pyramid (R20)
+def test_cascade_sizes_hand_derived():
+    """Recursive floor(5x/6) sizes of a 640x480 frame, worked by hand:
+    533 = floor(3200/6), 444 = floor(2665/6), ... down to 122x91 (the next,
+    101x75, is below the window).  They differ from the direct sizes by a
+    pixel from level 4 on (230 against 231)."""
+    want = [(480, 640), (400, 533), (333, 444), (277, 370), (230, 308), (191, 256), (159, 213), (132, 177),
+            (110, 147), (91, 122)]
+    assert [(l.h, l.w) for l in hog.pyramid_cascade(480, 640)] == want
+    direct = [(l.h, l.w) for l in hog.pyramid(480, 640)]
+    assert direct[:4] == want[:4] and direct[4] == (231, 308)
+    assert [(l.h, l.w) for l in hog.pyramid_cascade(240, 320, 2)] == want
+    assert [l.k for l in hog.pyramid_cascade(79, 500)] == []
+
+
+def test_cascade_taps_exact_fractions():
+    """A 5/6 step puts output sample i at (12 i + 1)/10 of the input: the
+    fractional parts cycle through 1/10, 3/10, 5/10, 7/10, 9/10, whose
+    nearest multiples of 1/256 are 26, 77, 128, 179 and 230."""
+    i0, i1, a = hog.cascade_taps(10, 12)
+    assert list(a) == [26, 77, 128, 179, 230] * 2
+    assert list(i0) == [0, 1, 2, 3, 4, 6, 7, 8, 9, 10] and list(i1) == [1, 2, 3, 4, 5, 7, 8, 9, 10, 11]
+
+
+def test_cascade_constant_and_ramp():
+    """A constant frame stays constant at every level; a horizontal ramp
+    U = 2x + 20 is reproduced at level 1 within the rounding to grey levels
+    (1/2) plus the weight rounding (1/512 of a 2-unit step)."""
+    for lv, L in hog.cascade_levels(np.full((200, 260), 77, np.uint8)):
+        assert np.all(L == 77), lv.k
+    U = np.tile(2 * np.arange(110) + 20, (180, 1)).astype(np.uint8)
+    (l0, L0), (l1, L1) = hog.cascade_levels(U)[:2]
+    assert np.array_equal(L0, U.astype(np.float64))
+    xs = (12 * np.arange(l1.w) + 1) / 10.0
+    assert np.all(np.abs(L1 - (2 * xs + 20)[None, :]) <= 0.5 + 2.0 / 512 + 1e-12)
+
+
+def test_cascade_first_step_equals_rounded_direct():
+    """One 5/6 step from the frame is the direct level 1 (R2, resampled from
+    the frame with the fixed-point inverse scale) rounded to grey levels,
+    wherever the two tap tables agree: an independent route to the same
+    numbers."""
+    from paper_2006_00816_amd import synth
+    U = synth.ClipGenerator(3, 240, 320, face_h=100.0).frame()
+    casc = hog.cascade_levels(U)
+    lv1 = hog.pyramid(240, 320)[1]
+    dy = hog.axis_taps(lv1.h, 240, lv1)
+    dx = hog.axis_taps(lv1.w, 320, lv1)
+    cy = hog.cascade_taps(lv1.h, 240)
+    cx = hog.cascade_taps(lv1.w, 320)
+    assert all(np.array_equal(a, b) for a, b in zip(dy, cy)) and all(np.array_equal(a, b) for a, b in zip(dx, cx))
+    assert np.array_equal(casc[1][1], hog.round_grey(hog.resample(U, lv1)))
+
+
+def test_cascade_candidates_boxes_use_nominal_scale():
+    """Windows of a cascade level map back to the frame with the level's
+    nominal scale u (5/6)^k, as in the direct pyramid: the same box for
+    the same anchor."""
+    from paper_2006_00816_amd import synth
+    U = synth.ClipGenerator(4, 240, 320, face_h=100.0).frame()
+    W, b = synth.filters([101], bias=0.5)
+    c = hog.candidates(U, W, b, cascade=True)
+    assert len(c) > 0
+    for lv in hog.pyramid_cascade(240, 320):
+        sel = c[c["k"] == lv.k]
+        x0, y0, x1, y1 = hog.window_box(lv, sel["r"], sel["c"])
+        assert np.array_equal(sel["x0"], x0) and np.array_equal(sel["y1"], y1)
