@@ -204,8 +204,8 @@ def pixel_grad_leg(n_frames, chunk):
     def run(lo, hi):
         f = fr[lo:hi]
         m = hi - lo
-        hog355.detect_batch_into(f, W, b, dets[:m], nd[:m], upsample=2, ws=ws_d)
-        win, _ = hog355.topk_windows(f, W, b, 10, upsample=2, ws=ws_g)
+        # detections and top-10 windows from one forward pass
+        win, _ = hog355.detect_topk_into(f, W, b, dets[:m], nd[:m], 10, upsample=2, ws=ws_d)
         _, _, dpix = hog355.filter_backward(f, W, win.reshape(-1, 5).contiguous(), ones[:m * 10], upsample=2,
                                             pixels=True, ws=ws_g)
         return dpix
@@ -217,8 +217,8 @@ def pixel_grad_leg(n_frames, chunk):
         dpix = run(lo, min(lo + chunk, n_frames))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return {"workload": f"config 4: {n_frames} 1920x1080 u8 frames, pyramid from 2x, 5 filters f32; detect + "
-                        f"top-10 + backward of summed top-10 scores to pixels, chunks of {chunk}",
+    return {"workload": f"config 4: {n_frames} 1920x1080 u8 frames, pyramid from 2x, 5 filters f32; detect and "
+                        f"top-10 from one forward pass + backward of summed top-10 scores to pixels, chunks of {chunk}",
             "frames": n_frames, "frames_per_s": round(n_frames / dt, 2), "ms_per_frame": round(1e3 * dt / n_frames, 4),
             "dpix_abs_max_last_chunk": float(dpix.abs().max())}
 
@@ -287,6 +287,75 @@ def pipeline_leg(frames_np, W, b, batches):
                         "threads, 64 detections per frame copied back", "legs": out}
 
 
+def graph_fps(hog355, frames, Wt, bt, steps, warmup, **kw):
+    """Graph-replayed frames/s of the clip under detection options kw."""
+    import torch
+    g = hog355.DetectGraph(frames, Wt, bt, **kw)
+    for _ in range(warmup):
+        g.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.launch()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    _, nd = hog355.dets_to_numpy(g.dets, g.n_dets)
+    g.close()
+    return CLIP * steps / dt, 1e3 * dt / steps, float(np.mean(nd))
+
+
+def options_leg(hog355, frames, Wt, bt, tuning, steps, warmup, ksteps):
+    """The clip under the options that change which levels and windows run
+    and how levels are built: the largest scale skipped (min_face 96, the
+    paper's configuration for 640x480 frames with faces of at least 20 %),
+    a search region around the face found in the first frame (its box grown
+    by 32 px, levels +- 1), and the recursive pyramid.  Graph-replayed
+    frames/s and per-kernel times of eager steps."""
+    ws = hog355.Workspace()
+    dets, nd = hog355.alloc_dets(CLIP, hog355.MAX_DETS)
+    regions = first_frame_region(hog355, frames, Wt, bt)
+    hog355.tuning_set(H, W_PX, 1 | hog355.CASCADE, CLIP, NF, tuning)
+    legs = []
+    for name, kw in (("min_face 96 (largest scale skipped)", {"min_face": 96}),
+                     ("search region: first-frame face box + 32 px, levels +- 1", {"regions": regions}),
+                     ("recursive pyramid", {"upsample": 1 | hog355.CASCADE})):
+        fps, ms, kept = graph_fps(hog355, frames, Wt, bt, steps, warmup, **kw)
+        run = lambda: hog355.detect_batch_into(frames, Wt, bt, dets, nd, ws=ws, **kw)
+        kt = kernel_times(hog355, run, ("geom", "cascade", "hist", "feat", "score", "nms_edges", "nms"),
+                          ksteps) if ksteps else {}
+        legs.append({"option": name, "fps": round(fps, 1), "ms_per_step": round(ms, 4),
+                     "kept_per_frame_mean": round(kept, 2), "kernels_per_step": kt})
+    r = regions[0].tolist()
+    return {"region": r, "tuning": tuning, "legs": legs}
+
+
+def tracking_leg(hog355, frames, Wt, bt, n_frames):
+    """One frame per call, as the closed-loop eyeblink case needs: plain,
+    and with the search region of each frame derived on the device from the
+    previous frame's detections (box + 32 px, levels +- 1).  Submit to
+    completion latency."""
+    import torch
+    ws = hog355.Workspace()
+    dets, nd = hog355.alloc_dets(1, hog355.MAX_DETS)
+    regions = hog355.region_tensor([(0, 0, W_PX, H, 0, hog355.ALL_LEVELS)])
+    out = {}
+    for name, track in (("plain", False), ("tracked region", True)):
+        lat = []
+        for i in range(n_frames + 20):
+            t1 = time.perf_counter()
+            hog355.detect_batch_into(frames[i % CLIP:i % CLIP + 1], Wt, bt, dets, nd, ws=ws,
+                                     regions=regions if track else None)
+            if track:
+                hog355.track_regions(dets, nd, H, W_PX, 32, 1, regions)
+            torch.cuda.synchronize()
+            if i >= 20:
+                lat.append(1e3 * (time.perf_counter() - t1))
+        lat = np.array(lat)
+        out[name] = {"p50_ms": round(float(np.percentile(lat, 50)), 4),
+                     "p99_ms": round(float(np.percentile(lat, 99)), 4), "frames": n_frames}
+    return out
+
+
 def copy_calibration(mib):
     """A plain device-to-device copy of known size, to scale the HBM byte
     counters (FETCH_SIZE, WRITE_SIZE) of the detector's kernels."""
@@ -301,7 +370,29 @@ def copy_calibration(mib):
     print(json.dumps({"copy_bytes": n, "copies": 3}), flush=True)
 
 
-def batched_leg(hog355, frames, Wt, bt, args):
+def first_frame_region(hog355, frames, Wt, bt, margin=32, span=1):
+    """Search regions [CLIP][6] for the clip: the best detection of its first
+    frame grown by `margin` px, levels +- span (hog_track_regions)."""
+    import torch
+    dets, nd = hog355.alloc_dets(1, hog355.MAX_DETS)
+    hog355.detect_batch_into(frames[:1], Wt, bt, dets, nd)
+    regions = torch.zeros((CLIP, 6), dtype=torch.int32, device="cuda")
+    hog355.track_regions(dets, nd, H, W_PX, margin, span, regions[:1])
+    regions[:] = regions[:1].clone()
+    return regions
+
+
+def option_kwargs(hog355, name, frames, Wt, bt):
+    if name == "min_face":
+        return {"min_face": 96}
+    if name == "region":
+        return {"regions": first_frame_region(hog355, frames, Wt, bt)}
+    if name == "cascade":
+        return {"upsample": 1 | hog355.CASCADE}
+    return {}
+
+
+def batched_leg(hog355, frames, Wt, bt, args, kw=None):
     """The clip replayed from a hipGraph under the schedule the autotuner
     picks (or the one named), with per-kernel HIP-event times of eager
     steps of that schedule."""
@@ -317,7 +408,10 @@ def batched_leg(hog355, frames, Wt, bt, args):
         hog355.tuning_set(H, W_PX, 1, CLIP, NF, tuning)
     torch.cuda.synchronize()
 
-    g = hog355.DetectGraph(frames, Wt, bt)
+    kw = kw or {}
+    if "upsample" in kw:
+        hog355.tuning_set(H, W_PX, kw["upsample"], CLIP, NF, tuning)
+    g = hog355.DetectGraph(frames, Wt, bt, **kw)
     for _ in range(args.warmup):
         g.launch()
     torch.cuda.synchronize()
@@ -344,15 +438,16 @@ def batched_leg(hog355, frames, Wt, bt, args):
     ws = hog355.Workspace()
     dets, nd = hog355.alloc_dets(CLIP, hog355.MAX_DETS)
     ksteps = min(args.steps, args.kernel_steps)
-    names = ("geom", "hist", "feat", "score", "fused", "nms_edges", "nms")
-    run = lambda: hog355.detect_batch_into(frames, Wt, bt, dets, nd, ws=ws)
+    names = ("geom", "cascade", "hist", "feat", "score", "fused", "nms_edges", "nms")
+    run = lambda: hog355.detect_batch_into(frames, Wt, bt, dets, nd, ws=ws, **kw)
     kern = kernel_times(hog355, run, names, ksteps) if ksteps else {}
+    u = kw.get("upsample", 1)
     if tuning == staged:
         kern_staged = kern
     else:
-        hog355.tuning_set(H, W_PX, 1, CLIP, NF, staged)
+        hog355.tuning_set(H, W_PX, u, CLIP, NF, staged)
         kern_staged = kernel_times(hog355, run, names, ksteps) if ksteps else {}
-        hog355.tuning_set(H, W_PX, 1, CLIP, NF, tuning)
+        hog355.tuning_set(H, W_PX, u, CLIP, NF, tuning)
     return {"dt": dt, "lat": lat, "n_kept": n_kept, "tuning": tuning, "tune_ms": tune_ms, "kern": kern,
             "kern_staged": kern_staged, "staged": staged, "ksteps": ksteps}
 
@@ -399,6 +494,11 @@ def main():
                     help="auto: run the library's autotuner on the clip first")
     ap.add_argument("--separable-rank", type=int, default=1,
                     help="also time the clip with separable filters of this rank (0: skip)")
+    ap.add_argument("--option", choices=("none", "min_face", "region", "cascade"), default="none",
+                    help="run the batched clip itself under one detection option (for profiling it alone): "
+                         "min_face 96, a first-frame face region, or the recursive pyramid")
+    ap.add_argument("--no-options", action="store_true",
+                    help="skip the level-skipping, search-region, recursive-pyramid and tracking legs")
     ap.add_argument("--pipeline-batches", type=int, default=20,
                     help="64-frame batches through the host pipeline per source (0: skip)")
     ap.add_argument("--no-batched", action="store_true",
@@ -453,8 +553,10 @@ def main():
                    "frames_per_step": CLIP, "h": H, "w": W_PX, "filters": NF, "levels": ps["levels"],
                    "windows_per_frame": win, "thresh": 0.0, "iou": 0.5},
     }
+    if args.option != "none":
+        out["config"]["option"] = args.option
     if not args.no_batched:
-        bl = batched_leg(hog355, frames, Wt, bt, args)
+        bl = batched_leg(hog355, frames, Wt, bt, args, option_kwargs(hog355, args.option, frames, Wt, bt))
         fps = CLIP * args.steps / bl["dt"]
         lines = rooflines(bl["kern_staged"], ps, CLIP, 2.0 * 3100 * NF, "hog_score_kernel")
         # the dominant kernel: most GPU time per step among the stage kernels
@@ -485,6 +587,10 @@ def main():
         })
     if args.plain_frames > 0:
         out["plain"] = plain_leg(hog355, frames, Wt, bt, args.plain_frames)
+    if not args.no_options and not args.no_batched:
+        out["options"] = options_leg(hog355, frames, Wt, bt, bl["tuning"], min(args.steps, 200), args.warmup,
+                                     min(args.steps, args.kernel_steps))
+        out["tracking"] = tracking_leg(hog355, frames, Wt, bt, max(args.plain_frames, 200))
     out["paper_context"] = {"ms_per_frame": 0.333, "hardware": "NVIDIA Titan X (Pascal), 16 images per launch",
                             "end_to_end_ms_per_frame": 0.533}
     ksteps = min(args.steps, args.kernel_steps)

@@ -422,6 +422,17 @@ int hog_topk_windows(const uint8_t* frames, int n, int h, int w, int pitch, int6
                      hog_window* windows, float* scores,
                      void* ws, size_t ws_bytes, void* stream);
 
+/* hog_detect_batch and hog_topk_windows of the same frames from one
+ * forward pass: the scoring launch writes the dense scores the top k are
+ * taken from and the candidate keys the detection starts from.  Outputs as
+ * the two calls give them, bit for bit.  The top k range over every window
+ * of every level, so prm->min_face must be 0 and prm->regions NULL.  The
+ * workspace is hog_grad_workspace_bytes(h, w, upsample, n, nf, 1) bytes. */
+int hog_detect_topk(const hog_params* prm, const uint8_t* frames, int n, int h, int w, int pitch,
+                    int64_t frame_stride, const float* filters, const float* bias, int nf,
+                    hog_det* dets, int cap, int* n_dets, int k, hog_window* windows, float* scores,
+                    void* ws, size_t ws_bytes, void* stream);
+
 /* Backward pass of window scores: every forward step of Sec. IV-A
  * differentiated in reverse order (linear classification, feature
  * computation and normalisation, histogramisation, gradient computation,

@@ -1099,6 +1099,37 @@ int hog_topk_windows(const uint8_t* frames, int n, int h, int w, int pitch, int6
     });
 }
 
+int hog_detect_topk(const hog_params* prm, const uint8_t* frames, int n, int h, int w, int pitch, int64_t frame_stride,
+                    const float* filters, const float* bias, int nf, hog_det* dets, int cap, int* n_dets, int k,
+                    hog_window* windows, float* scores, void* ws, size_t ws_bytes, void* stream) {
+    HOG_TRY(check_detect_args(prm, frames, pitch, w, filters, bias, nf, dets, cap, n_dets));
+    if (!windows || !scores || k < 1 || k > 16) return HOG_E_INVAL;
+    // the top k are taken over every window of every level
+    if (prm->regions || prm->min_face) return HOG_E_INVAL;
+    if (n < 1 || (n > 1 && frame_stride < (int64_t)pitch * h)) return HOG_E_INVAL;
+    Plan P;
+    HOG_TRY(make_plan(h, w, prm->upsample, n, nf, &P, 1));
+    HOG_TRY(check_ws(P, ws, ws_bytes));
+    if (P.T.n == 0) return HOG_E_INVAL;
+    long long total = 0;
+    for (int l = 0; l < P.T.n; ++l) total += (long long)P.T.L[l].rows * P.T.L[l].cols * nf;
+    if (total < k) return HOG_E_INVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const bool multi = P.groups > 1;
+    const hog_tuning tune = lookup_tuning(h, w, prm->upsample, n, nf);
+    // one forward pass: dense scores for the top k and candidate keys for
+    // the detection from the same scoring launch
+    HOG_TRY(run_pixels(P, frames, frame_stride, pitch, ws, nullptr, filters, s, multi));
+    const hog_filterbank fb = full_bank(filters, bias, nf);
+    HOG_TRY(score_stage(P, n, at<float>(ws, P.o_feat), bank_of(&fb), prm->thresh, at<float>(ws, P.o_dense),
+                        at<unsigned long long>(ws, P.o_key), tune.score_rows, ws, s));
+    HOG_TRY(nms_chain(P, n, frame_bufs(P, ws, frames, frame_stride, dets, cap, n_dets, 0), prm, cap, nullptr,
+                      tune.nms_rounds, ws, s));
+    return timed("topk", s, [&] {
+        return launch_topk(P.T, n, at<float>(ws, P.o_dense), P.T.dense_frame, nf, k, windows, scores, s);
+    });
+}
+
 int hog_filter_backward(const uint8_t* frames, int n, int h, int w, int pitch, int64_t frame_stride, int upsample,
                         const float* filters, int nf, const hog_window* windows, const float* dscore, int n_windows,
                         float* dfilters, float* dbias, float* dpixels, void* ws, size_t ws_bytes, void* stream) {

@@ -126,6 +126,8 @@ def lib():
         "hog_detect_batch": ([vp, vp, i32, i32, i32, i32, i64, vp, vp, i32, vp, i32, vp, vp, sz, vp], i32),
         "hog_detect_batch_static": ([vp, vp, i32, i32, i32, i32, i64, vp, vp, i32, vp, i32, vp, vp], i32),
         "hog_track_regions": ([vp, vp, i32, i32, i32, i32, i32, i32, vp, vp], i32),
+        "hog_detect_topk": ([vp, vp, i32, i32, i32, i32, i64, vp, vp, i32, vp, i32, vp, i32, vp, vp, vp, sz, vp],
+                            i32),
         "hog_pipeline_create": ([vp, vp, vp, vp, vp, i32], i32),
         "hog_pipeline_submit": ([vp, vp, i32, i64], i32),
         "hog_pipeline_drain": ([vp], i32),
@@ -599,6 +601,23 @@ def topk_windows(frames: torch.Tensor, W, b, k: int = 10, upsample: int = 1, ws=
     wp, wn = _ws(ws, grad_workspace_bytes(h, w, upsample, n, nf, 1))
     _check(lib().hog_topk_windows(_fptr(frames), n, h, w, pitch, stride, upsample, _ptr(W), _ptr(b), nf, k,
                                   _ptr(win), _ptr(sc), wp, wn, _stream()), "hog_topk_windows")
+    return win, sc
+
+
+def detect_topk_into(frames: torch.Tensor, W, b, dets: torch.Tensor, n_dets: torch.Tensor, k: int = 10,
+                     thresh: float = 0.0, iou: float = 0.5, upsample: int = 1, ws=None):
+    """hog_detect_topk: detections into dets / n_dets and the k best windows
+    of every frame, from one forward pass.  Returns (windows int32 [n][k][5],
+    scores float32 [n][k])."""
+    n, h, w, pitch, stride = _frames_args(frames)
+    nf = int(W.shape[0])
+    win = torch.empty((n, k, 5), dtype=torch.int32, device=frames.device)
+    sc = torch.empty((n, k), dtype=torch.float32, device=frames.device)
+    prm = _params(thresh, iou, upsample)
+    wp, wn = _ws(ws, grad_workspace_bytes(h, w, upsample, n, nf, 1))
+    _check(lib().hog_detect_topk(ctypes.byref(prm), _fptr(frames), n, h, w, pitch, stride, _ptr(W), _ptr(b), nf,
+                                 _ptr(dets), int(dets.shape[1]), _ptr(n_dets), k, _ptr(win), _ptr(sc), wp, wn,
+                                 _stream()), "hog_detect_topk")
     return win, sc
 
 
