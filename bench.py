@@ -452,9 +452,14 @@ def batched_leg(hog355, frames, Wt, bt, args, kw=None):
             "kern_staged": kern_staged, "staged": staged, "ksteps": ksteps}
 
 
-def plain_leg(hog355, frames, Wt, bt, n_frames):
-    """One frame per call, submit to completion, on the clip's frames."""
+def plain_leg(hog355, frames, Wt, bt, n_frames, autotune=True):
+    """One frame per call, submit to completion, on the clip's frames, under
+    the schedule the autotuner picks for one frame (NMS rounds, scoring
+    rows)."""
     import torch
+    tuning = None
+    if autotune:
+        tuning, _ = hog355.autotune(frames[:1], Wt, bt, reps=20)
     ws = hog355.Workspace()
     one = frames[0]
     for _ in range(20):
@@ -473,7 +478,7 @@ def plain_leg(hog355, frames, Wt, bt, n_frames):
     return {"fps": round(n_frames / max(plain_dt, 1e-9), 1),
             "p50_ms": round(float(np.percentile(plain_lat, 50)), 4),
             "p99_ms": round(float(np.percentile(plain_lat, 99)), 4),
-            "latency": "one frame per call, submit to completion"}
+            "latency": "one frame per call, submit to completion", "tuning": tuning}
 
 
 def main():
@@ -586,7 +591,7 @@ def main():
             "roofline_path": path,
         })
     if args.plain_frames > 0:
-        out["plain"] = plain_leg(hog355, frames, Wt, bt, args.plain_frames)
+        out["plain"] = plain_leg(hog355, frames, Wt, bt, args.plain_frames, autotune=args.schedule == "auto")
     if not args.no_options and not args.no_batched:
         out["options"] = options_leg(hog355, frames, Wt, bt, bl["tuning"], min(args.steps, 200), args.warmup,
                                      min(args.steps, args.kernel_steps))

@@ -62,23 +62,26 @@ struct hog_pipeline {
 
 namespace {
 
+// Frees what create allocated (teardown: errors are not actionable here).
 void release(hog_pipeline* p) {
     for (Stage& s : p->stages) {
-        if (s.done) hipEventDestroy(s.done);
-        if (s.stream) hipStreamDestroy(s.stream);
-        if (s.h_frames) hipHostFree(s.h_frames);
-        if (s.h_dets) hipHostFree(s.h_dets);
-        if (s.h_n) hipHostFree(s.h_n);
-        if (s.d_frames) hipFree(s.d_frames);
-        if (s.ws) hipFree(s.ws);
-        if (s.d_dets) hipFree(s.d_dets);
-        if (s.d_n) hipFree(s.d_n);
+        if (s.done) (void)hipEventDestroy(s.done);
+        if (s.stream) (void)hipStreamDestroy(s.stream);
+        if (s.h_frames) (void)hipHostFree(s.h_frames);
+        if (s.h_dets) (void)hipHostFree(s.h_dets);
+        if (s.h_n) (void)hipHostFree(s.h_n);
+        if (s.d_frames) (void)hipFree(s.d_frames);
+        if (s.ws) (void)hipFree(s.ws);
+        if (s.d_dets) (void)hipFree(s.d_dets);
+        if (s.d_n) (void)hipFree(s.d_n);
     }
     p->stages.clear();
 }
 
 void consumer_loop(hog_pipeline* p) {
-    hipSetDevice(p->device);
+    // the pipeline's device for this thread's HIP calls (a failure shows up
+    // as an error of the event wait below)
+    (void)hipSetDevice(p->device);
     for (;;) {
         int idx;
         {
