@@ -376,6 +376,13 @@ int hog_level_maps(const uint8_t* frame, int h, int w, int pitch, int upsample, 
                    float* level_px, uint8_t* bins, float* hist,
                    void* ws, size_t ws_bytes, void* stream);
 
+/* The windows of `level` (of an h x w frame's pyramid) that a search region
+ * lets through, as the kernels compute them (test entry point): range4 =
+ * {r_lo, r_hi, c_lo, c_hi}, the anchor rows and columns whose boxes lie
+ * inside the region's rectangle; empty when r_lo > r_hi or c_lo > c_hi, or
+ * when the level is outside [k_lo, k_hi].  Host only. */
+int hog_region_windows(int h, int w, int upsample, int level, const hog_region* region, int32_t* range4);
+
 /* The orientation decision alone (test entry point): bins[i] for the
  * integer gradient (gx[i], gy[i]) in units of 2^-16 (|gx|, |gy| < 2^24),
  * n <= 2^31 - 1.  Sec. IV-A: one of eighteen signed directions. */

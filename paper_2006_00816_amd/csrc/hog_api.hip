@@ -10,7 +10,7 @@
 #include <string>
 #include <vector>
 
-#include "hog_internal.h"
+#include "hog_device.h"
 
 using namespace hog;
 
@@ -913,6 +913,19 @@ int hog_track_regions(const hog_det* dets, const int* n_dets, int n, int cap, in
     return timed("track", (hipStream_t)stream, [&] {
         return launch_track(dets, n_dets, n, cap, h, w, margin, span, regions, (hipStream_t)stream);
     });
+}
+
+int hog_region_windows(int h, int w, int upsample, int level, const hog_region* region, int32_t* range4) {
+    if (!region || !range4) return HOG_E_INVAL;
+    Plan P;
+    HOG_TRY(make_plan(h, w, upsample, 1, 0, &P));
+    if (level < 0 || level >= P.T.n) return HOG_E_INVAL;
+    const RegionRange R = region_range(P.T.L[level], level, *region);
+    range4[0] = R.r_lo;
+    range4[1] = R.r_hi;
+    range4[2] = R.c_lo;
+    range4[3] = R.c_hi;
+    return HOG_OK;
 }
 
 int hog_init(void) {

@@ -35,6 +35,16 @@ ALL_LEVELS = 1 << 30
 CASCADE = 0x100   # recursive pyramid, or-ed into upsample
 
 
+def region_windows(h: int, w: int, upsample: int, level: int, region):
+    """(r_lo, r_hi, c_lo, c_hi): the anchors of `level` whose windows a
+    search region (x0, y0, x1, y1, k_lo, k_hi) lets through, as the kernels
+    compute them (host)."""
+    reg = (ctypes.c_int32 * 6)(*[int(v) for v in region])
+    out = (ctypes.c_int32 * 4)()
+    _check(lib().hog_region_windows(h, w, upsample, level, reg, out), "hog_region_windows")
+    return tuple(out)
+
+
 def region_tensor(regions, device="cuda"):
     """Search regions as the int32 [n][6] device tensor the library reads:
     rows (x0, y0, x1, y1, k_lo, k_hi) in frame pixels (half-open) and
@@ -126,6 +136,7 @@ def lib():
         "hog_detect_batch": ([vp, vp, i32, i32, i32, i32, i64, vp, vp, i32, vp, i32, vp, vp, sz, vp], i32),
         "hog_detect_batch_static": ([vp, vp, i32, i32, i32, i32, i64, vp, vp, i32, vp, i32, vp, vp], i32),
         "hog_track_regions": ([vp, vp, i32, i32, i32, i32, i32, i32, vp, vp], i32),
+        "hog_region_windows": ([i32, i32, i32, i32, vp, vp], i32),
         "hog_detect_topk": ([vp, vp, i32, i32, i32, i32, i64, vp, vp, i32, vp, i32, vp, i32, vp, vp, vp, sz, vp],
                             i32),
         "hog_pipeline_create": ([vp, vp, vp, vp, vp, i32], i32),

@@ -181,6 +181,28 @@ def test_pipeline_config_checked_before_any_allocation(L):
     assert L.hog_pipeline_submit(None, v(1), 1, 0) == -1 and L.hog_pipeline_drain(None) == -1
 
 
+@pytest.mark.parametrize("h,w,u", [(480, 640, 1), (97, 331, 1), (240, 320, 2), (1080, 1920, 2)])
+def test_region_windows_match_oracle(L, h, w, u):
+    """The anchor ranges the kernels derive from a search region select
+    exactly the windows whose boxes the oracle finds inside it (random
+    regions, also partly or wholly outside the frame and empty ones)."""
+    from paper_2006_00816_amd import hog355
+    rng = np.random.default_rng(h + w + u)
+    levels = oracle.pyramid(h, w, u)
+    for _ in range(60):
+        x0, x1 = sorted(rng.integers(-60, w + 60, 2))
+        y0, y1 = sorted(rng.integers(-60, h + 60, 2))
+        if rng.random() < 0.2:
+            x0, x1 = x1, x0
+        reg = (int(x0), int(y0), int(x1), int(y1), int(rng.integers(0, 3)), int(rng.integers(1, 30)))
+        for lv in levels[:: max(1, len(levels) // 4)]:
+            r_lo, r_hi, c_lo, c_hi = hog355.region_windows(h, w, u, lv.k, reg)
+            rr, cc = np.meshgrid(np.arange(lv.rows), np.arange(lv.cols), indexing="ij")
+            want = oracle.window_in_region(lv, rr, cc, reg)
+            got = (rr >= r_lo) & (rr <= r_hi) & (cc >= c_lo) & (cc <= c_hi)
+            assert np.array_equal(got, want), (reg, lv.k, (r_lo, r_hi, c_lo, c_hi))
+
+
 def test_level_table_limits(L):
     from paper_2006_00816_amd import hog355
     lv = hog355.pyramid(4096, 4096, 2, 32)
