@@ -398,7 +398,7 @@ def batched_leg(hog355, frames, Wt, bt, args, kw=None):
     steps of that schedule."""
     import torch
     staged = {"fused": 0, "queues": 8, "wg_per_queue": 32, "lag_f": 1, "lag_s": 2, "split": 1, "nms_rounds": 3,
-              "score_rows": 0}
+              "score_rows": 0, "stagger": 0}
     fused = {**staged, "fused": 1}
     tune_ms = None
     if args.schedule == "auto":

@@ -339,6 +339,9 @@ typedef struct hog_tuning {
     int32_t split;
     int32_t nms_rounds;
     int32_t score_rows;
+    int32_t stagger;   /* split schedules: 0 the groups start together; 1 group j starts once
+                          group j - 1 has its histograms, 2 once it has its scores, so that one
+                          group's NMS runs beside the next group's histograms and scores */
 } hog_tuning;
 
 /* The schedule in effect for a shape: the one set by hog_tuning_set or
@@ -355,8 +358,9 @@ int hog_tuning_set(int h, int w, int upsample, int n, int nf, const hog_tuning* 
  * HIP events on `stream`), keeps the fastest for this shape as with
  * hog_tuning_set and returns it in `best` with its mean time per call in
  * `best_ms`.  Arguments as hog_detect_batch; blocks the host until done.
- * The candidates: the per-stage schedule with split 1, 2 and 4, 2, 3, 4,
- * 6, 8 or 12 NMS rounds and scoring items of 4 or 16 rows, and the fused
+ * The candidates: the per-stage schedule with split 1, 2 and 4 (staggered
+ * 0, 1 or 2 when split), 2, 3, 4, 6, 8 or 12 NMS rounds and scoring items
+ * of 4 or 16 rows, and the fused
  * kernel with 8 or 1 queues, one workgroup per compute unit, and
  * lags (1,2), (1,3), (2,3), (2,4); a candidate that reports an error in
  * any n_dets entry is skipped. */

@@ -363,6 +363,7 @@ bool tuning_valid(const hog_tuning& t) {
     if (t.split < 1 || t.split > MAX_SPLIT) return false;
     if (t.nms_rounds < 0 || t.nms_rounds > MAX_NMS_ROUNDS) return false;
     if (t.score_rows != 0 && t.score_rows != SCORE_SMALL_ROWS && t.score_rows != ROWS_PER_ITEM) return false;
+    if (t.stagger < 0 || t.stagger > 2 || (t.stagger && t.fused)) return false;
     if (t.fused == 0) return true;
     return t.fused == 1 && t.split == 1 && t.queues >= 1 && t.queues <= FUSED_MAX_QUEUES && t.wg_per_queue >= 1 &&
            t.wg_per_queue <= 65536 && t.lag_f >= 1 && t.lag_s > t.lag_f && t.lag_s <= 64;
@@ -379,6 +380,7 @@ hog_tuning default_tuning(int, int, int, int n, int) {
     t.lag_f = 1;
     t.lag_s = 2;
     t.split = 1;
+    t.stagger = 0;
     return t;
 }
 
@@ -436,6 +438,7 @@ struct SplitRes {
     bool ready = false;
     hipStream_t st[MAX_SPLIT - 1] = {};
     hipEvent_t ev[MAX_SPLIT] = {};
+    hipEvent_t stage[MAX_SPLIT] = {};   // a group's histograms (or scores) done: the next group may start
 };
 thread_local SplitRes g_split[MAX_DEVICES];
 
@@ -448,7 +451,9 @@ int init_split_resources() {
     for (int j = 0; j < MAX_SPLIT - 1; ++j)
         if (hipStreamCreateWithFlags(&r.st[j], hipStreamNonBlocking) != hipSuccess) return HOG_E_HIP;
     for (int j = 0; j < MAX_SPLIT; ++j)
-        if (hipEventCreateWithFlags(&r.ev[j], hipEventDisableTiming) != hipSuccess) return HOG_E_HIP;
+        if (hipEventCreateWithFlags(&r.ev[j], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&r.stage[j], hipEventDisableTiming) != hipSuccess)
+            return HOG_E_HIP;
     r.ready = true;
     return HOG_OK;
 }
@@ -512,16 +517,21 @@ int score_stage(const Plan& P, int m, const float* feat, const Bank& bank, float
     });
 }
 
-// histograms -> features -> scores -> NMS for frames lo .. lo + m - 1
+// histograms -> features -> scores -> NMS for frames lo .. lo + m - 1.
+// `mark` (if any) is recorded after the histograms (stagger 1) or after
+// the scores (stagger 2), for the next group of a staggered split.
 int staged_chain(const Plan& P, int m, const FrameBufs& b, long long fstride, int pitch, const hog_params* prm,
-                 const Bank& bank, int cap, int rounds, int score_rows, void* ws, hipStream_t s) {
+                 const Bank& bank, int cap, int rounds, int score_rows, void* ws, hipStream_t s,
+                 hipEvent_t mark = nullptr, int stagger = 0) {
     const LevelTable& T = P.T;
     HOG_TRY(run_cascade(P, m, b.frames, fstride, pitch, b.casc, s));
     HOG_TRY(timed("hist", s, [&] {
         return launch_hist(T, b.frames, fstride, pitch, m, at<int4>(ws, P.o_taps), b.hist, b.regions, b.casc, s);
     }));
+    if (mark && stagger == 1 && hipEventRecord(mark, s) != hipSuccess) return HOG_E_HIP;
     HOG_TRY(timed("feat", s, [&] { return launch_feat(T, m, b.hist, b.feat, nullptr, s); }));
     HOG_TRY(score_stage(P, m, b.feat, bank, prm->thresh, nullptr, b.keys, score_rows, ws, s, b.regions));
+    if (mark && stagger == 2 && hipEventRecord(mark, s) != hipSuccess) return HOG_E_HIP;
     return nms_chain(P, m, b, prm, cap, nullptr, rounds, ws, s);
 }
 
@@ -585,11 +595,19 @@ int detect_sequence(const Plan& P, const hog_params* prm, const uint8_t* frames,
     if (hipEventRecord(r->ev[0], s) != hipSuccess) return HOG_E_HIP;
     for (int j = 1; j < parts; ++j)
         if (hipStreamWaitEvent(r->st[j - 1], r->ev[0], 0) != hipSuccess) return HOG_E_HIP;
+    // staggered: group j starts once group j - 1 has its histograms (or
+    // scores), so that the groups are in different stages at a time and a
+    // group's latency-bound NMS runs beside the next group's compute
+    const int stagger = tune.stagger;
     int st = HOG_OK;
     for (int j = 0; j < parts && st == HOG_OK; ++j) {
         const int lo = (int)((long long)j * P.n / parts), hi = (int)((long long)(j + 1) * P.n / parts);
-        st = staged_chain(P, hi - lo, frame_bufs(P, ws, frames, fstride, dets, cap, n_dets, lo, regions), fstride,
-                          pitch, prm, bank, cap, tune.nms_rounds, tune.score_rows, ws, j == 0 ? s : r->st[j - 1]);
+        hipStream_t sj = j == 0 ? s : r->st[j - 1];
+        if (stagger && j > 0 && hipStreamWaitEvent(sj, r->stage[j - 1], 0) != hipSuccess) st = HOG_E_HIP;
+        if (st == HOG_OK)
+            st = staged_chain(P, hi - lo, frame_bufs(P, ws, frames, fstride, dets, cap, n_dets, lo, regions), fstride,
+                              pitch, prm, bank, cap, tune.nms_rounds, tune.score_rows, ws, sj,
+                              stagger && j + 1 < parts ? r->stage[j] : nullptr, stagger);
     }
     // join (also after an error, so that no forked stream is left behind a capture)
     for (int j = 1; j < parts; ++j) {
@@ -961,12 +979,15 @@ int hog_autotune(const hog_params* prm, const uint8_t* frames, int n, int h, int
     std::vector<hog_tuning> cand;
     for (int sp : {1, 2, 4}) {
         if (sp > n) break;
-        for (int nr : {2, 3, 4, 6, 8, 12}) {
-            for (int rows : {SCORE_SMALL_ROWS, ROWS_PER_ITEM}) {
-                cand.push_back(default_tuning(h, w, prm->upsample, n, nf));
-                cand.back().split = sp;
-                cand.back().nms_rounds = nr;
-                cand.back().score_rows = rows;
+        for (int sg = 0; sg <= (sp > 1 ? 2 : 0); ++sg) {
+            for (int nr : {2, 3, 4, 6, 8, 12}) {
+                for (int rows : {SCORE_SMALL_ROWS, ROWS_PER_ITEM}) {
+                    cand.push_back(default_tuning(h, w, prm->upsample, n, nf));
+                    cand.back().split = sp;
+                    cand.back().stagger = sg;
+                    cand.back().nms_rounds = nr;
+                    cand.back().score_rows = rows;
+                }
             }
         }
     }

@@ -56,7 +56,7 @@ def region_tensor(regions, device="cuda"):
 class hog_tuning(ctypes.Structure):
     _fields_ = [("fused", ctypes.c_int32), ("queues", ctypes.c_int32), ("wg_per_queue", ctypes.c_int32),
                 ("lag_f", ctypes.c_int32), ("lag_s", ctypes.c_int32), ("split", ctypes.c_int32),
-                ("nms_rounds", ctypes.c_int32), ("score_rows", ctypes.c_int32)]
+                ("nms_rounds", ctypes.c_int32), ("score_rows", ctypes.c_int32), ("stagger", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -433,7 +433,8 @@ def tuning_set(h: int, w: int, upsample: int, n: int, nf: int, t: dict | None):
     if t is None:
         _check(lib().hog_tuning_set(h, w, upsample, n, nf, None), "hog_tuning_set")
         return
-    tt = hog_tuning(**{"split": 1, "nms_rounds": 3, "score_rows": 0, **{k: int(v) for k, v in t.items()}})
+    tt = hog_tuning(**{"split": 1, "nms_rounds": 3, "score_rows": 0, "stagger": 0,
+                       **{k: int(v) for k, v in t.items()}})
     _check(lib().hog_tuning_set(h, w, upsample, n, nf, ctypes.byref(tt)), "hog_tuning_set")
 
 

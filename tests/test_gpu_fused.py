@@ -81,18 +81,20 @@ def test_split_rounds_rows_equal_staged(H, split, n, rounds, rows):
     _assert_same(got, ref, n)
 
 
-@pytest.mark.parametrize("split", [2, 4])
-def test_split_clip_64_frames_numbered(H, split):
+@pytest.mark.parametrize("split,stagger", [(2, 0), (4, 0), (2, 1), (4, 1), (2, 2), (3, 2)])
+def test_split_clip_64_frames_numbered(H, split, stagger):
     """The 64-frame 640x480 clip under split schedules (frame groups on
-    forked streams, eager and graph-replayed): every field of every
-    detection equals the single-group schedule's, frame index included."""
+    forked streams, starting together or staggered after the previous
+    group's histograms or scores; eager and graph-replayed): every field of
+    every detection equals the single-group schedule's, frame index
+    included."""
     wl = synth.config1(seed=1, n=64)
     fr, W, b = cu(wl.frames), cu(wl.W), cu(wl.b)
-    print(f"split={split} n=64", flush=True)
+    print(f"split={split} stagger={stagger} n=64", flush=True)
     ref = _run(H, fr, W, b, STAGED)
-    got = _run(H, fr, W, b, {**STAGED, "split": split})
+    got = _run(H, fr, W, b, {**STAGED, "split": split, "stagger": stagger})
     _assert_same(got, ref, 64)
-    H.tuning_set(480, 640, 1, 64, 5, {**STAGED, "split": split})
+    H.tuning_set(480, 640, 1, 64, 5, {**STAGED, "split": split, "stagger": stagger})
     try:
         g = H.DetectGraph(fr, W, b)
         g.launch()

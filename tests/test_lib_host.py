@@ -215,7 +215,8 @@ def test_tuning_table_roundtrip_and_validation(L):
     shape = (123, 321, 1, 5, 3)
     t, found = hog355.tuning_get(*shape)
     assert not found and t["fused"] == 0
-    want = {"fused": 1, "queues": 8, "wg_per_queue": 32, "lag_f": 1, "lag_s": 3, "split": 1, "nms_rounds": 3, "score_rows": 0}
+    want = {"fused": 1, "queues": 8, "wg_per_queue": 32, "lag_f": 1, "lag_s": 3, "split": 1, "nms_rounds": 3,
+            "score_rows": 0, "stagger": 0}
     hog355.tuning_set(*shape, want)
     got, found = hog355.tuning_get(*shape)
     assert found and got == want
@@ -225,7 +226,8 @@ def test_tuning_table_roundtrip_and_validation(L):
                 {**want, "wg_per_queue": 0}, {**want, "fused": 2}, {**want, "split": 2},
                 {**want, "fused": 0, "split": 0}, {**want, "fused": 0, "split": 5},
                 {**want, "fused": 0, "nms_rounds": -1}, {**want, "fused": 0, "nms_rounds": 17},
-                {**want, "fused": 0, "score_rows": 8}):
+                {**want, "fused": 0, "score_rows": 8}, {**want, "stagger": 1}, {**want, "fused": 0, "stagger": 3},
+                {**want, "fused": 0, "stagger": -1}):
         with pytest.raises(hog355.HogError):
             hog355.tuning_set(*shape, bad)
     assert hog355.tuning_get(*shape)[0] == want
