@@ -334,8 +334,8 @@ int run_pixels(const Plan& P, const uint8_t* frames, long long fstride, int pitc
     }));
     HOG_TRY(run_cascade(P, P.n, frames, fstride, pitch, at<uint8_t>(ws, P.o_casc), s));
     HOG_TRY(timed("hist", s, [&] {
-        return launch_hist(T, frames, fstride, pitch, P.n, at<int4>(ws, P.o_taps), at<float>(ws, P.o_hist),
-                           nullptr, at<uint8_t>(ws, P.o_casc), s);
+        return launch_hist(T, frames, fstride, pitch, P.n, at<float>(ws, P.o_hist), nullptr, at<uint8_t>(ws, P.o_casc),
+                           s);
     }));
     HOG_TRY(timed("feat", s, [&] {
         return launch_feat(T, P.n, at<float>(ws, P.o_hist), at<float>(ws, P.o_feat), packed, s);
@@ -526,7 +526,7 @@ int staged_chain(const Plan& P, int m, const FrameBufs& b, long long fstride, in
     const LevelTable& T = P.T;
     HOG_TRY(run_cascade(P, m, b.frames, fstride, pitch, b.casc, s));
     HOG_TRY(timed("hist", s, [&] {
-        return launch_hist(T, b.frames, fstride, pitch, m, at<int4>(ws, P.o_taps), b.hist, b.regions, b.casc, s);
+        return launch_hist(T, b.frames, fstride, pitch, m, b.hist, b.regions, b.casc, s);
     }));
     if (mark && stagger == 1 && hipEventRecord(mark, s) != hipSuccess) return HOG_E_HIP;
     HOG_TRY(timed("feat", s, [&] { return launch_feat(T, m, b.hist, b.feat, nullptr, s); }));
@@ -568,8 +568,8 @@ int detect_sequence(const Plan& P, const hog_params* prm, const uint8_t* frames,
         cfg.lag_f = tune.lag_f;
         cfg.lag_s = tune.lag_s;
         HOG_TRY(timed("fused", s, [&] {
-            return launch_fused(T, P.n, cfg, frames, fstride, pitch, at<int4>(ws, P.o_taps), at<float>(ws, P.o_hist),
-                                at<float>(ws, P.o_feat), at<float4>(ws, P.o_bpack), bias, P.nf, prm->thresh,
+            return launch_fused(T, P.n, cfg, frames, fstride, pitch, at<float>(ws, P.o_hist), at<float>(ws, P.o_feat),
+                                at<float4>(ws, P.o_bpack), bias, P.nf, prm->thresh,
                                 at<unsigned long long>(ws, P.o_key), multi, sync, s);
         }));
         return nms_chain(P, P.n, frame_bufs(P, ws, frames, fstride, dets, cap, n_dets, 0), prm, cap, sync,
@@ -1073,8 +1073,7 @@ int hog_level_maps(const uint8_t* frame, int h, int w, int pitch, int upsample, 
     }
     if (hist) {
         HOG_TRY(timed("hist", s, [&] {
-            return launch_hist(T, frame, 0, pitch, 1, at<int4>(ws, P.o_taps), at<float>(ws, P.o_hist), nullptr, casc,
-                               s);
+            return launch_hist(T, frame, 0, pitch, 1, at<float>(ws, P.o_hist), nullptr, casc, s);
         }));
         const DevLevel& L = T.L[level];
         const float* src = at<float>(ws, P.o_hist) + (size_t)L.hist_off * HSTRIDE;

@@ -127,6 +127,13 @@ static __device__ inline int4 axis_tap(int i, int n_in, long long sig) {
     return make_int4(i0, i1, a, 0);
 }
 
+// Tap i of a level axis with n_level samples: from the frame axis of
+// n_src samples at the level's inverse scale, or the identity for a level
+// image of the recursive pyramid (read as is).
+static __device__ inline int4 level_tap(const DevLevel& L, int i, int n_level, int n_src) {
+    return L.src ? make_int4(i, min(i + 1, n_level - 1), 0, 0) : axis_tap(i, n_src, L.sig);
+}
+
 // Orders a wave's LDS accesses on either side (LDS operations of one wave
 // execute in program order; this keeps the compiler from moving them).
 __device__ __forceinline__ void wave_lds_order() {

@@ -150,8 +150,7 @@ hipError_t launch_setup(const LevelTable& T, int4* taps, int2* boxes,
                         unsigned long long* poskey_zero, long long poskey_count, unsigned* sync_zero,
                         int sync_count, hipStream_t s);
 hipError_t launch_hist(const LevelTable& T, const uint8_t* frames, long long fstride, int pitch,
-                       int n, const int4* taps, float* hist, const hog_region* regions, const uint8_t* casc,
-                       hipStream_t s);
+                       int n, float* hist, const hog_region* regions, const uint8_t* casc, hipStream_t s);
 // One level of the recursive pyramid for n frames: the 8-bit image
 // [h_out][w_out] at dst_off of each frame's block of `casc`, scaled down by
 // 5/6 from the level image [h_in][w_in] at src_off (src_off < 0: the frame
@@ -168,9 +167,8 @@ struct FusedNeed {
 };
 FusedNeed fused_need(const LevelTable& T, int nf);
 hipError_t launch_fused(const LevelTable& T, int n, const FusedCfg& cfg, const uint8_t* frames, long long fstride,
-                        int pitch, const int4* taps, float* hist, float* feat, const float4* bpack,
-                        const float* bias, int nf, float thresh, unsigned long long* poskey, bool atomic_key,
-                        unsigned* sync, hipStream_t s);
+                        int pitch, float* hist, float* feat, const float4* bpack, const float* bias, int nf,
+                        float thresh, unsigned long long* poskey, bool atomic_key, unsigned* sync, hipStream_t s);
 int score_rows_auto(const LevelTable& T, int n, int nf, int cus);
 int sep_rows_auto(const LevelTable& T, int n, int nf, int cus);
 hipError_t launch_score(const LevelTable& T, int n, const float* feat, const float4* bpack,

@@ -79,7 +79,7 @@ __device__ __forceinline__ unsigned xcc_id() {
 template <bool LOCAL>
 __global__ __launch_bounds__(SCORE_THREADS) void hog_fused_kernel(
     LevelTable T, int n, int groups, int Q, int lag_f, int lag_s, const uint8_t* __restrict__ frames,
-    long long fstride, int pitch, const int4* __restrict__ taps, float* __restrict__ hist, float* __restrict__ feat,
+    long long fstride, int pitch, float* __restrict__ hist, float* __restrict__ feat,
     const float4* __restrict__ bpack, const float* __restrict__ bias, int nf, float thresh,
     unsigned long long* __restrict__ poskey, int atomic_key, unsigned* __restrict__ sync, unsigned spin_limit) {
     __shared__ FusedSmem sm;
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(SCORE_THREADS) void hog_fused_kernel(
             const int frame = q + Q * jf;
             int tile = 2 * (o - nS - nF) + (tid >> 9);
             if (tile >= T.th_total) tile = -1;
-            hist_tile(T, frames, fstride, pitch, taps, hist, frame, tile, tid & 511, sm.hist[tid >> 9]);
+            hist_tile(T, frames, fstride, pitch, hist, frame, tile, tid & 511, sm.hist[tid >> 9]);
             wave_done<LOCAL>(hdone + frame, tid);
         }
     }
@@ -150,9 +150,8 @@ FusedNeed fused_need(const LevelTable& T, int nf) {
 }
 
 hipError_t launch_fused(const LevelTable& T, int n, const FusedCfg& cfg, const uint8_t* frames, long long fstride,
-                        int pitch, const int4* taps, float* hist, float* feat, const float4* bpack,
-                        const float* bias, int nf, float thresh, unsigned long long* poskey, bool atomic_key,
-                        unsigned* sync, hipStream_t s) {
+                        int pitch, float* hist, float* feat, const float4* bpack, const float* bias, int nf,
+                        float thresh, unsigned long long* poskey, bool atomic_key, unsigned* sync, hipStream_t s) {
     const int groups = (nf + FGROUP - 1) / FGROUP;
     if (cfg.queues < 1 || cfg.queues > FUSED_MAX_QUEUES || cfg.lag_f < 1 || cfg.lag_s <= cfg.lag_f ||
         cfg.wg_per_queue < 1)
@@ -162,11 +161,11 @@ hipError_t launch_fused(const LevelTable& T, int n, const FusedCfg& cfg, const u
     const int blocks = cfg.queues * cfg.wg_per_queue;
     if (cfg.queues == FUSED_MAX_QUEUES)
         hipLaunchKernelGGL(hog_fused_kernel<true>, dim3(blocks), dim3(SCORE_THREADS), 0, s, T, n, groups, cfg.queues,
-                           cfg.lag_f, cfg.lag_s, frames, fstride, pitch, taps, hist, feat, bpack, bias, nf, thresh,
+                           cfg.lag_f, cfg.lag_s, frames, fstride, pitch, hist, feat, bpack, bias, nf, thresh,
                            poskey, atomic_key ? 1 : 0, sync, (unsigned)FUSED_SPIN_LIMIT);
     else
         hipLaunchKernelGGL(hog_fused_kernel<false>, dim3(blocks), dim3(SCORE_THREADS), 0, s, T, n, groups,
-                           cfg.queues, cfg.lag_f, cfg.lag_s, frames, fstride, pitch, taps, hist, feat, bpack, bias, nf,
+                           cfg.queues, cfg.lag_f, cfg.lag_s, frames, fstride, pitch, hist, feat, bpack, bias, nf,
                            thresh, poskey, atomic_key ? 1 : 0, sync, (unsigned)FUSED_SPIN_LIMIT);
     return hipGetLastError();
 }

@@ -30,8 +30,7 @@ __device__ __forceinline__ bool hist_tile_needed(const LevelTable& T, int tile, 
 // every XCD fetching every frame.
 __global__ __launch_bounds__(HIST_THREADS) void hog_hist_kernel(
     LevelTable T, int n, const uint8_t* __restrict__ frames, long long fstride, int pitch,
-    const int4* __restrict__ taps, float* __restrict__ hist, const hog_region* __restrict__ regions,
-    const uint8_t* __restrict__ casc) {
+    float* __restrict__ hist, const hog_region* __restrict__ regions, const uint8_t* __restrict__ casc) {
     __shared__ HistSmem sm;
     const long long items = (long long)T.th_total * n;
     const int x = (int)(blockIdx.x & 7);
@@ -42,18 +41,17 @@ __global__ __launch_bounds__(HIST_THREADS) void hog_hist_kernel(
     const int tile = (int)(item - (long long)frame * T.th_total);
     // the whole workgroup leaves together, before any barrier
     if (regions && !hist_tile_needed(T, tile, regions[frame])) return;
-    hist_tile(T, frames, fstride, pitch, taps, hist, frame, tile, (int)threadIdx.x, sm, casc);
+    hist_tile(T, frames, fstride, pitch, hist, frame, tile, (int)threadIdx.x, sm, casc);
 }
 
 hipError_t launch_hist(const LevelTable& T, const uint8_t* frames, long long fstride, int pitch, int n,
-                       const int4* taps, float* hist, const hog_region* regions, const uint8_t* casc,
-                       hipStream_t s) {
+                       float* hist, const hog_region* regions, const uint8_t* casc, hipStream_t s) {
     const long long items = (long long)T.th_total * n;
     if (items <= 0) return hipSuccess;
     const long long per_xcd = (items + 7) / 8;
     if (per_xcd * 8 > 0x7fffffffLL) return hipErrorInvalidValue;
     hipLaunchKernelGGL(hog_hist_kernel, dim3((unsigned)(per_xcd * 8)), dim3(HIST_THREADS), 0, s, T, n, frames,
-                       fstride, pitch, taps, hist, regions, casc);
+                       fstride, pitch, hist, regions, casc);
     return hipGetLastError();
 }
 

@@ -30,12 +30,12 @@ __global__ __launch_bounds__(256) void hog_setup_kernel(
                 // a level image of the recursive pyramid is read as is
                 if (e >= L.tap_y && e < L.tap_y + L.h) {
                     const int i = (int)(e - L.tap_y);
-                    taps[e] = L.src ? make_int4(i, min(i + 1, L.h - 1), 0, 0) : axis_tap(i, T.h, L.sig);
+                    taps[e] = level_tap(L, i, L.h, T.h);
                     return;
                 }
                 if (e >= L.tap_x && e < L.tap_x + L.w) {
                     const int i = (int)(e - L.tap_x);
-                    taps[e] = L.src ? make_int4(i, min(i + 1, L.w - 1), 0, 0) : axis_tap(i, T.w, L.sig);
+                    taps[e] = level_tap(L, i, L.w, T.w);
                     return;
                 }
             }

@@ -19,7 +19,8 @@ constexpr int CS = NBINS + 1;                     // u64 words per local cell (o
 
 // LDS of one histogram tile (64 KB).
 struct HistSmem {
-    int4 Ty[TPY], Tx[TPX];                        // row / column taps of the tile
+    int4 Ty[TPY], Tx[TPX];                        // row / column taps of the tile (see resample_tile)
+    int Row[TPY];                                 // swizzled offset of each tile row
     unsigned long long H[LC_H * LC_W * CS];       // fixed-point cell histograms (see quad_votes)
     int V[64 * PLANE];                            // swizzled level pixels (value * 2^16)
 };
@@ -90,51 +91,85 @@ __device__ __forceinline__ void quad_votes_q(int q, const int* sV, int lb, unsig
     }
 }
 
-// Level pixels of a tile from the frame, RS pixels per thread at a time
-// with all their frame loads in flight together (taps are clamped to the
-// frame, so every load is in bounds; a zero weight or a pixel outside the
-// level discards the value).  IDENT: every tap weight is zero, so only the
-// first sample is read.
+// Level pixels of a tile from the frame, exact in integers (value * 2^16).
+// Thread t takes column t mod 128 in every fourth row from row t / 128
+// (rows 0 .. 63), so a column's taps stay in registers and a row's taps
+// are one LDS broadcast; its seventeenth pixel is row 64 or 65 (row sets
+// 0, 1) or one of the 132 pixels of columns 128, 129 (row sets 2, 3).  All
+// seventeen pixels' frame loads are issued together, the histogram
+// accumulators are cleared while they are in flight, then the arithmetic
+// and the stores follow.
+//
+// Row taps a = {row 0 offset, row 1 offset, wy0, wy1}; column taps b =
+// {xs, sel, wx0, wx1}: the two column samples x0, x1 (x1 = x0 + 1, or x0
+// where the tap is clamped to the frame edge) are bytes x0 - xs and
+// x1 - xs of the 16-bit pair at xs = min(x0, w - 2) of a row, read with
+// one unaligned 16-bit load that stays inside the row; sel holds their bit
+// offsets (8 (x0 - xs) and 8 (x1 - xs), in bits 0..7 and 8..15).  Weights
+// in 1/256.  Taps outside the level carry zero weights, so such a pixel is
+// zero (its offsets are 0: every load is in bounds).  24-bit products
+// (samples < 2^8, weights <= 2^8, row sums < 2^16).  IDENT: the second
+// taps have zero weight and are not read (b.x is x0 itself); the weights
+// are 256 or 0, so the pixel is the sample times (wy0 & wx0) 2^8.
+constexpr int RS_COLS = 128, RS_SETS = HIST_THREADS / RS_COLS, RS_PX = 17;
+static_assert(RS_SETS == 4 && TPY == 66 && TPX == 130, "pixel slots below assume a 66 x 130 tile");
+
 template <bool IDENT>
-__device__ __forceinline__ void resample_tile(const int4* __restrict__ sTy, const int4* __restrict__ sTx,
-                                              const uint8_t* __restrict__ U, int* __restrict__ sV, int tid) {
-    constexpr int RS = 6;
-    for (int e0 = tid; e0 < TPY * TPX; e0 += RS * HIST_THREADS) {
-        int ty[RS], tx[RS], ay[RS], bx[RS], inside[RS];
-        int u00[RS], u01[RS], u10[RS], u11[RS];
-#pragma unroll
-        for (int r = 0; r < RS; ++r) {
-            const int e = min(e0 + r * HIST_THREADS, TPY * TPX - 1);
-            ty[r] = e / TPX;
-            tx[r] = e - ty[r] * TPX;
-            const int4 a = sTy[ty[r]], b = sTx[tx[r]];
-            ay[r] = a.z;
-            bx[r] = b.z;
-            inside[r] = (a.w | b.w) == 0;
-            u00[r] = U[(unsigned)(a.x + b.x)];
-            if (!IDENT) {
-                u01[r] = U[(unsigned)(a.x + b.y)];
-                u10[r] = U[(unsigned)(a.y + b.x)];
-                u11[r] = U[(unsigned)(a.y + b.y)];
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < RS; ++r) {
-            // 24-bit multiplies (samples < 2^8, weights <= 2^8, rows < 2^16):
-            // full-rate v_mul_u32_u24, where 32-bit products are quarter rate
-            unsigned v;
-            if (IDENT) {
-                v = (unsigned)u00[r] << 16;
-            } else {
-                const unsigned wx1 = (unsigned)bx[r], wx0 = 256u - wx1;
-                const unsigned wy1 = (unsigned)ay[r], wy0 = 256u - wy1;
-                const unsigned top = __umul24(wx0, (unsigned)u00[r]) + __umul24(wx1, (unsigned)u01[r]);
-                const unsigned bot = __umul24(wx0, (unsigned)u10[r]) + __umul24(wx1, (unsigned)u11[r]);
-                v = __umul24(wy0, top) + __umul24(wy1, bot);
-            }
-            if (e0 + r * HIST_THREADS < TPY * TPX) sV[swz(ty[r], tx[r])] = inside[r] ? (int)v : 0;
-        }
+__device__ __forceinline__ unsigned resample_value(const int4& a, const int4& b, const unsigned* u) {
+    if (IDENT) return __umul24((unsigned)(a.z & b.z) << 8, u[0]);
+    const unsigned s0 = (unsigned)b.y & 0xffu, s1 = (unsigned)b.y >> 8;
+    const unsigned top = __umul24((unsigned)b.z, __builtin_amdgcn_ubfe(u[0], s0, 8)) +
+                         __umul24((unsigned)b.w, __builtin_amdgcn_ubfe(u[0], s1, 8));
+    const unsigned bot = __umul24((unsigned)b.z, __builtin_amdgcn_ubfe(u[1], s0, 8)) +
+                         __umul24((unsigned)b.w, __builtin_amdgcn_ubfe(u[1], s1, 8));
+    return __umul24((unsigned)a.z, top) + __umul24((unsigned)a.w, bot);
+}
+
+template <bool IDENT>
+__device__ __forceinline__ void resample_load(const int4& a, const int4& b, const uint8_t* __restrict__ U,
+                                              unsigned* u) {
+    if (IDENT) {
+        u[0] = U[(unsigned)(a.x + b.x)];
+    } else {
+        unsigned short p0, p1;
+        __builtin_memcpy(&p0, U + (unsigned)(a.x + b.x), 2);
+        __builtin_memcpy(&p1, U + (unsigned)(a.y + b.x), 2);
+        u[0] = p0;
+        u[1] = p1;
     }
+}
+
+template <bool IDENT>
+__device__ __forceinline__ void resample_tile(const int4* __restrict__ sTy, const int* __restrict__ sRow,
+                                              const int4* __restrict__ sTx, const uint8_t* __restrict__ U,
+                                              int* __restrict__ sV, unsigned long long* __restrict__ sH, int tid) {
+    const int set = tid / RS_COLS, tx = tid % RS_COLS;
+    const int4 b = sTx[tx];
+    const int cp = (tx & 7) * PLANE + (tx >> 3);
+    // the seventeenth pixel
+    int ty16 = set + 64, cp16 = cp;
+    int4 b16 = b;
+    bool w16 = true;
+    if (set >= 2) {
+        const int e = tid - 2 * RS_COLS;   // 0 .. 255, pixels 0 .. 131 of columns 128, 129
+        const int ee = min(e, 2 * TPY - 1);
+        const int x = RS_COLS + (ee & 1);
+        ty16 = ee >> 1;
+        b16 = sTx[x];
+        cp16 = (x & 7) * PLANE + (x >> 3);
+        w16 = e < 2 * TPY;
+    }
+    unsigned u[RS_PX][2];
+#pragma unroll
+    for (int i = 0; i < RS_PX - 1; ++i) resample_load<IDENT>(sTy[set + RS_SETS * i], b, U, u[i]);
+    resample_load<IDENT>(sTy[ty16], b16, U, u[RS_PX - 1]);
+    for (int h = tid; h < LC_H * LC_W * CS; h += HIST_THREADS) sH[h] = 0ull;
+#pragma unroll
+    for (int i = 0; i < RS_PX - 1; ++i) {
+        const int ty = set + RS_SETS * i;
+        sV[sRow[ty] + cp] = (int)resample_value<IDENT>(sTy[ty], b, u[i]);
+    }
+    if (w16) sV[sRow[ty16] + cp16] = (int)resample_value<IDENT>(sTy[ty16], b16, u[RS_PX - 1]);
 }
 
 // One tile of TCY x TCX cells of one level of one frame, by 512 threads
@@ -155,13 +190,14 @@ __device__ __forceinline__ void resample_tile(const int4* __restrict__ sTy, cons
 // Every thread of the workgroup passes the same three barriers; tile < 0
 // only takes part in them (a workgroup running two tiles side by side).
 __device__ __forceinline__ void hist_tile(const LevelTable& T, const uint8_t* __restrict__ frames, long long fstride,
-                                          int pitch, const int4* __restrict__ taps, float* __restrict__ hist,
+                                          int pitch, float* __restrict__ hist,
                                           int frame, int tile, int tid, HistSmem& sm,
                                           const uint8_t* __restrict__ casc = nullptr) {
     int* __restrict__ sV = sm.V;
     unsigned long long* __restrict__ sH = sm.H;
     int4* __restrict__ sTy = sm.Ty;
     int4* __restrict__ sTx = sm.Tx;
+    int* __restrict__ sRow = sm.Row;
     const bool on = tile >= 0;
     const int k = on ? HOG_FIND_LEVEL(T, tile, th_off) : 0;
     const DevLevel& L = T.L[k];
@@ -180,19 +216,30 @@ __device__ __forceinline__ void hist_tile(const LevelTable& T, const uint8_t* __
     }
 
     if (on) {
-        for (int e = tid; e < LC_H * LC_W * CS; e += HIST_THREADS) sH[e] = 0ull;
+        // taps {offset 0, offset 1, weight 0, weight 1} of the tile's rows
+        // and columns, computed from the level's scale: row offsets in
+        // bytes; zero weights outside the level
         for (int e = tid; e < TPY + TPX; e += HIST_THREADS) {
             if (e < TPY) {
                 const int y = ybase + e;
-                int4 a = make_int4(0, 0, 0, -1);
+                int4 a = make_int4(0, 0, 0, 0);
                 if (y >= 0 && y < L.h) {
-                    const int4 tp = taps[L.tap_y + y];
-                    a = make_int4(tp.x * spitch, tp.y * spitch, tp.z, 0);   // row byte offsets
+                    const int4 tp = level_tap(L, y, L.h, T.h);
+                    a = make_int4(tp.x * spitch, tp.y * spitch, 256 - tp.z, tp.z);
                 }
                 sTy[e] = a;
+                sRow[e] = (e & 7) * 8 * PLANE + (e >> 3) * PL_W;
             } else {
                 const int x = xbase + e - TPY;
-                sTx[e - TPY] = (x >= 0 && x < L.w) ? taps[L.tap_x + x] : make_int4(0, 0, 0, -1);
+                int4 b = make_int4(0, 0, 0, 0);
+                if (x >= 0 && x < L.w) {
+                    const int4 tp = level_tap(L, x, L.w, T.w);
+                    // the source row's width: the level image's, or the frame's
+                    const int ws = L.src ? L.w : T.w;
+                    const int xs = L.ident ? tp.x : max(min(tp.x, ws - 2), 0);
+                    b = make_int4(xs, 8 * (tp.x - xs) | (8 * (tp.y - xs)) << 8, 256 - tp.z, tp.z);
+                }
+                sTx[e - TPY] = b;
             }
         }
     }
@@ -201,8 +248,8 @@ __device__ __forceinline__ void hist_tile(const LevelTable& T, const uint8_t* __
     // 1. resample (a level at scale 1, or a level image, is a copy of its
     // source: its taps have zero weights on the second sample)
     if (on) {
-        if (L.ident) resample_tile<true>(sTy, sTx, U, sV, tid);
-        else resample_tile<false>(sTy, sTx, U, sV, tid);
+        if (L.ident) resample_tile<true>(sTy, sRow, sTx, U, sV, sH, tid);
+        else resample_tile<false>(sTy, sRow, sTx, U, sV, sH, tid);
     }
     __syncthreads();
 
