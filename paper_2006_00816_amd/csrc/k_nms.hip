@@ -482,6 +482,7 @@ constexpr int RANK_DECIDE_MAX = 256;
 constexpr int RC_CHUNKS = 1536;
 constexpr int RC_BYTES = RC_CHUNKS * 64 + RC_MAXI * (4 + 2 + 2 + 2 + 8);
 static_assert(RC_CHUNKS * 64 >= SORT_CAP * 8, "sort buffer aliases the chunk cache");
+static_assert(SORT_CAP % NMS_THREADS == 0, "kept keys per thread in the gather");
 
 template <typename E, bool G>
 __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
@@ -742,29 +743,63 @@ __global__ __launch_bounds__(NMS_THREADS) void hog_nms_resolve_kernel(
         thr = s_prefix;
     }
 
-    // gather kept keys >= thr, pad with zeros to a power of two
+    // gather kept keys >= thr
     if (tid == 0) s_count = 0;
     __syncthreads();
-    for (int w = tid; w < nw; w += NMS_THREADS) {
-        unsigned m = kept_bits(state_word<G>(S, w));
-        while (m) {
-            const int p = 16 * w + (__builtin_ctz(m) >> 1);
-            m &= m - 1u;
-            const unsigned long long kk = keys[p];
-            if (kk < thr) continue;
-            const int slot = atomicAdd(&s_count, 1);
-            if (slot < SORT_CAP) sk[slot] = kk;
+    if (nkept <= SORT_CAP) {
+        // all kept: their positions first, then their keys, each thread's
+        // loads in flight together
+        for (int w = tid; w < nw; w += NMS_THREADS) {
+            unsigned m = kept_bits(state_word<G>(S, w));
+            if (!m) continue;
+            int slot = atomicAdd(&s_count, __popc(m));
+            while (m) {
+                sk[slot++] = (unsigned long long)(16 * w + (__builtin_ctz(m) >> 1));
+                m &= m - 1u;
+            }
+        }
+        __syncthreads();
+        constexpr int KU = SORT_CAP / NMS_THREADS;
+        unsigned long long kk[KU];
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+            const int e = tid + u * NMS_THREADS;
+            kk[u] = e < nkept ? keys[(int)sk[e]] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+            const int e = tid + u * NMS_THREADS;
+            if (e < nkept) sk[e] = kk[u];
+        }
+    } else {
+        for (int w = tid; w < nw; w += NMS_THREADS) {
+            unsigned m = kept_bits(state_word<G>(S, w));
+            while (m) {
+                const int p = 16 * w + (__builtin_ctz(m) >> 1);
+                m &= m - 1u;
+                const unsigned long long kk = keys[p];
+                if (kk < thr) continue;
+                const int slot = atomicAdd(&s_count, 1);
+                if (slot < SORT_CAP) sk[slot] = kk;
+            }
         }
     }
     __syncthreads();
     const int ng = min(s_count, SORT_CAP);
     if (ng <= NMS_THREADS) {
         // the keys are distinct, so a key's place in descending order is
-        // the number of larger keys (all threads read the same key at a
-        // time: LDS broadcasts)
+        // the number of larger keys (all threads of a wave read the same
+        // two keys at a time: LDS broadcasts; waves without a key skip)
         const unsigned long long mykey = tid < ng ? sk[tid] : 0ull;
         int rank = 0;
-        for (int i = 0; i < ng; ++i) rank += sk[i] > mykey ? 1 : 0;
+        if ((tid & ~63) < ng) {
+            const ulonglong2* __restrict__ sk2 = reinterpret_cast<const ulonglong2*>(sk);
+            for (int i = 0; i < (ng >> 1); ++i) {
+                const ulonglong2 q = sk2[i];
+                rank += (q.x > mykey ? 1 : 0) + (q.y > mykey ? 1 : 0);
+            }
+            if (ng & 1) rank += sk[ng - 1] > mykey ? 1 : 0;
+        }
         __syncthreads();
         if (tid < ng) sk[rank] = mykey;
         __syncthreads();
