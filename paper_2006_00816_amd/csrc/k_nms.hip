@@ -319,8 +319,12 @@ __global__ __launch_bounds__(256) void hog_nms_edges_split_kernel(
 // undecided candidate is dropped if a listed neighbour is kept and kept if
 // all are dropped.  Neighbour states read while other threads update them
 // can only be stale towards UNDECIDED, which delays a decision but never
-// changes it.  Candidates whose list overflowed are left to the per-frame
-// kernel.
+// changes it.  So the neighbour reads are workgroup-scope atomic loads,
+// which may be served by the compute unit's L1 cache: a state that another
+// workgroup writes during this round may be seen late, and every state
+// written before this launch is seen as written (the L1 is invalidated at
+// launch).  A frame's states are a few KB, so the gathers mostly hit L1.
+// Candidates whose list overflowed are left to the per-frame kernel.
 template <typename E>
 __global__ __launch_bounds__(256) void hog_nms_round_kernel(
     LevelTable T, const E* __restrict__ lists, unsigned char* __restrict__ state8) {
@@ -346,7 +350,7 @@ __global__ __launch_bounds__(256) void hog_nms_round_kernel(
             const int e = ch * CH + j;
             const bool in = e >= 1 && e <= cnt;
             const unsigned char w =
-                __hip_atomic_load(st + (in ? R.at(j) : (unsigned)p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_load(st + (in ? R.at(j) : (unsigned)p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             sy[j] = in ? w : (unsigned char)DROPPED;
         }
         bool kept = false, und = false;
