@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import time
 
 import numpy as np
 import torch
@@ -528,6 +529,79 @@ class DetectGraph:
             self.close()
         except Exception:
             pass
+
+
+class ClipStream:
+    """Several clips in flight: one captured DetectGraph per input buffer
+    (``frames_list``; each graph has its own workspace and outputs), launched
+    in turn on as many streams.  While one clip's per-frame NMS holds a few
+    compute units, the next clip's histograms and scores run on the others.
+    ``launch`` returns the graph just launched; its ``dets`` / ``n_dets`` are
+    valid once ``stream_of(graph)`` has completed the launch.  Refill a
+    graph's frames on its stream (or after synchronising it) before its next
+    launch."""
+
+    def __init__(self, frames_list, W=None, b=None, **kw):
+        if not frames_list:
+            raise ValueError("ClipStream needs at least one frames buffer")
+        self.graphs = [DetectGraph(f, W, b, **kw) for f in frames_list]
+        dev = frames_list[0].device
+        self.streams = [torch.cuda.Stream(device=dev) for _ in self.graphs]
+        self.next = 0
+
+    def __len__(self):
+        return len(self.graphs)
+
+    def launch(self):
+        i = self.next
+        with torch.cuda.stream(self.streams[i]):
+            self.graphs[i].launch()
+        self.next = (i + 1) % len(self.graphs)
+        return self.graphs[i]
+
+    def stream_of(self, graph):
+        return self.streams[self.graphs.index(graph)]
+
+    def synchronize(self):
+        for s in self.streams:
+            s.synchronize()
+
+    def close(self):
+        for g in self.graphs:
+            g.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tune_clip_stream(frames_list, W, b, candidates, warmup: int = 10, reps: int = 40, **kw):
+    """Time ``reps`` launches of a ClipStream over ``frames_list`` under each
+    candidate schedule (dicts for ``tuning_set``); the fastest is set for the
+    shape and returned with its ms per clip."""
+    n, h, w = (int(v) for v in frames_list[0].shape)
+    nf = int(W.shape[0])
+    up = int(kw.get("upsample", 1))
+    best, best_ms = None, float("inf")
+    for t in candidates:
+        tuning_set(h, w, up, n, nf, t)
+        cs = ClipStream(frames_list, W, b, **kw)
+        for _ in range(warmup):
+            cs.launch()
+        cs.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            cs.launch()
+        cs.synchronize()
+        ms = (time.perf_counter() - t0) / reps * 1e3
+        cs.close()
+        if ms < best_ms:
+            best, best_ms = dict(t), ms
+    tuning_set(h, w, up, n, nf, best)
+    return best, best_ms
 
 
 def level_maps(frame: torch.Tensor, level: int, upsample: int = 1, ws=None):
