@@ -438,7 +438,7 @@ def batched_leg(hog355, frames, Wt, bt, args, kw=None):
     inflight = None
     if args.schedule == "auto" and args.in_flight != 1 and not kw:
         cands = [{**staged, "split": sp, "nms_rounds": nr, "score_rows": rows}
-                 for sp in (1, 2) for nr in (3, 4) for rows in (4, 16)]
+                 for sp in (1, 2) for nr in (0, 1, 2, 3) for rows in (4, 16)]
         best = None
         for depth in ((2, 3) if args.in_flight == 0 else (args.in_flight,)):
             fl = [frames] + [frames.clone() for _ in range(depth - 1)]

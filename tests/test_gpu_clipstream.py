@@ -85,3 +85,30 @@ def test_tune_clip_stream_keeps_a_candidate(H):
     finally:
         n, h, w = (int(v) for v in fr.shape)
         H.tuning_set(h, w, 1, n, int(W.shape[0]), None)
+
+
+@pytest.mark.parametrize("rounds", [0, 3])
+def test_clip_64_in_flight_schedules(H, rounds):
+    """The 64-frame 640x480 clip, three clips in flight under the schedules
+    the benchmark's in-flight tuner chooses among (one group, 16-row
+    scoring items, 0 or 3 parallel NMS rounds): every graph's detections
+    equal those of the default schedule, bit for bit."""
+    wl = synth.config1(seed=1, n=64)
+    fr, W, b = cu(wl.frames), cu(wl.W), cu(wl.b)
+    ref, nref = H.detect_batch(fr, W, b)
+    t = {"fused": 0, "queues": 8, "wg_per_queue": 32, "lag_f": 1, "lag_s": 2, "stagger": 0, "split": 1,
+         "nms_rounds": rounds, "score_rows": 16}
+    print(f"64-frame clip, 3 in flight, nms_rounds={rounds}", flush=True)
+    H.tuning_set(480, 640, 1, 64, 5, t)
+    try:
+        cs = H.ClipStream([fr, fr.clone(), fr.clone()], W, b)
+        try:
+            for _ in range(7):
+                cs.launch()
+            cs.synchronize()
+            for g in cs.graphs:
+                _check_graph(H, g, ref, nref)
+        finally:
+            cs.close()
+    finally:
+        H.tuning_set(480, 640, 1, 64, 5, None)
