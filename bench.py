@@ -456,6 +456,7 @@ def batched_leg(hog355, frames, Wt, bt, args, kw=None):
         for _ in range(args.steps):
             cs.launch()
         cs.synchronize()
+        torch.cuda.synchronize()
         dt_if = time.perf_counter() - t0
         same = all(bool(torch.equal(gg.n_dets, n_ref)) for gg in cs.graphs)
         cs.close()
