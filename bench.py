@@ -484,6 +484,72 @@ def batched_leg(hog355, frames, Wt, bt, args, kw=None):
             "kern_staged": kern_staged, "staged": staged, "ksteps": ksteps, "inflight": inflight}
 
 
+def f16x3_leg(hog355, frames, Wt, bt, bl, steps, warmup, ksteps, ps):
+    """The clip with window scores from split fp16 operands
+    (HOG_ARITH_F16X3, an opt-in arithmetic; the headline uses FP32): one
+    captured graph under the autotuned schedule, the clips in flight under
+    the in-flight schedule, the scoring kernel's HIP-event time on the
+    per-stage schedule, and the largest difference of its scores from the
+    FP32 scorer's over one frame."""
+    import torch
+    A = hog355.ARITH_F16X3
+    res = {"arith": "f16x3: each product from three fp16 matrix products of split operands "
+                    "(hi + 2^-11 lo), FP32 sums"}
+    g = hog355.DetectGraph(frames, Wt, bt, arith=A)
+    for _ in range(warmup):
+        g.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.launch()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    _, nk = hog355.dets_to_numpy(g.dets, g.n_dets)
+    g.close()
+    res["fps_one_clip_in_flight"] = round(CLIP * steps / dt, 1)
+    res["ms_per_clip_one_in_flight"] = round(1e3 * dt / steps, 4)
+    inf = bl["inflight"]
+    if inf:
+        hog355.tuning_set(H, W_PX, 1, CLIP, NF, inf["tuning"])
+        fl = [frames] + [frames.clone() for _ in range(inf["clips"] - 1)]
+        cs = hog355.ClipStream(fl, Wt, bt, arith=A)
+        for _ in range(warmup):
+            cs.launch()
+        cs.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            cs.launch()
+        cs.synchronize()
+        torch.cuda.synchronize()
+        dt_if = time.perf_counter() - t0
+        cs.close()
+        hog355.tuning_set(H, W_PX, 1, CLIP, NF, bl["tuning"])
+        res["fps"] = round(CLIP * steps / dt_if, 1)
+        res["ms_per_clip"] = round(1e3 * dt_if / steps, 4)
+        res["clips_in_flight"] = inf["clips"]
+        res["in_flight_tuning"] = inf["tuning"]
+    if ksteps:
+        hog355.tuning_set(H, W_PX, 1, CLIP, NF, bl["staged"])
+        ws = hog355.Workspace()
+        dets, nd = hog355.alloc_dets(CLIP, hog355.MAX_DETS)
+        kt = kernel_times(hog355, lambda: hog355.detect_batch_into(frames, Wt, bt, dets, nd, ws=ws, arith=A),
+                          ("feat", "score"), ksteps)
+        hog355.tuning_set(H, W_PX, 1, CLIP, NF, bl["tuning"])
+        res["kernels_per_step_staged"] = kt
+        if "score" in kt:
+            ms = kt["score"]["ms_per_launch"]
+            tf = 2.0 * 3100 * NF * ps["windows"] * CLIP / (ms * 1e-3) / 1e12
+            res["score_tflops_algorithmic"] = round(tf, 2)
+            res["score_frac_of_fp32_matrix_peak"] = round(tf / FP32_PEAK_TFLOPS, 4)
+    s0 = hog355.scores(frames[0], Wt, bt)
+    s1 = hog355.scores(frames[0], Wt, bt, arith=A)
+    torch.cuda.synchronize()
+    res["max_abs_score_diff_vs_f32_frame0"] = float(max(float((a[1] - c[1]).abs().max()) for a, c in zip(s0, s1)))
+    res["kept_per_frame_mean"] = float(np.mean(nk))
+    return res
+
+
 def plain_leg(hog355, frames, Wt, bt, n_frames, autotune=True):
     """One frame per call, submit to completion, on the clip's frames, under
     the schedule the autotuner picks for one frame (NMS rounds, scoring
@@ -566,6 +632,8 @@ def main():
                     help="skip the level-skipping, search-region, recursive-pyramid and tracking legs")
     ap.add_argument("--pipeline-batches", type=int, default=20,
                     help="64-frame batches through the host pipeline per source (0: skip)")
+    ap.add_argument("--no-f16x3", action="store_true",
+                    help="skip the leg with split-fp16 window scoring (HOG_ARITH_F16X3)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched clip (autotune, graph replay, kernel timing), e.g. to profile the "
                          "other legs alone; the line then has no value")
@@ -659,6 +727,9 @@ def main():
             "roofline_kernels": lines,
             "roofline_path": path,
         })
+    if not args.no_batched and not args.no_f16x3 and args.option == "none":
+        out["score_f16x3"] = f16x3_leg(hog355, frames, Wt, bt, bl, args.steps, args.warmup,
+                                       min(args.steps, args.kernel_steps), ps)
     if args.plain_frames > 0:
         out["plain"] = plain_leg(hog355, frames, Wt, bt, args.plain_frames, autotune=args.schedule == "auto")
     if not args.no_options and not args.no_batched:

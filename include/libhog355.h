@@ -106,7 +106,26 @@ typedef struct hog_params {
                           that no window inside it needs are skipped.  Read
                           when the work runs, so a captured graph sees the
                           values current at each replay. */
+    int32_t score_arith;  /* HOG_ARITH_F32 (the default): window scores from
+                          FP32 products on the matrix cores.
+                          HOG_ARITH_F16X3: each product of the window
+                          scores (Sec. IV-A linear classification) from
+                          three fp16 matrix products of split operands,
+                          v = fp16(v) + 2^-11 fp16((v - fp16(v)) 2^11),
+                          summed in FP32 (Ootomo and Yokota 2022): about
+                          FP32 accuracy (every product within 2^-22
+                          relative) at a fraction of the FP32 matrix time.
+                          Filter weights must lie below 2^15 in magnitude
+                          (larger ones give non-finite scores).  Applies
+                          to full filters in hog_detect, hog_detect_batch*,
+                          their graphs and hog_autotune (which then run
+                          the per-stage schedule); separable filter banks
+                          use FP32; hog_detect_topk returns HOG_E_INVAL
+                          for it.  Any other value: HOG_E_INVAL. */
 } hog_params;
+
+#define HOG_ARITH_F32 0
+#define HOG_ARITH_F16X3 1
 
 /* One pyramid level.  Level k has scale s_k = upsample * (5/6)^k and size
  * floor(h * s_k) x floor(w * s_k); levels continue while both sides are at
@@ -218,6 +237,15 @@ typedef struct hog_filterbank {
     const float* col;
     const float* bias;
 } hog_filterbank;
+
+/* hog_scores with a choice of the scoring arithmetic, score_arith as in
+ * hog_params (HOG_ARITH_F32: the same as hog_scores; HOG_ARITH_F16X3:
+ * products from split fp16 operands, weights below 2^15 in magnitude).
+ * HOG_E_INVAL for any other value, else as hog_scores. */
+int hog_scores_arith(const uint8_t* frame, int h, int w, int pitch, int upsample,
+                     const float* filters, const float* bias, int nf, int score_arith,
+                     float* scores, int64_t scores_cap,
+                     void* ws, size_t ws_bytes, void* stream);
 
 /* hog_scores for a filter bank (full or separable). */
 int hog_scores_bank(const uint8_t* frame, int h, int w, int pitch, int upsample,

@@ -222,7 +222,7 @@ int make_plan(int h, int w, int upsample, int n, int nf, Plan* P, int n_windows 
     P->o_boxes = o;
     o = align256(o + sizeof(int2) * (size_t)std::max(boxes, 1));
     P->o_bpack = o;
-    o = align256(o + sizeof(float4) * (size_t)std::max(P->groups, 1) * BPACK_PER_GROUP);
+    o = align256(o + BPACK_GROUP_BYTES * (size_t)std::max(P->groups, 1));
     P->o_hist = o;
     o = align256(o + sizeof(float) * (size_t)n * std::max(hist, 1LL) * HSTRIDE);
     P->o_feat = o;
@@ -325,12 +325,12 @@ int run_cascade(const Plan& P, int m, const uint8_t* frames, long long fstride, 
 }
 
 int run_pixels(const Plan& P, const uint8_t* frames, long long fstride, int pitch, void* ws, float* packed,
-               const float* filters, hipStream_t s, bool zero_keys) {
+               const float* filters, hipStream_t s, bool zero_keys, bool f16x3 = false) {
     const LevelTable& T = P.T;
     HOG_TRY(timed("geom", s, [&] {
         return launch_setup(T, at<int4>(ws, P.o_taps), at<int2>(ws, P.o_boxes), filters, P.nf,
                             at<float4>(ws, P.o_bpack), zero_keys ? at<unsigned long long>(ws, P.o_key) : nullptr,
-                            (long long)P.n * T.pos_frame, nullptr, 0, s);
+                            (long long)P.n * T.pos_frame, nullptr, 0, s, f16x3);
     }));
     HOG_TRY(run_cascade(P, P.n, frames, fstride, pitch, at<uint8_t>(ws, P.o_casc), s));
     HOG_TRY(timed("hist", s, [&] {
@@ -338,7 +338,7 @@ int run_pixels(const Plan& P, const uint8_t* frames, long long fstride, int pitc
                            s);
     }));
     HOG_TRY(timed("feat", s, [&] {
-        return launch_feat(T, P.n, at<float>(ws, P.o_hist), at<float>(ws, P.o_feat), packed, s);
+        return launch_feat(T, P.n, at<float>(ws, P.o_hist), at<float>(ws, P.o_feat), packed, s, f16x3);
     }));
     return HOG_OK;
 }
@@ -495,6 +495,7 @@ struct Bank {
     const float* col = nullptr;
     int rank = 0;
     const float* bias = nullptr;
+    bool f16x3 = false;   // full filters scored from split fp16 operands (HOG_ARITH_F16X3)
 };
 
 // Window scores of m frames into dense maps and / or keys.
@@ -507,7 +508,7 @@ int score_stage(const Plan& P, int m, const float* feat, const Bank& bank, float
         if (bank.rank == 0) {
             const int rows = score_rows ? score_rows : score_rows_auto(T, m, P.nf, compute_units());
             return launch_score(T, m, feat, at<float4>(ws, P.o_bpack), bank.bias, P.nf, thresh, dense, keys,
-                                keys && multi, rows, regions, s);
+                                keys && multi, rows, regions, s, bank.f16x3);
         }
         const int rows = score_rows == SCORE_SMALL_ROWS ? SCORE_SMALL_ROWS
                          : score_rows ? SEP_ROWS
@@ -529,19 +530,21 @@ int staged_chain(const Plan& P, int m, const FrameBufs& b, long long fstride, in
         return launch_hist(T, b.frames, fstride, pitch, m, b.hist, b.regions, b.casc, s);
     }));
     if (mark && stagger == 1 && hipEventRecord(mark, s) != hipSuccess) return HOG_E_HIP;
-    HOG_TRY(timed("feat", s, [&] { return launch_feat(T, m, b.hist, b.feat, nullptr, s); }));
+    HOG_TRY(timed("feat", s, [&] { return launch_feat(T, m, b.hist, b.feat, nullptr, s, bank.f16x3); }));
     HOG_TRY(score_stage(P, m, b.feat, bank, prm->thresh, nullptr, b.keys, score_rows, ws, s, b.regions));
     if (mark && stagger == 2 && hipEventRecord(mark, s) != hipSuccess) return HOG_E_HIP;
     return nms_chain(P, m, b, prm, cap, nullptr, rounds, ws, s);
 }
 
 int detect_sequence(const Plan& P, const hog_params* prm, const uint8_t* frames, long long fstride, int pitch,
-                    const Bank& bank, hog_det* dets, int cap, int* n_dets, void* ws, const hog_tuning& tune_in,
+                    const Bank& bank_in, hog_det* dets, int cap, int* n_dets, void* ws, const hog_tuning& tune_in,
                     hipStream_t s) {
-    // separable filters, search regions and the recursive pyramid run the
-    // per-stage schedule
+    Bank bank = bank_in;
+    bank.f16x3 = bank.rank == 0 && prm->score_arith == HOG_ARITH_F16X3;
+    // separable filters, search regions, the recursive pyramid and split
+    // fp16 scoring run the per-stage schedule
     hog_tuning tune = tune_in;
-    if ((bank.rank != 0 || prm->regions || P.cascade) && tune.fused) {
+    if ((bank.rank != 0 || prm->regions || P.cascade || bank.f16x3) && tune.fused) {
         tune.fused = 0;
         tune.split = 1;
     }
@@ -559,7 +562,7 @@ int detect_sequence(const Plan& P, const hog_params* prm, const uint8_t* frames,
         return launch_setup(T, at<int4>(ws, P.o_taps), at<int2>(ws, P.o_boxes), filters, P.nf,
                             at<float4>(ws, P.o_bpack), multi ? at<unsigned long long>(ws, P.o_key) : nullptr,
                             (long long)P.n * T.pos_frame, tune.fused ? sync : nullptr,
-                            tune.fused ? fused_sync_words(P.n) : 0, s);
+                            tune.fused ? fused_sync_words(P.n) : 0, s, bank.f16x3);
     }));
     if (tune.fused) {
         FusedCfg cfg;
@@ -684,6 +687,7 @@ int check_detect_args(const hog_params* prm, const void* frames, int pitch, int 
     if (!(prm->iou >= 0.5f && prm->iou < 1.f)) return HOG_E_INVAL;
     if (prm->thresh != prm->thresh) return HOG_E_INVAL;
     if (prm->min_face < 0 || prm->min_face > MAX_MIN_FACE) return HOG_E_INVAL;
+    if (prm->score_arith != HOG_ARITH_F32 && prm->score_arith != HOG_ARITH_F16X3) return HOG_E_INVAL;
     return HOG_OK;
 }
 
@@ -703,6 +707,9 @@ int hog_params_default(hog_params* p) {
     p->upsample = 1;
     p->thresh = 0.f;
     p->iou = 0.5f;
+    p->min_face = 0;
+    p->regions = nullptr;
+    p->score_arith = HOG_ARITH_F32;
     return HOG_OK;
 }
 
@@ -802,6 +809,28 @@ int hog_scores(const uint8_t* frame, int h, int w, int pitch, int upsample, cons
     if (!filters || !bias || nf < 1) return HOG_E_INVAL;
     const hog_filterbank fb = full_bank(filters, bias, nf);
     return hog_scores_bank(frame, h, w, pitch, upsample, &fb, scores, scores_cap, ws, ws_bytes, stream);
+}
+
+int hog_scores_arith(const uint8_t* frame, int h, int w, int pitch, int upsample, const float* filters,
+                     const float* bias, int nf, int score_arith, float* scores, int64_t scores_cap, void* ws,
+                     size_t ws_bytes, void* stream) {
+    if (score_arith != HOG_ARITH_F32 && score_arith != HOG_ARITH_F16X3) return HOG_E_INVAL;
+    if (score_arith == HOG_ARITH_F32)
+        return hog_scores(frame, h, w, pitch, upsample, filters, bias, nf, scores, scores_cap, ws, ws_bytes, stream);
+    if (!frame || !scores || !filters || !bias || pitch < w || pitch > MAX_PITCH) return HOG_E_INVAL;
+    if (nf < 1) return HOG_E_INVAL;
+    if (nf > MAX_FILTERS) return HOG_E_TOO_LARGE;
+    Plan P;
+    HOG_TRY(make_plan(h, w, upsample, 1, nf, &P));
+    HOG_TRY(check_ws(P, ws, ws_bytes));
+    if (scores_cap < P.dense_floats) return HOG_E_CAP;
+    if (P.T.n == 0) return HOG_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const hog_filterbank fb = full_bank(filters, bias, nf);
+    Bank bank = bank_of(&fb);
+    bank.f16x3 = true;
+    HOG_TRY(run_pixels(P, frame, 0, pitch, ws, nullptr, bank.W, s, false, true));
+    return score_stage(P, 1, at<float>(ws, P.o_feat), bank, 0.f, scores, nullptr, 0, ws, s);
 }
 
 int hog_detect_batch_bank(const hog_params* prm, const uint8_t* frames, int n, int h, int w, int pitch,
@@ -1137,8 +1166,8 @@ int hog_detect_topk(const hog_params* prm, const uint8_t* frames, int n, int h, 
                     hog_window* windows, float* scores, void* ws, size_t ws_bytes, void* stream) {
     HOG_TRY(check_detect_args(prm, frames, pitch, w, filters, bias, nf, dets, cap, n_dets));
     if (!windows || !scores || k < 1 || k > 16) return HOG_E_INVAL;
-    // the top k are taken over every window of every level
-    if (prm->regions || prm->min_face) return HOG_E_INVAL;
+    // the top k are taken over every window of every level, in FP32
+    if (prm->regions || prm->min_face || prm->score_arith != HOG_ARITH_F32) return HOG_E_INVAL;
     if (n < 1 || (n > 1 && frame_stride < (int64_t)pitch * h)) return HOG_E_INVAL;
     Plan P;
     HOG_TRY(make_plan(h, w, prm->upsample, n, nf, &P, 1));

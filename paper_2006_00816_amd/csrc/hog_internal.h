@@ -55,6 +55,13 @@ constexpr int SCORE_ORDER_SEARCH = 48;              // slots per frame up to whi
 constexpr int BPACK_MFMA = SC_KC * SC_NT * 64;      // float4 B operands of the matrix-core columns
 constexpr int BPACK_XTRA = SC_KC * 4 * 2;           // float4 weights of the two vector-ALU columns
 constexpr int BPACK_PER_GROUP = BPACK_MFMA + BPACK_XTRA;   // 64,000 bytes per filter group
+// Split fp16 operands (HOG_ARITH_F16X3, see stage_score.h): per filter
+// group, window row dr, N tile (4, all 50 columns) and part (hi, lo), one
+// 8-half B operand per lane.
+constexpr int B16_NT = 4;
+constexpr int B16_PER_GROUP = WIN * B16_NT * 2 * 64;       // uint4, 81,920 bytes per filter group
+constexpr size_t BPACK_GROUP_BYTES =
+    (size_t)BPACK_PER_GROUP * 16 > (size_t)B16_PER_GROUP * 16 ? (size_t)BPACK_PER_GROUP * 16 : (size_t)B16_PER_GROUP * 16;
 
 // Fused persistent kernel (k_fused.hip): counters in the workspace, as
 // u32 words: queue tickets [0, 8), error flag [8], then per frame the
@@ -148,7 +155,7 @@ __host__ __device__ inline unsigned int pack_window(int f, int k, int r, int c) 
 hipError_t launch_setup(const LevelTable& T, int4* taps, int2* boxes,
                         const float* filters, int nf, float4* bpack,
                         unsigned long long* poskey_zero, long long poskey_count, unsigned* sync_zero,
-                        int sync_count, hipStream_t s);
+                        int sync_count, hipStream_t s, bool f16x3 = false);
 hipError_t launch_hist(const LevelTable& T, const uint8_t* frames, long long fstride, int pitch,
                        int n, float* hist, const hog_region* regions, const uint8_t* casc, hipStream_t s);
 // One level of the recursive pyramid for n frames: the 8-bit image
@@ -159,8 +166,9 @@ hipError_t launch_hist(const LevelTable& T, const uint8_t* frames, long long fst
 hipError_t launch_cascade(const uint8_t* frames, long long fstride, int pitch, int n, uint8_t* casc,
                           long long casc_frame, int h_out, int w_out, int dst_off, int h_in, int w_in, int src_off,
                           long long sig, hipStream_t s);
+// f16x3: the maps hold split fp16 operands for the scorer (HOG_ARITH_F16X3)
 hipError_t launch_feat(const LevelTable& T, int n, const float* hist, float* feat,
-                       float* packed, hipStream_t s);
+                       float* packed, hipStream_t s, bool f16x3 = false);
 int fused_sync_words(int n);
 struct FusedNeed {
     unsigned hist, feat, score;   // finished-wave counts of a complete frame
@@ -171,10 +179,12 @@ hipError_t launch_fused(const LevelTable& T, int n, const FusedCfg& cfg, const u
                         float thresh, unsigned long long* poskey, bool atomic_key, unsigned* sync, hipStream_t s);
 int score_rows_auto(const LevelTable& T, int n, int nf, int cus);
 int sep_rows_auto(const LevelTable& T, int n, int nf, int cus);
+// f16x3: B was packed by launch_setup with f16x3 set, and the products are
+// formed from split fp16 operands (HOG_ARITH_F16X3).
 hipError_t launch_score(const LevelTable& T, int n, const float* feat, const float4* bpack,
                         const float* bias, int nf, float thresh, float* dense,
                         unsigned long long* poskey, bool atomic_key, int rows, const hog_region* regions,
-                        hipStream_t s);
+                        hipStream_t s, bool f16x3 = false);
 constexpr int SEP_MAX_RANK = 4;   // row / column filter pairs per channel of a separable filter
 constexpr int SEP_ROWS = 8;       // window rows per separable scoring item (256 VGPRs per lane at 512 threads)
 hipError_t launch_score_sep(const LevelTable& T, int n, const float* feat, const float* row, const float* col,

@@ -6,6 +6,7 @@
 #include <functional>
 #include <map>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "stage_score.h"
@@ -51,13 +52,15 @@ __device__ __forceinline__ bool score_slot(const ScoreOrder& ord, int per_frame,
     return true;
 }
 
-template <int ROWS>
+// F16: products from split fp16 operands (HOG_ARITH_F16X3).
+template <int ROWS, bool F16>
 __global__ __launch_bounds__(ROWS * 64) void hog_score_kernel(
     LevelTable T, ScoreOrder ord, int groups, int per_frame, int units, int halves, const float* __restrict__ feat,
     const float4* __restrict__ bpack, const float* __restrict__ bias, int nf, float thresh,
     float* __restrict__ dense, unsigned long long* __restrict__ poskey, int atomic_key,
     const hog_region* __restrict__ regions) {
-    __shared__ ScoreSmemT<ROWS> sm;
+    using SM = typename std::conditional<F16, Score16SmemT<ROWS>, ScoreSmemT<ROWS>>::type;
+    __shared__ SM sm;
     int unit, it;
     if (!score_slot(ord, per_frame, units, &unit, &it)) return;
     const int grp = unit % groups;
@@ -66,8 +69,8 @@ __global__ __launch_bounds__(ROWS * 64) void hog_score_kernel(
     load_bpack(sm, bpack, grp, tid);
     __syncthreads();
     // halves = 2: slot it runs one half of the tiles of row block it / 2
-    score_item<ROWS>(T, frame, grp, halves == 2 ? it >> 1 : it, sm, sm.P[tid >> 6], feat, nf, bias, thresh, dense,
-                     poskey, atomic_key, tid, halves == 2 ? it & 1 : -1, regions);
+    score_item<ROWS, F16>(T, frame, grp, halves == 2 ? it >> 1 : it, sm, sm.P[tid >> 6], feat, nf, bias, thresh,
+                          dense, poskey, atomic_key, tid, halves == 2 ? it & 1 : -1, regions);
 }
 
 // The same work items and dispatch with separable filters (row and column
@@ -255,20 +258,24 @@ int score_rows_auto(const LevelTable& T, int n, int nf, int cus) {
 
 hipError_t launch_score(const LevelTable& T, int n, const float* feat, const float4* bpack, const float* bias,
                         int nf, float thresh, float* dense, unsigned long long* poskey, bool atomic_key, int rows,
-                        const hog_region* regions, hipStream_t s) {
+                        const hog_region* regions, hipStream_t s, bool f16x3) {
     ScoreGrid g;
     if (T.rows_total <= 0 || n <= 0) return hipSuccess;
     if (!score_grid(T, n, nf, rows, &g)) return hipErrorInvalidValue;
-    if (rows == SCORE_SMALL_ROWS)
-        hipLaunchKernelGGL(hog_score_kernel<SCORE_SMALL_ROWS>, dim3(g.blocks), dim3(SCORE_SMALL_ROWS * 64), 0, s, T,
-                           g.ord, g.groups, g.per_frame, g.units, g.halves, feat, bpack, bias, nf, thresh, dense,
-                           poskey, atomic_key ? 1 : 0, regions);
-    else if (rows == ROWS_PER_ITEM)
-        hipLaunchKernelGGL(hog_score_kernel<ROWS_PER_ITEM>, dim3(g.blocks), dim3(ROWS_PER_ITEM * 64), 0, s, T, g.ord,
-                           g.groups, g.per_frame, g.units, g.halves, feat, bpack, bias, nf, thresh, dense, poskey,
-                           atomic_key ? 1 : 0, regions);
-    else
+#define HOG_SCORE_LAUNCH(R, F)                                                                                   \
+    hipLaunchKernelGGL((hog_score_kernel<R, F>), dim3(g.blocks), dim3(R * 64), 0, s, T, g.ord, g.groups,          \
+                       g.per_frame, g.units, g.halves, feat, bpack, bias, nf, thresh, dense, poskey,             \
+                       atomic_key ? 1 : 0, regions)
+    if (rows == SCORE_SMALL_ROWS) {
+        if (f16x3) HOG_SCORE_LAUNCH(SCORE_SMALL_ROWS, true);
+        else HOG_SCORE_LAUNCH(SCORE_SMALL_ROWS, false);
+    } else if (rows == ROWS_PER_ITEM) {
+        if (f16x3) HOG_SCORE_LAUNCH(ROWS_PER_ITEM, true);
+        else HOG_SCORE_LAUNCH(ROWS_PER_ITEM, false);
+    } else {
         return hipErrorInvalidValue;
+    }
+#undef HOG_SCORE_LAUNCH
     return hipGetLastError();
 }
 

@@ -21,7 +21,7 @@ namespace hog {
 __global__ __launch_bounds__(256) void hog_setup_kernel(
     LevelTable T, int4* __restrict__ taps, int2* __restrict__ boxes,
     const float* __restrict__ W, int nf, float4* __restrict__ bpack,
-    unsigned long long* __restrict__ keys, long long nkeys, unsigned* __restrict__ sync, int nsync) {
+    unsigned long long* __restrict__ keys, long long nkeys, unsigned* __restrict__ sync, int nsync, int f16x3) {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (blockIdx.y == 0) {
         if (e < T.taps_total) {
@@ -52,6 +52,29 @@ __global__ __launch_bounds__(256) void hog_setup_kernel(
                 }
             }
         }
+    } else if (blockIdx.y == 1 && f16x3) {
+        // split fp16 B operands: entry ((dr B16_NT + nt) 2 + part) 64 + lane
+        // of group grp holds the hi (part 0) or lo (part 1) halves of the
+        // weights of channels 8 (lane / 16) + i, column 16 nt + lane % 16
+        const int ngroups = (nf + FGROUP - 1) / FGROUP;
+        if (!W || e >= (long long)ngroups * B16_PER_GROUP) return;
+        const int grp = (int)(e / B16_PER_GROUP);
+        const int rem = (int)(e % B16_PER_GROUP);
+        const int lane = rem & 63, part = (rem >> 6) & 1, nt = (rem >> 7) % B16_NT, dr = rem / (B16_NT * 128);
+        const int n = 16 * nt + (lane & 15);
+        const int f = grp * FGROUP + n / WIN, dc = n % WIN;
+        _Float16 v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int ch = 8 * (lane >> 4) + i;
+            const bool ok = n < FGROUP * WIN && f < nf && ch < NFEAT;
+            const float w = ok ? W[((f * WIN + dr) * WIN + dc) * NFEAT + ch] : 0.f;
+            const _Float16 h = (_Float16)w;
+            v[i] = part ? (_Float16)((w - (float)h) * 2048.f) : h;
+        }
+        uint4 q;
+        __builtin_memcpy(&q, v, sizeof q);
+        reinterpret_cast<uint4*>(bpack)[e] = q;
     } else if (blockIdx.y == 1) {
         const int ngroups = (nf + FGROUP - 1) / FGROUP;
         if (!W || e >= (long long)ngroups * BPACK_PER_GROUP) return;
@@ -87,9 +110,10 @@ __global__ __launch_bounds__(256) void hog_setup_kernel(
 
 hipError_t launch_setup(const LevelTable& T, int4* taps, int2* boxes, const float* filters, int nf,
                         float4* bpack, unsigned long long* poskey_zero, long long poskey_count, unsigned* sync_zero,
-                        int sync_count, hipStream_t s) {
+                        int sync_count, hipStream_t s, bool f16x3) {
     const long long geo = (long long)T.taps_total + T.boxes_total;
-    const long long pk = filters ? (long long)((nf + FGROUP - 1) / FGROUP) * BPACK_PER_GROUP : 0;
+    const long long pk =
+        filters ? (long long)((nf + FGROUP - 1) / FGROUP) * (f16x3 ? B16_PER_GROUP : BPACK_PER_GROUP) : 0;
     const long long zk = poskey_zero ? poskey_count : 0;
     const int zs = sync_zero ? sync_count : 0;
     long long m = geo > pk ? geo : pk;
@@ -98,7 +122,7 @@ hipError_t launch_setup(const LevelTable& T, int4* taps, int2* boxes, const floa
     const int segs = (zk || zs) ? 3 : (filters ? 2 : 1);
     dim3 grid((unsigned)((m + 255) / 256), segs);
     hipLaunchKernelGGL(hog_setup_kernel, grid, dim3(256), 0, s, T, taps, boxes, filters, nf, bpack,
-                       poskey_zero, zk, sync_zero, zs);
+                       poskey_zero, zk, sync_zero, zs, f16x3 ? 1 : 0);
     return hipGetLastError();
 }
 

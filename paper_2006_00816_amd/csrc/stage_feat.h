@@ -16,9 +16,13 @@ namespace hog {
 // The padded layout stores 32 floats per cell (channel 31 = 0) and two
 // zero cells after each row, which the scorer reads past the last column.
 // `packed`, when non-null, also receives [cy][cx][31] at the level's
-// packed offset (single frame).
+// packed offset (single frame).  F16: the cell's 128 bytes hold instead
+// the split fp16 operands of the scorer (HOG_ARITH_F16X3): the 32 high
+// parts fp16(F[c]), then the 32 low parts fp16((F[c] - hi) 2^11), both
+// rounded to nearest (zero cells are zero either way).
 // Block `blk` (of FEAT_THREADS cells, within one level) of a frame; thread
 // `tid` of the block.
+template <bool F16 = false>
 __device__ __forceinline__ void feat_cell(const LevelTable& T, const float* __restrict__ hist,
                                           float* __restrict__ feat, float* __restrict__ packed, int frame, int blk,
                                           int tid) {
@@ -71,8 +75,27 @@ __device__ __forceinline__ void feat_cell(const LevelTable& T, const float* __re
         for (int o = 0; o < NORIENT; ++o) F[NBINS + o] += 0.5f * fminf((h[o] + h[o + NORIENT]) * n[q], 0.2f);
         F[27 + q] = 0.23570226039551584f * tsum;   // 1/sqrt(18)
     }
+    if (F16) {
+        _Float16 hl[2 * FPAD];
 #pragma unroll
-    for (int q = 0; q < FPAD / 4; ++q) out[q] = make_float4(F[4 * q], F[4 * q + 1], F[4 * q + 2], F[4 * q + 3]);
+        for (int c = 0; c < FPAD; ++c) {
+            // both parts from the stored FP32 feature: the empty asm keeps
+            // the compiler from forming the high part with a mixed-precision
+            // FMA from the unrounded last sum
+            float f = F[c];
+            asm volatile("" : "+v"(f));
+            const _Float16 hi = (_Float16)f;
+            hl[c] = hi;
+            hl[FPAD + c] = (_Float16)((f - (float)hi) * 2048.f);
+        }
+        uint4 q4[FPAD / 4];
+        __builtin_memcpy(q4, hl, sizeof q4);
+#pragma unroll
+        for (int q = 0; q < FPAD / 4; ++q) reinterpret_cast<uint4*>(out)[q] = q4[q];
+    } else {
+#pragma unroll
+        for (int q = 0; q < FPAD / 4; ++q) out[q] = make_float4(F[4 * q], F[4 * q + 1], F[4 * q + 2], F[4 * q + 3]);
+    }
     if (packed) {
         float* p = packed + L.pk_off + ((long long)i * L.cx + j) * NFEAT;
 #pragma unroll

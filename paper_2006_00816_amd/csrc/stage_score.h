@@ -18,11 +18,26 @@ struct ScoreSmemT {
 };
 using ScoreSmem = ScoreSmemT<ROWS_PER_ITEM>;
 
+// LDS of one scoring item with split fp16 operands (HOG_ARITH_F16X3): the
+// group's packed B16 (80 KB) and the per-wave partial-product tiles.
+template <int ROWS>
+struct Score16SmemT {
+    uint4 B[B16_PER_GROUP];
+    float P[ROWS][SC_RING];
+};
+
 template <int ROWS>
 __device__ __forceinline__ void load_bpack(ScoreSmemT<ROWS>& sm, const float4* __restrict__ bpack, int grp,
                                            int tid) {
     const float4* __restrict__ g = bpack + (long long)grp * BPACK_PER_GROUP;
     for (int e = tid; e < BPACK_PER_GROUP; e += ROWS * 64) sm.B[e] = g[e];
+}
+
+template <int ROWS>
+__device__ __forceinline__ void load_bpack(Score16SmemT<ROWS>& sm, const float4* __restrict__ bpack, int grp,
+                                           int tid) {
+    const uint4* __restrict__ g = reinterpret_cast<const uint4*>(bpack) + (long long)grp * B16_PER_GROUP;
+    for (int e = tid; e < B16_PER_GROUP; e += ROWS * 64) sm.B[e] = g[e];
 }
 
 // Window scores of M tile t of window row r from the tile's partial
@@ -263,14 +278,109 @@ __device__ __forceinline__ void score_row(const DevLevel& L, int k, int r, const
     }
 }
 
+// ------------------------- FP32-accurate scoring from fp16 matrix products
+// With HOG_ARITH_F16X3 every operand v (feature or weight) is split into
+// v_hi = fp16(v) and v_lo = fp16((v - v_hi) 2^11), both rounded to
+// nearest, so that v = v_hi + 2^-11 v_lo to within 2^-24 |v| (below 2^15
+// in magnitude; v - v_hi and the scaling are exact in FP32).  A product is
+//   x w = x_hi w_hi + 2^-11 (x_hi w_lo + x_lo w_hi) + 2^-22 x_lo w_lo,
+// of which the last term (at most 2^-24 |x w|) is dropped.  Products of
+// fp16 values are exact in FP32 and v_mfma_f32_16x16x32_f16 sums them in
+// FP32, the first term into one accumulator and the two cross terms into
+// another: P = acc_hi + 2^-11 acc_cross.  This is the split-operand
+// scheme of Ootomo and Yokota (2022), which recovers single-precision
+// accuracy from half-precision matrix units; the scale 2^11 keeps the
+// low parts out of the fp16 subnormal range.
+//
+// Operand layout (the same for A and B, so any K order the hardware uses
+// pairs them alike): one MFMA per feature row dr of the window, K = the
+// 32 channels; lane (g4, j) holds channels 8 g4 .. 8 g4 + 7 of cell
+// 16 t + j (A) or of column 16 nt + j (B).  The feature kernel stores
+// each cell's split operands in its 128 bytes (32 hi halves, then 32 lo
+// halves), so a lane's A operands are two 16-byte loads.  B16 entry
+// ((dr B16_NT + nt) 2 + part) 64 + lane holds the hi (part 0) or lo
+// (part 1) halves of that lane.  All 50 columns (f, dc) run on the matrix
+// cores: N tile 3 holds columns 48, 49 (f = 4, dc = 8, 9).
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+
+// One window row r with split fp16 operands; NT N tiles (4 for a group of
+// 5 filters, fewer for smaller groups); arguments and outputs as score_row,
+// with the same tile walk, carry and epilogue.
+template <int NT, bool XTRA, int ROWS>
+__device__ __forceinline__ void score_row16(const DevLevel& L, int k, int r, const float* __restrict__ Ffr,
+                                            const Score16SmemT<ROWS>& sm, float* __restrict__ ring, int grp, int nf,
+                                            const float* __restrict__ bias, float thresh, float* __restrict__ Dfr,
+                                            unsigned long long* __restrict__ PKfr, int atomic_key, int lane,
+                                            int t_begin, int t_end, int c_lo, int c_hi) {
+    static_assert(!XTRA || NT == 4, "a group of 5 filters needs 4 N tiles");
+    const int g4 = lane >> 4, j = lane & 15;
+    const int pitch = (L.cx + 2) * FPAD;
+    // the cell's hi halves of channels 8 g4 .. 8 g4 + 7 at float 4 g4,
+    // the lo halves 16 floats further
+    const float* __restrict__ Fr = Ffr + L.feat_off + (long long)r * pitch + 4 * g4;
+    const int f0 = grp * FGROUP + g4, f1 = f0 + 4;
+    const bool f0ok = f0 < nf, f1ok = XTRA && g4 == 0;
+    const float b0 = f0ok ? bias[f0] : 0.f, b1 = f1ok ? bias[f1] : 0.f;
+    float* __restrict__ D = Dfr ? Dfr + L.sc_off : nullptr;
+    unsigned long long* __restrict__ PK = PKfr ? PKfr + L.pos_off + (long long)r * L.cols : nullptr;
+    const uint4* __restrict__ Bl = sm.B + lane;
+    const int t_first = max(t_begin - 1, 0);
+    float carry0 = 0.f, carry1 = 0.f;
+    for (int t = t_first; t < t_end; ++t) {
+        const float* __restrict__ a = Fr + min(16 * t + j, L.cx + 1) * FPAD;
+        floatx4 ah[NT], ac[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) ah[nt] = ac[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+        // feature rows dr + 1 and dr + 2 are loaded while row dr computes
+        uint4 x[3][2];
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+            x[d][0] = *reinterpret_cast<const uint4*>(a + d * pitch);
+            x[d][1] = *reinterpret_cast<const uint4*>(a + d * pitch + 16);
+        }
+#pragma unroll
+        for (int dr = 0; dr < WIN; ++dr) {
+            if (dr + 2 < WIN) {
+                x[(dr + 2) % 3][0] = *reinterpret_cast<const uint4*>(a + (dr + 2) * pitch);
+                x[(dr + 2) % 3][1] = *reinterpret_cast<const uint4*>(a + (dr + 2) * pitch + 16);
+            }
+            const halfx8 hi = __builtin_bit_cast(halfx8, x[dr % 3][0]);
+            const halfx8 lo = __builtin_bit_cast(halfx8, x[dr % 3][1]);
+            const uint4* __restrict__ b = Bl + dr * (B16_NT * 2 * 64);
+            halfx8 bh[NT], bl[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                bh[nt] = __builtin_bit_cast(halfx8, b[(2 * nt) * 64]);
+                bl[nt] = __builtin_bit_cast(halfx8, b[(2 * nt + 1) * 64]);
+            }
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) ah[nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(hi, bh[nt], ah[nt], 0, 0, 0);
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) ac[nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(hi, bl[nt], ac[nt], 0, 0, 0);
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) ac[nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(lo, bh[nt], ac[nt], 0, 0, 0);
+        }
+        // lane (g4, j) holds P[16 t + 4 g4 + i][16 nt + j], i = 0..3
+        wave_lds_order();
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const float4 v = make_float4(fmaf(ac[nt][0], 0x1p-11f, ah[nt][0]), fmaf(ac[nt][1], 0x1p-11f, ah[nt][1]),
+                                         fmaf(ac[nt][2], 0x1p-11f, ah[nt][2]), fmaf(ac[nt][3], 0x1p-11f, ah[nt][3]));
+            if (nt < 3 || j < 2) *reinterpret_cast<float4*>(ring + (16 * nt + j) * SC_RSTR + 4 * g4) = v;
+        }
+        wave_lds_order();
+        tile_windows<XTRA>(L, k, r, t, t_begin, ring, carry0, carry1, g4, j, f0, f1, f0ok, f1ok, b0, b1, thresh, D,
+                           PK, atomic_key, c_lo, c_hi);
+    }
+}
+
 // One scoring item: window rows q = ROWS * item + wave of the frame's list
 // of rows (levels in order), filter group grp; sm.B holds the group's B.
 // Waves past the last row do nothing.  half < 0: whole rows; half = 0 or 1:
 // the first or second half of the M tiles of rows with three or more tiles
 // (the second half of a shorter row is empty).
-template <int ROWS>
-__device__ __forceinline__ void score_item(const LevelTable& T, int frame, int grp, int item,
-                                           const ScoreSmemT<ROWS>& sm,
+template <int ROWS, bool F16 = false, class SM>
+__device__ __forceinline__ void score_item(const LevelTable& T, int frame, int grp, int item, const SM& sm,
                                            float* __restrict__ ring, const float* __restrict__ feat, int nf,
                                            const float* __restrict__ bias, float thresh, float* __restrict__ dense,
                                            unsigned long long* __restrict__ poskey, int atomic_key, int tid,
@@ -298,18 +408,34 @@ __device__ __forceinline__ void score_item(const LevelTable& T, int frame, int g
     int c_lo, c_hi;
     region_row(T, L, k, r, regions ? regions + frame : nullptr, PKfr, atomic_key, lane, tb, te, c_lo, c_hi);
     if (tb >= te) return;
-    if (fg == 5)
-        score_row<3, true, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane, tb, te,
-                                 c_lo, c_hi);
-    else if (fg == 4)
-        score_row<3, false, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane, tb,
-                                  te, c_lo, c_hi);
-    else if (fg >= 2)
-        score_row<2, false, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane, tb,
-                                  te, c_lo, c_hi);
-    else
-        score_row<1, false, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane, tb,
-                                  te, c_lo, c_hi);
+    if constexpr (F16) {
+        // N tiles of 16 columns (f, dc) that the group's filters fill
+        if (fg == 5)
+            score_row16<4, true, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane, tb,
+                                       te, c_lo, c_hi);
+        else if (fg >= 4)
+            score_row16<3, false, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane,
+                                        tb, te, c_lo, c_hi);
+        else if (fg >= 2)
+            score_row16<2, false, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane,
+                                        tb, te, c_lo, c_hi);
+        else
+            score_row16<1, false, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane,
+                                        tb, te, c_lo, c_hi);
+    } else {
+        if (fg == 5)
+            score_row<3, true, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane, tb,
+                                     te, c_lo, c_hi);
+        else if (fg == 4)
+            score_row<3, false, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane, tb,
+                                      te, c_lo, c_hi);
+        else if (fg >= 2)
+            score_row<2, false, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane, tb,
+                                      te, c_lo, c_hi);
+        else
+            score_row<1, false, ROWS>(L, k, r, Ffr, sm, ring, grp, nf, bias, thresh, Dfr, PKfr, atomic_key, lane, tb,
+                                      te, c_lo, c_hi);
+    }
 }
 
 // ------------------------------------------- separable (row / column) filters

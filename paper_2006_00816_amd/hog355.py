@@ -29,7 +29,11 @@ class HogError(RuntimeError):
 
 class hog_params(ctypes.Structure):
     _fields_ = [("upsample", ctypes.c_int32), ("thresh", ctypes.c_float), ("iou", ctypes.c_float),
-                ("min_face", ctypes.c_int32), ("regions", ctypes.c_void_p)]
+                ("min_face", ctypes.c_int32), ("regions", ctypes.c_void_p), ("score_arith", ctypes.c_int32)]
+
+
+ARITH_F32 = 0     # HOG_ARITH_F32: FP32 products (the default)
+ARITH_F16X3 = 1   # HOG_ARITH_F16X3: each product from three fp16 products of split operands
 
 
 ALL_LEVELS = 1 << 30
@@ -131,6 +135,7 @@ def lib():
         "hog_features": ([vp, i32, i32, i32, i32, vp, i64, vp, sz, vp], i32),
         "hog_scores": ([vp, i32, i32, i32, i32, vp, vp, i32, vp, i64, vp, sz, vp], i32),
         "hog_scores_bank": ([vp, i32, i32, i32, i32, vp, vp, i64, vp, sz, vp], i32),
+        "hog_scores_arith": ([vp, i32, i32, i32, i32, vp, vp, i32, i32, vp, i64, vp, sz, vp], i32),
         "hog_detect_batch_bank": ([vp, vp, i32, i32, i32, i32, i64, vp, vp, i32, vp, vp, sz, vp], i32),
         "hog_graph_create_bank": ([vp, vp, vp, i32, i32, i32, i32, i64, vp, vp, i32, vp, vp, sz, vp], i32),
         "hog_detect": ([vp, vp, i32, i32, i32, vp, vp, i32, vp, i32, vp, vp, sz, vp], i32),
@@ -278,16 +283,21 @@ def features(frame: torch.Tensor, upsample: int = 1, ws=None):
             for l in levels]
 
 
-def scores(frame: torch.Tensor, W: torch.Tensor, b: torch.Tensor, upsample: int = 1, ws=None):
-    """Dense window scores per level: list of (level dict, tensor [nf][rows][cols])."""
+def scores(frame: torch.Tensor, W: torch.Tensor, b: torch.Tensor, upsample: int = 1, ws=None, arith=None):
+    """Dense window scores per level: list of (level dict, tensor [nf][rows][cols]).
+    arith (ARITH_*): through hog_scores_arith; None: hog_scores."""
     h, w, pitch = _frame_args(frame)
     nf = int(W.shape[0])
     levels = pyramid(h, w, upsample, nf)
     total = sum(nf * l["rows"] * l["cols"] for l in levels)
     out = torch.empty(max(total, 1), dtype=torch.float32, device=frame.device)
     wp, wn = _ws(ws, workspace_bytes(h, w, upsample, 1, nf))
-    _check(lib().hog_scores(_fptr(frame), h, w, pitch, upsample, _ptr(W), _ptr(b), nf, _ptr(out), out.numel(),
-                            wp, wn, _stream()), "hog_scores")
+    if arith is None:
+        _check(lib().hog_scores(_fptr(frame), h, w, pitch, upsample, _ptr(W), _ptr(b), nf, _ptr(out), out.numel(),
+                                wp, wn, _stream()), "hog_scores")
+    else:
+        _check(lib().hog_scores_arith(_fptr(frame), h, w, pitch, upsample, _ptr(W), _ptr(b), nf, int(arith),
+                                      _ptr(out), out.numel(), wp, wn, _stream()), "hog_scores_arith")
     return [(l, out[l["score_offset"]:l["score_offset"] + nf * l["rows"] * l["cols"]]
              .view(nf, l["rows"], l["cols"])) for l in levels]
 
@@ -327,9 +337,9 @@ def detect_batch_bank(frames: torch.Tensor, bank: FilterBank, thresh=0.0, iou=0.
     return dets_to_numpy(dets, nd)
 
 
-def _params(thresh, iou, upsample, min_face=0, regions=None, n=None):
+def _params(thresh, iou, upsample, min_face=0, regions=None, n=None, arith=ARITH_F32):
     """hog_params; `regions` is an int32 [n][6] device tensor (see
-    region_tensor) or None."""
+    region_tensor) or None; `arith` the scoring arithmetic (ARITH_*)."""
     rp = None
     if regions is not None:
         if regions.dtype != torch.int32 or regions.dim() != 2 or regions.shape[1] != 6:
@@ -337,22 +347,23 @@ def _params(thresh, iou, upsample, min_face=0, regions=None, n=None):
         if n is not None and regions.shape[0] < n:
             raise HogError(f"{regions.shape[0]} regions for {n} frames")
         rp = _ptr(regions).value
-    return hog_params(upsample, thresh, iou, int(min_face), rp)
+    return hog_params(upsample, thresh, iou, int(min_face), rp, int(arith))
 
 
 def detect_batch_into(frames: torch.Tensor, W: torch.Tensor, b: torch.Tensor, dets: torch.Tensor,
                       n_dets: torch.Tensor, thresh: float = 0.0, iou: float = 0.5, upsample: int = 1, ws=None,
-                      min_face: int = 0, regions: torch.Tensor = None):
+                      min_face: int = 0, regions: torch.Tensor = None, arith: int = ARITH_F32):
     """Enqueue hog_detect_batch into caller-provided outputs: dets int32
     [n][cap][10] (hog_det records), n_dets int32 [n].  min_face skips the
     levels whose window spans fewer frame pixels; regions (int32 [n][6],
-    device) restricts each frame's search."""
+    device) restricts each frame's search; arith selects the scoring
+    arithmetic (ARITH_F32, or ARITH_F16X3: split fp16 operands)."""
     if frames.dtype != torch.uint8 or frames.dim() != 3:
         raise HogError("frames must be a uint8 [n][h][w] device tensor")
     n, h, w = (int(v) for v in frames.shape)
     cap = int(dets.shape[1])
     nf = int(W.shape[0])
-    prm = _params(thresh, iou, upsample, min_face, regions, n)
+    prm = _params(thresh, iou, upsample, min_face, regions, n, arith)
     wp, wn = _ws(ws, workspace_bytes(h, w, upsample, n, nf))
     _check(lib().hog_detect_batch(ctypes.byref(prm), _fptr(frames), n, h, w, int(frames.stride(1)),
                                   int(frames.stride(0)), _ptr(W), _ptr(b), nf, _ptr(dets), cap, _ptr(n_dets),
@@ -403,9 +414,9 @@ def detect(frame: torch.Tensor, W, b, thresh=0.0, iou=0.5, upsample=1, cap=MAX_D
 
 
 def detect_batch(frames: torch.Tensor, W, b, thresh=0.0, iou=0.5, upsample=1, cap=MAX_DETS, ws=None, min_face=0,
-                 regions=None):
+                 regions=None, arith=ARITH_F32):
     dets, nd = alloc_dets(int(frames.shape[0]), cap, frames.device)
-    detect_batch_into(frames, W, b, dets, nd, thresh, iou, upsample, ws, min_face, regions)
+    detect_batch_into(frames, W, b, dets, nd, thresh, iou, upsample, ws, min_face, regions, arith)
     return dets_to_numpy(dets, nd)
 
 
@@ -498,7 +509,7 @@ class DetectGraph:
     FilterBank) takes the place of W and b when given."""
 
     def __init__(self, frames: torch.Tensor, W=None, b=None, cap=MAX_DETS, thresh=0.0, iou=0.5, upsample=1,
-                 bank: FilterBank = None, min_face: int = 0, regions: torch.Tensor = None):
+                 bank: FilterBank = None, min_face: int = 0, regions: torch.Tensor = None, arith: int = ARITH_F32):
         n, h, w = (int(v) for v in frames.shape)
         if bank is None:
             bank = FilterBank(b, W=W)
@@ -506,7 +517,7 @@ class DetectGraph:
         self.frames, self.bank, self.regions = frames, bank, regions
         self.dets, self.n_dets = alloc_dets(n, cap, frames.device)
         self.ws = torch.empty(workspace_bytes(h, w, upsample, n, nf), dtype=torch.uint8, device=frames.device)
-        self.prm = _params(thresh, iou, upsample, min_face, regions, n)
+        self.prm = _params(thresh, iou, upsample, min_face, regions, n, arith)
         self.stream = torch.cuda.Stream(device=frames.device)
         self.handle = ctypes.c_void_p()
         torch.cuda.synchronize(frames.device)

@@ -143,12 +143,26 @@ def test_region_and_level_arguments_checked_before_launch(L):
     rejected on the host (dummy pointers, no GPU); hog_params has the
     header's layout."""
     from paper_2006_00816_amd import hog355
-    assert ctypes.sizeof(hog355.hog_params) == 24 and hog355.hog_params.regions.offset == 16
+    assert ctypes.sizeof(hog355.hog_params) == 32 and hog355.hog_params.regions.offset == 16
+    assert hog355.hog_params.score_arith.offset == 24
     v = ctypes.c_void_p
     for mf, want in ((-1, -1), (65537, -1)):
         p = hog355.hog_params(1, 0.0, 0.5, mf, None)
         assert L.hog_detect(ctypes.byref(p), v(1), 240, 320, 320, v(1), v(1), 1, v(1), 16, v(1), v(1), 1 << 40,
                             None) == want
+    # the scoring arithmetic: HOG_ARITH_F32 (0) or HOG_ARITH_F16X3 (1)
+    for ar in (-1, 2, 7):
+        p = hog355.hog_params(1, 0.0, 0.5, 0, None, ar)
+        assert L.hog_detect(ctypes.byref(p), v(1), 240, 320, 320, v(1), v(1), 1, v(1), 16, v(1), v(1), 1 << 40,
+                            None) == -1, ar
+        assert L.hog_scores_arith(v(1), 240, 320, 320, 1, v(1), v(1), 1, ar, v(1), 1 << 30, v(1), 1 << 40,
+                                  None) == -1, ar
+    p = hog355.hog_params(1, 0.0, 0.5, 0, None, hog355.ARITH_F16X3)
+    assert L.hog_detect_topk(ctypes.byref(p), v(1), 1, 240, 320, 320, 0, v(1), v(1), 1, v(1), 16, v(1), 1, v(1),
+                             v(1), v(1), 1 << 40, None) == -1
+    d = hog355.hog_params(7, 1.0, 0.9, 5, 3, 9)
+    assert L.hog_params_default(ctypes.byref(d)) == 0
+    assert (d.upsample, d.thresh, d.iou, d.min_face, d.regions, d.score_arith) == (1, 0.0, 0.5, 0, None, 0)
     ok = dict(dets=v(1), nd=v(1), n=2, cap=16, h=480, w=640, margin=8, span=1, regs=v(1))
 
     def track(**kw):
