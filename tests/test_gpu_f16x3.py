@@ -120,3 +120,51 @@ def test_clip_64_f16x3_batch_graph_and_sampled_frames(H):
         assert int(n1[0]) == int(nref[i]) and _same(a, c), i
         cg = _assert_nms(H, wl.frames[i], wl.W, wl.b, 1, ref[i], int(nref[i]))
         assert_end_to_end(wl.frames[i], wl.W, wl.b, 1, cg, ref[i], int(nref[i]), f"f16x3 clip frame {i}")
+
+
+@pytest.mark.parametrize("split,rounds,rows", [(2, 3, 16), (1, 0, 4), (4, 8, 16)])
+def test_f16x3_schedules_equal(H, split, rounds, rows):
+    """Split-fp16 scoring under other per-stage schedules (frame groups on
+    forked streams, NMS rounds, scoring rows per item): the same detections
+    in every field as the single-group schedule; a request for the fused
+    schedule runs the per-stage one."""
+    wl = synth.config1(seed=27, n=12)
+    fr, W, b = cu(wl.frames), cu(wl.W), cu(wl.b)
+    base = {"fused": 0, "queues": 8, "wg_per_queue": 32, "lag_f": 1, "lag_s": 2, "stagger": 0, "split": 1,
+            "nms_rounds": 3, "score_rows": 16}
+    print(f"f16x3 split={split} rounds={rounds} rows={rows}", flush=True)
+    out = []
+    for t in (base, {**base, "split": split, "nms_rounds": rounds, "score_rows": rows}, {**base, "fused": 1}):
+        H.tuning_set(480, 640, 1, 12, 5, t)
+        try:
+            out.append(H.detect_batch(fr, W, b, arith=H.ARITH_F16X3))
+        finally:
+            H.tuning_set(480, 640, 1, 12, 5, None)
+    (ref, nref) = out[0]
+    for got, n in out[1:]:
+        assert np.array_equal(n, nref)
+        for i in range(12):
+            assert _same(got[i], ref[i]), i
+
+
+def test_f16x3_clips_in_flight(H):
+    """Three clips in flight with split-fp16 scoring: every graph gives the
+    detections of detect_batch on its own buffer."""
+    clips = [synth.config1(seed=50 + k, n=4) for k in range(3)]
+    W, b = cu(clips[0].W), cu(clips[0].b)
+    frames = [cu(c.frames) for c in clips]
+    refs = [H.detect_batch(f, W, b, arith=H.ARITH_F16X3) for f in frames]
+    print("f16x3: 3 clips in flight", flush=True)
+    cs = H.ClipStream(frames, W, b, arith=H.ARITH_F16X3)
+    try:
+        for _ in range(7):
+            cs.launch()
+        cs.synchronize()
+        torch.cuda.synchronize()
+        for g, (ref, nref) in zip(cs.graphs, refs):
+            got, n = H.dets_to_numpy(g.dets, g.n_dets)
+            assert np.array_equal(n, nref)
+            for i in range(len(ref)):
+                assert _same(got[i], ref[i]), i
+    finally:
+        cs.close()
