@@ -115,6 +115,7 @@ int hog_pipeline_create(hog_pipeline** out, const hog_params* prm, const hog_pip
     if (!out || !prm || !cfg || !filters || !bias) return HOG_E_INVAL;
     *out = nullptr;
     if (prm->regions) return HOG_E_INVAL;
+    if (prm->score_arith != HOG_ARITH_F32 && prm->score_arith != HOG_ARITH_F16X3) return HOG_E_INVAL;
     const hog_pipeline_config& c = *cfg;
     if (c.batch < 1 || c.batch > 1024 || c.depth < 1 || c.depth > 16 || c.cap < 1 || c.cap > HOG_MAX_DETS ||
         c.consumer_threads < 1 || c.consumer_threads > 64 || (c.staging != 0 && c.staging != 1))

@@ -192,6 +192,8 @@ def test_pipeline_config_checked_before_any_allocation(L):
     cfg = hog355.hog_pipeline_config(480, 640, 4, 2, 16, 1, 1, 0, hog355.CONSUMER_FN(), None)
     prm_r = hog355.hog_params(1, 0.0, 0.5, 0, 1)   # regions are not supported by the pipeline
     assert L.hog_pipeline_create(ctypes.byref(v()), ctypes.byref(prm_r), ctypes.byref(cfg), v(1), v(1), 5) == -1
+    prm_a = hog355.hog_params(1, 0.0, 0.5, 0, None, 5)   # no such scoring arithmetic
+    assert L.hog_pipeline_create(ctypes.byref(v()), ctypes.byref(prm_a), ctypes.byref(cfg), v(1), v(1), 5) == -1
     assert L.hog_pipeline_submit(None, v(1), 1, 0) == -1 and L.hog_pipeline_drain(None) == -1
 
 
