@@ -113,8 +113,8 @@ typedef struct hog_params {
                           three fp16 matrix products of split operands,
                           v = fp16(v) + 2^-11 fp16((v - fp16(v)) 2^11),
                           summed in FP32 (Ootomo and Yokota 2022): about
-                          FP32 accuracy (every product within 2^-22
-                          relative) at a fraction of the FP32 matrix time.
+                          FP32 accuracy (operands kept to 2^-23 |v| +
+                          2^-36) at a fraction of the FP32 matrix time.
                           Filter weights must lie below 2^15 in magnitude
                           (larger ones give non-finite scores).  Applies
                           to full filters in hog_detect, hog_detect_batch*,

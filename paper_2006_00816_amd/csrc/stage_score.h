@@ -281,10 +281,10 @@ __device__ __forceinline__ void score_row(const DevLevel& L, int k, int r, const
 // ------------------------- FP32-accurate scoring from fp16 matrix products
 // With HOG_ARITH_F16X3 every operand v (feature or weight) is split into
 // v_hi = fp16(v) and v_lo = fp16((v - v_hi) 2^11), both rounded to
-// nearest, so that v = v_hi + 2^-11 v_lo to within 2^-24 |v| (below 2^15
-// in magnitude; v - v_hi and the scaling are exact in FP32).  A product is
+// nearest, so that v = v_hi + 2^-11 v_lo to within 2^-23 |v| + 2^-36 (for
+// |v| below 2^15; v - v_hi and the scaling are exact in FP32).  A product is
 //   x w = x_hi w_hi + 2^-11 (x_hi w_lo + x_lo w_hi) + 2^-22 x_lo w_lo,
-// of which the last term (at most 2^-24 |x w|) is dropped.  Products of
+// of which the last term (at most 2^-22 |x w|) is dropped.  Products of
 // fp16 values are exact in FP32 and v_mfma_f32_16x16x32_f16 sums them in
 // FP32, the first term into one accumulator and the two cross terms into
 // another: P = acc_hi + 2^-11 acc_cross.  This is the split-operand
