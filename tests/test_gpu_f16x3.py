@@ -168,3 +168,26 @@ def test_f16x3_clips_in_flight(H):
                 assert _same(got[i], ref[i]), i
     finally:
         cs.close()
+
+
+@pytest.mark.parametrize("n,nf", [(2, 5), (3, 7)])
+def test_f16x3_regions_and_min_face(H, n, nf):
+    """Split-fp16 scoring with per-frame search regions (rows and tiles
+    narrowed per window row) and with the largest scale skipped: the GPU
+    NMS equals the oracle's over the split-fp16 candidates under the same
+    mask, and the end-to-end decisions are the oracle's outside near ties."""
+    from test_gpu_region import REGIONS, check_frame
+    wl = synth.config1(seed=60 + n, n=n)
+    Wn, bn = synth.filters(range(210, 210 + nf))
+    names = ["box", "box_levels", "corner"][:n]
+    regs = [REGIONS[k](wl.frames[0].shape) for k in names]
+    dets, nd = H.detect_batch(cu(wl.frames), cu(Wn), cu(bn), regions=H.region_tensor(regs), arith=H.ARITH_F16X3)
+    for i in range(n):
+        print(f"f16x3 region {names[i]} n={n} nf={nf}: {nd[i]} kept", flush=True)
+        check_frame(H, wl.frames[i], Wn, bn, 1, dets[i], int(nd[i]), region=regs[i], label=f"f16x3 {names[i]}",
+                    arith=H.ARITH_F16X3)
+    dets, nd = H.detect_batch(cu(wl.frames), cu(Wn), cu(bn), min_face=96, arith=H.ARITH_F16X3)
+    for i in range(n):
+        assert np.all(dets[i]["level"] >= 1)
+        check_frame(H, wl.frames[i], Wn, bn, 1, dets[i], int(nd[i]), min_face=96, label=f"f16x3 mf96 {i}",
+                    arith=H.ARITH_F16X3)

@@ -146,11 +146,12 @@ def test_scores_parity(H, name, nf):
 
 
 # -------------------------------------------------------------- detection
-def gpu_candidates(H, frame, Wn, bn, u, thresh=0.0):
-    """Candidates from the GPU dense scores, with the GPU's float32 scores."""
+def gpu_candidates(H, frame, Wn, bn, u, thresh=0.0, arith=None):
+    """Candidates from the GPU dense scores, with the GPU's float32 scores
+    (arith: the scoring arithmetic, as hog_scores_arith; None: hog_scores)."""
     rows = []
     levels = oracle.pyramid(*frame.shape, u)
-    for (glv, gS) in H.scores(cu(frame), cu(Wn), cu(bn), u):
+    for (glv, gS) in H.scores(cu(frame), cu(Wn), cu(bn), u, arith=arith):
         s = gS.cpu().numpy()
         f, r, c = np.nonzero(s > np.float32(thresh))
         lv = levels[glv["k"]]

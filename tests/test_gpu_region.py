@@ -37,8 +37,8 @@ def masked(cands, frame_shape, u, min_face=0, region=None):
     return cands[ok]
 
 
-def check_frame(Hm, frame, Wn, bn, u, dets, n, min_face=0, region=None, label=""):
-    cg = masked(gpu_candidates(Hm, frame, Wn, bn, u), frame.shape, u, min_face, region)
+def check_frame(Hm, frame, Wn, bn, u, dets, n, min_face=0, region=None, label="", arith=None):
+    cg = masked(gpu_candidates(Hm, frame, Wn, bn, u, arith=arith), frame.shape, u, min_face, region)
     kept = oracle.nms(cg, 0.5)
     assert n == len(kept) == len(dets), (label, n, len(kept), len(dets))
     assert det_key(dets) == cand_key(kept), label
