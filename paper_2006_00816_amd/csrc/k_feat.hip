@@ -9,7 +9,8 @@ namespace hog {
 template <bool F16>
 __global__ __launch_bounds__(FEAT_THREADS) void hog_feat_kernel(
     LevelTable T, const float* __restrict__ hist, float* __restrict__ feat, float* __restrict__ packed) {
-    feat_cell<F16>(T, hist, feat, packed, (int)blockIdx.y, (int)blockIdx.x, (int)threadIdx.x);
+    __shared__ uint4 stage[FEAT_THREADS * FPAD / 4];
+    feat_cell<F16>(T, hist, feat, packed, (int)blockIdx.y, (int)blockIdx.x, (int)threadIdx.x, stage);
 }
 
 hipError_t launch_feat(const LevelTable& T, int n, const float* hist, float* feat, float* packed,

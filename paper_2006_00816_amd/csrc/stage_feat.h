@@ -21,85 +21,105 @@ namespace hog {
 // parts fp16(F[c]), then the 32 low parts fp16((F[c] - hi) 2^11), both
 // rounded to nearest (zero cells are zero either way).
 // Block `blk` (of FEAT_THREADS cells, within one level) of a frame; thread
-// `tid` of the block.
+// `tid` of the block.  With `stage` (LDS, 64 x 8 uint4 per wave) the
+// wave's 64 cells, which are consecutive in the map, are exchanged through
+// LDS so that each store writes 1 KB of consecutive bytes (a cell's own
+// 128 bytes at a 128-byte lane stride would touch 64 lines per store).
 template <bool F16 = false>
 __device__ __forceinline__ void feat_cell(const LevelTable& T, const float* __restrict__ hist,
                                           float* __restrict__ feat, float* __restrict__ packed, int frame, int blk,
-                                          int tid) {
+                                          int tid, uint4* __restrict__ stage = nullptr) {
     const int k = HOG_FIND_LEVEL(T, blk, tf_off);
     const DevLevel& L = T.L[k];
     const int pw = L.cx + 2;
+    const int ncell = L.cy * pw;
     const int idx = (blk - L.tf_off) * FEAT_THREADS + tid;
-    if (idx >= L.cy * pw) return;
     const int i = idx / pw, j = idx - i * pw;
-    float4* out = reinterpret_cast<float4*>(feat + (long long)frame * T.feat_frame + L.feat_off +
-                                            (long long)idx * FPAD);
-    if (j >= L.cx) {
+    float* const fmap = feat + (long long)frame * T.feat_frame + L.feat_off;
+    // the cell's 128 bytes; zero for the padding cells after each row
+    uint4 q4[FPAD / 4];
 #pragma unroll
-        for (int q = 0; q < FPAD / 4; ++q) out[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-        return;
-    }
-    const float* H = hist + ((long long)frame * T.hist_frame + L.hist_off) * HSTRIDE;
-    const float4* hc = reinterpret_cast<const float4*>(H + ((long long)i * L.cx + j) * HSTRIDE);
-    float h[20];
+    for (int q = 0; q < FPAD / 4; ++q) q4[q] = make_uint4(0u, 0u, 0u, 0u);
+    if (idx < ncell && j < L.cx) {
+        const float* H = hist + ((long long)frame * T.hist_frame + L.hist_off) * HSTRIDE;
+        const float4* hc = reinterpret_cast<const float4*>(H + ((long long)i * L.cx + j) * HSTRIDE);
+        float h[20];
 #pragma unroll
-    for (int q = 0; q < 5; ++q) {
-        const float4 v = hc[q];
-        h[4 * q] = v.x; h[4 * q + 1] = v.y; h[4 * q + 2] = v.z; h[4 * q + 3] = v.w;
-    }
-    auto E = [&](int y, int x) -> float {
-        return (y >= 0 && y < L.cy && x >= 0 && x < L.cx) ? H[((long long)y * L.cx + x) * HSTRIDE + NBINS]
-                                                          : 0.f;
-    };
-    const float e0 = h[NBINS];
-    const float eu = E(i - 1, j), ed = E(i + 1, j), el = E(i, j - 1), er = E(i, j + 1);
-    const float eul = E(i - 1, j - 1), eur = E(i - 1, j + 1), edl = E(i + 1, j - 1), edr = E(i + 1, j + 1);
-    float n[4];
-    n[0] = 1.0f / sqrtf(e0 + eu + el + eul + 1e-4f);   // block (-1, -1)
-    n[1] = 1.0f / sqrtf(e0 + eu + er + eur + 1e-4f);   // block (-1, +1)
-    n[2] = 1.0f / sqrtf(e0 + ed + el + edl + 1e-4f);   // block (+1, -1)
-    n[3] = 1.0f / sqrtf(e0 + ed + er + edr + 1e-4f);   // block (+1, +1)
-    float F[FPAD];
-#pragma unroll
-    for (int c = 0; c < FPAD; ++c) F[c] = 0.f;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        float tsum = 0.f;
-#pragma unroll
-        for (int b = 0; b < NBINS; ++b) {
-            const float tv = fminf(h[b] * n[q], 0.2f);
-            F[b] += 0.5f * tv;
-            tsum += tv;
+        for (int q = 0; q < 5; ++q) {
+            const float4 v = hc[q];
+            h[4 * q] = v.x; h[4 * q + 1] = v.y; h[4 * q + 2] = v.z; h[4 * q + 3] = v.w;
         }
+        auto E = [&](int y, int x) -> float {
+            return (y >= 0 && y < L.cy && x >= 0 && x < L.cx) ? H[((long long)y * L.cx + x) * HSTRIDE + NBINS]
+                                                              : 0.f;
+        };
+        const float e0 = h[NBINS];
+        const float eu = E(i - 1, j), ed = E(i + 1, j), el = E(i, j - 1), er = E(i, j + 1);
+        const float eul = E(i - 1, j - 1), eur = E(i - 1, j + 1), edl = E(i + 1, j - 1), edr = E(i + 1, j + 1);
+        float n[4];
+        n[0] = 1.0f / sqrtf(e0 + eu + el + eul + 1e-4f);   // block (-1, -1)
+        n[1] = 1.0f / sqrtf(e0 + eu + er + eur + 1e-4f);   // block (-1, +1)
+        n[2] = 1.0f / sqrtf(e0 + ed + el + edl + 1e-4f);   // block (+1, -1)
+        n[3] = 1.0f / sqrtf(e0 + ed + er + edr + 1e-4f);   // block (+1, +1)
+        float F[FPAD];
 #pragma unroll
-        for (int o = 0; o < NORIENT; ++o) F[NBINS + o] += 0.5f * fminf((h[o] + h[o + NORIENT]) * n[q], 0.2f);
-        F[27 + q] = 0.23570226039551584f * tsum;   // 1/sqrt(18)
-    }
-    if (F16) {
-        _Float16 hl[2 * FPAD];
+        for (int c = 0; c < FPAD; ++c) F[c] = 0.f;
 #pragma unroll
-        for (int c = 0; c < FPAD; ++c) {
-            // both parts from the stored FP32 feature: the empty asm keeps
-            // the compiler from forming the high part with a mixed-precision
-            // FMA from the unrounded last sum
-            float f = F[c];
-            asm volatile("" : "+v"(f));
-            const _Float16 hi = (_Float16)f;
-            hl[c] = hi;
-            hl[FPAD + c] = (_Float16)((f - (float)hi) * 2048.f);
+        for (int q = 0; q < 4; ++q) {
+            float tsum = 0.f;
+#pragma unroll
+            for (int b = 0; b < NBINS; ++b) {
+                const float tv = fminf(h[b] * n[q], 0.2f);
+                F[b] += 0.5f * tv;
+                tsum += tv;
+            }
+#pragma unroll
+            for (int o = 0; o < NORIENT; ++o) F[NBINS + o] += 0.5f * fminf((h[o] + h[o + NORIENT]) * n[q], 0.2f);
+            F[27 + q] = 0.23570226039551584f * tsum;   // 1/sqrt(18)
         }
-        uint4 q4[FPAD / 4];
-        __builtin_memcpy(q4, hl, sizeof q4);
+        if (F16) {
+            _Float16 hl[2 * FPAD];
 #pragma unroll
-        for (int q = 0; q < FPAD / 4; ++q) reinterpret_cast<uint4*>(out)[q] = q4[q];
-    } else {
+            for (int c = 0; c < FPAD; ++c) {
+                // both parts from the stored FP32 feature: the empty asm keeps
+                // the compiler from forming the high part with a mixed-precision
+                // FMA from the unrounded last sum
+                float f = F[c];
+                asm volatile("" : "+v"(f));
+                const _Float16 hi = (_Float16)f;
+                hl[c] = hi;
+                hl[FPAD + c] = (_Float16)((f - (float)hi) * 2048.f);
+            }
+            __builtin_memcpy(q4, hl, sizeof q4);
+        } else {
+            __builtin_memcpy(q4, F, sizeof q4);
+        }
+        if (packed) {
+            float* p = packed + L.pk_off + ((long long)i * L.cx + j) * NFEAT;
 #pragma unroll
-        for (int q = 0; q < FPAD / 4; ++q) out[q] = make_float4(F[4 * q], F[4 * q + 1], F[4 * q + 2], F[4 * q + 3]);
+            for (int c = 0; c < NFEAT; ++c) p[c] = F[c];
+        }
     }
-    if (packed) {
-        float* p = packed + L.pk_off + ((long long)i * L.cx + j) * NFEAT;
+    if (stage) {
+        const int lane = tid & 63;
+        const int base = idx - lane;   // the wave's first cell
+        uint4* __restrict__ w = stage + (tid >> 6) * (64 * FPAD / 4);
+        // 16-byte slots of a cell rotated by the cell's low bits: the eight
+        // lanes of one store phase hit different banks
 #pragma unroll
-        for (int c = 0; c < NFEAT; ++c) p[c] = F[c];
+        for (int q = 0; q < FPAD / 4; ++q) w[lane * 8 + (q ^ (lane & 7))] = q4[q];
+        wave_lds_order();
+        uint4* __restrict__ out = reinterpret_cast<uint4*>(fmap) + (long long)base * (FPAD / 4);
+#pragma unroll
+        for (int r = 0; r < FPAD / 4; ++r) {
+            const int c = lane + 64 * r, cell = c >> 3, part = c & 7;
+            const uint4 v = w[cell * 8 + (part ^ (cell & 7))];
+            if (base + cell < ncell) out[c] = v;
+        }
+    } else if (idx < ncell) {
+        uint4* __restrict__ out = reinterpret_cast<uint4*>(fmap + (long long)idx * FPAD);
+#pragma unroll
+        for (int q = 0; q < FPAD / 4; ++q) out[q] = q4[q];
     }
 }
 
