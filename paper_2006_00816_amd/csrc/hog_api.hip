@@ -1105,10 +1105,15 @@ int hog_level_maps(const uint8_t* frame, int h, int w, int pitch, int upsample, 
             return launch_hist(T, frame, 0, pitch, 1, at<float>(ws, P.o_hist), nullptr, casc, s);
         }));
         const DevLevel& L = T.L[level];
+        // part-major records: bins 4q .. 4q + 3 of every cell from plane q
+        const size_t ncell = (size_t)L.cy * L.cx;
         const float* src = at<float>(ws, P.o_hist) + (size_t)L.hist_off * HSTRIDE;
-        if (hipMemcpy2DAsync(hist, NBINS * sizeof(float), src, HSTRIDE * sizeof(float), NBINS * sizeof(float),
-                             (size_t)L.cy * L.cx, hipMemcpyDeviceToDevice, s) != hipSuccess)
-            return HOG_E_HIP;
+        for (int q = 0; q < 5; ++q) {
+            const int nb = std::min(4, NBINS - 4 * q);
+            if (hipMemcpy2DAsync(hist + 4 * q, NBINS * sizeof(float), src + 4 * q * ncell, 4 * sizeof(float),
+                                 nb * sizeof(float), ncell, hipMemcpyDeviceToDevice, s) != hipSuccess)
+                return HOG_E_HIP;
+        }
     }
     return HOG_OK;
 }

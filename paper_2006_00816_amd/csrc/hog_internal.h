@@ -14,7 +14,12 @@ constexpr int NORIENT = 9;     // unsigned orientations
 constexpr int WIN = 10;        // window side in cells
 constexpr int NFEAT = 31;      // features per cell
 constexpr int FPAD = 32;       // features per cell in the internal layout (31 + zero)
-constexpr int HSTRIDE = 20;    // internal histogram record: 18 bins, energy, zero
+// Internal histogram record of a cell: 18 bins, energy, zero (20 floats).
+// A level's records are stored part-major: plane q (q = 0..4) holds part q
+// (floats 4q .. 4q + 3) of every cell as one float4, cells in row-major
+// order, so that a wave reading part q of consecutive cells reads
+// consecutive bytes.
+constexpr int HSTRIDE = 20;
 constexpr int MIN_SIDE = 80;
 constexpr int SCALE_NUM = 5, SCALE_DEN = 6;   // pyramid step 5/6
 constexpr int SIG_BITS = 40;   // fractional bits of the fixed-point inverse scale

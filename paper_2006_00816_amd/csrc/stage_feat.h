@@ -41,17 +41,21 @@ __device__ __forceinline__ void feat_cell(const LevelTable& T, const float* __re
 #pragma unroll
     for (int q = 0; q < FPAD / 4; ++q) q4[q] = make_uint4(0u, 0u, 0u, 0u);
     if (idx < ncell && j < L.cx) {
-        const float* H = hist + ((long long)frame * T.hist_frame + L.hist_off) * HSTRIDE;
-        const float4* hc = reinterpret_cast<const float4*>(H + ((long long)i * L.cx + j) * HSTRIDE);
+        // part-major records (plane q holds part q of every cell): the
+        // lanes of a wave read consecutive float4s of each plane
+        const long long ncell = (long long)L.cy * L.cx;
+        const float4* H4 = reinterpret_cast<const float4*>(hist + ((long long)frame * T.hist_frame + L.hist_off) * HSTRIDE);
+        const float4* hc = H4 + (long long)i * L.cx + j;
         float h[20];
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-            const float4 v = hc[q];
+            const float4 v = hc[q * ncell];
             h[4 * q] = v.x; h[4 * q + 1] = v.y; h[4 * q + 2] = v.z; h[4 * q + 3] = v.w;
         }
+        // the energy is float 2 of part 4 (bins 16, 17, energy, 0)
+        const float* E4 = reinterpret_cast<const float*>(H4 + 4 * ncell) + 2;
         auto E = [&](int y, int x) -> float {
-            return (y >= 0 && y < L.cy && x >= 0 && x < L.cx) ? H[((long long)y * L.cx + x) * HSTRIDE + NBINS]
-                                                              : 0.f;
+            return (y >= 0 && y < L.cy && x >= 0 && x < L.cx) ? E4[((long long)y * L.cx + x) * 4] : 0.f;
         };
         const float e0 = h[NBINS];
         const float eu = E(i - 1, j), ed = E(i + 1, j), el = E(i, j - 1), er = E(i, j + 1);

@@ -286,13 +286,15 @@ __device__ __forceinline__ void hist_tile(const LevelTable& T, const uint8_t* __
                 const float u = h[o] + h[o + NORIENT];
                 E = fmaf(u, u, E);
             }
-            float4* dst = reinterpret_cast<float4*>(
-                hist + ((long long)frame * T.hist_frame + L.hist_off + (long long)gi * L.cx + gj) * HSTRIDE);
+            // part-major records: part q of cell c at plane q, entry c
+            const long long ncell = (long long)L.cy * L.cx;
+            float4* dst = reinterpret_cast<float4*>(hist + ((long long)frame * T.hist_frame + L.hist_off) * HSTRIDE) +
+                          (long long)gi * L.cx + gj;
             dst[0] = make_float4(h[0], h[1], h[2], h[3]);
-            dst[1] = make_float4(h[4], h[5], h[6], h[7]);
-            dst[2] = make_float4(h[8], h[9], h[10], h[11]);
-            dst[3] = make_float4(h[12], h[13], h[14], h[15]);
-            dst[4] = make_float4(h[16], h[17], E, 0.f);
+            dst[ncell] = make_float4(h[4], h[5], h[6], h[7]);
+            dst[2 * ncell] = make_float4(h[8], h[9], h[10], h[11]);
+            dst[3 * ncell] = make_float4(h[12], h[13], h[14], h[15]);
+            dst[4 * ncell] = make_float4(h[16], h[17], E, 0.f);
         }
     }
 }
