@@ -14,6 +14,12 @@ constexpr int NORIENT = 9;     // unsigned orientations
 constexpr int WIN = 10;        // window side in cells
 constexpr int NFEAT = 31;      // features per cell
 constexpr int FPAD = 32;       // features per cell in the internal layout (31 + zero)
+// Internal feature maps: per level row, two half-planes of 16 floats per
+// cell (channels 0..15 of every cell of the padded row, then channels
+// 16..31), so that a wave reading one half of 16 consecutive cells reads
+// 1 KB of consecutive bytes.  Element (row r, cell x, channel ch) is at
+// r * FPAD * (cx + 2) + (ch / 16) * 16 * (cx + 2) + 16 x + ch % 16.
+constexpr int FHALF = FPAD / 2;
 // Internal histogram record of a cell: 18 bins, energy, zero (20 floats).
 // A level's records are stored part-major: plane q (q = 0..4) holds part q
 // (floats 4q .. 4q + 3) of every cell as one float4, cells in row-major

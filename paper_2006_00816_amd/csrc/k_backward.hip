@@ -29,12 +29,13 @@ __global__ __launch_bounds__(256) void hog_window_score_kernel(LevelTable T, int
     const DevLevel& L = T.L[w.level];
     const float* F = feat + (long long)w.frame * T.feat_frame + L.feat_off;
     const float* Wf = W + (long long)w.filter * WIN * WIN * NFEAT;
-    const int pitch = (L.cx + 2) * FPAD;
+    const int pitch = (L.cx + 2) * FPAD, hp = (L.cx + 2) * FHALF;
     float acc = 0.f;
     for (int e = lane; e < WIN * WIN * NFEAT; e += 64) {
         const int ch = e % NFEAT, cell = e / NFEAT;
         const int dr = cell / WIN, dc = cell % WIN;
-        acc = fmaf(Wf[e], F[(long long)(w.row + dr) * pitch + (w.col + dc) * FPAD + ch], acc);
+        // feature-map half-planes: channels 0..15, then 16..31 of the row
+        acc = fmaf(Wf[e], F[(long long)(w.row + dr) * pitch + (ch >> 4) * hp + (w.col + dc) * FHALF + (ch & 15)], acc);
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);

@@ -14,7 +14,9 @@ namespace hog {
 //   F[18 + o] = 1/2 sum_k T((h_o + h_{o+9}) n_k)   (9 unsigned)
 //   F[27 + k] = 1/sqrt(18) sum_b T(h_b n_k)        (4 block energies)
 // The padded layout stores 32 floats per cell (channel 31 = 0) and two
-// zero cells after each row, which the scorer reads past the last column.
+// zero cells after each row, which the scorer reads past the last column,
+// in two half-planes per row (channels 0..15 of the row's cells, then
+// 16..31).
 // `packed`, when non-null, also receives [cy][cx][31] at the level's
 // packed offset (single frame).  F16: the cell's 128 bytes hold instead
 // the split fp16 operands of the scorer (HOG_ARITH_F16X3): the 32 high
@@ -104,6 +106,11 @@ __device__ __forceinline__ void feat_cell(const LevelTable& T, const float* __re
             for (int c = 0; c < NFEAT; ++c) p[c] = F[c];
         }
     }
+    // 16-byte part q of cell (i, j): half-plane q / 4 of row i
+    auto part_at = [&](int ci, int cj, int q) {
+        return reinterpret_cast<uint4*>(fmap + (long long)ci * pw * FPAD + (q >> 2) * (pw * FHALF) + cj * FHALF) +
+               (q & 3);
+    };
     if (stage) {
         const int lane = tid & 63;
         const int base = idx - lane;   // the wave's first cell
@@ -113,17 +120,21 @@ __device__ __forceinline__ void feat_cell(const LevelTable& T, const float* __re
 #pragma unroll
         for (int q = 0; q < FPAD / 4; ++q) w[lane * 8 + (q ^ (lane & 7))] = q4[q];
         wave_lds_order();
-        uint4* __restrict__ out = reinterpret_cast<uint4*>(fmap) + (long long)base * (FPAD / 4);
+        // store r: half-plane r / 4, cells 16 (r % 4) .. + 15 of the wave, four
+        // lanes per cell, so that the lanes write consecutive bytes of a row
 #pragma unroll
         for (int r = 0; r < FPAD / 4; ++r) {
-            const int c = lane + 64 * r, cell = c >> 3, part = c & 7;
+            const int cell = 16 * (r & 3) + (lane >> 2), part = 4 * (r >> 2) + (lane & 3);
             const uint4 v = w[cell * 8 + (part ^ (cell & 7))];
-            if (base + cell < ncell) out[c] = v;
+            const int ci = base + cell;
+            if (ci < ncell) {
+                const int ri = ci / pw;
+                *part_at(ri, ci - ri * pw, part) = v;
+            }
         }
     } else if (idx < ncell) {
-        uint4* __restrict__ out = reinterpret_cast<uint4*>(fmap + (long long)idx * FPAD);
 #pragma unroll
-        for (int q = 0; q < FPAD / 4; ++q) out[q] = q4[q];
+        for (int q = 0; q < FPAD / 4; ++q) *part_at(i, j, q) = q4[q];
     }
 }
 

@@ -181,7 +181,9 @@ __device__ __forceinline__ void score_row(const DevLevel& L, int k, int r, const
                                           unsigned long long* __restrict__ PKfr, int atomic_key, int lane,
                                           int t_begin, int t_end, int c_lo, int c_hi) {
     const int g4 = lane >> 4, j = lane & 15;
-    const int pitch = (L.cx + 2) * FPAD;
+    // row pitch and half-plane stride of the feature maps (channels 0..15
+    // of the row's cells, then 16..31)
+    const int pitch = (L.cx + 2) * FPAD, hp = (L.cx + 2) * FHALF;
     const float* __restrict__ Fr = Ffr + L.feat_off + (long long)r * pitch + 4 * g4;
     const int f0 = grp * FGROUP + g4, f1 = f0 + 4;
     const bool f0ok = f0 < nf, f1ok = XTRA && g4 == 0;
@@ -196,9 +198,9 @@ __device__ __forceinline__ void score_row(const DevLevel& L, int k, int r, const
     // tile's epilogue runs
     float4 a0n, a1n;
     {
-        const float* __restrict__ a = Fr + min(16 * t_first + j, L.cx + 1) * FPAD;
+        const float* __restrict__ a = Fr + min(16 * t_first + j, L.cx + 1) * FHALF;
         a0n = *reinterpret_cast<const float4*>(a);
-        a1n = *reinterpret_cast<const float4*>(a + 16);
+        a1n = *reinterpret_cast<const float4*>(a + hp);
     }
 
     for (int t = t_first; t < ntiles; ++t) {
@@ -210,9 +212,9 @@ __device__ __forceinline__ void score_row(const DevLevel& L, int k, int r, const
         // The operand of K chunk kc + 2 is loaded while chunk kc computes;
         // the MFMAs of one chunk alternate between the N tiles so that
         // consecutive ones are independent.
-        const float* __restrict__ a = Fr + min(16 * t + j, L.cx + 1) * FPAD;
+        const float* __restrict__ a = Fr + min(16 * t + j, L.cx + 1) * FHALF;
         auto load_a = [&](int kc) {
-            return *reinterpret_cast<const float4*>(a + (kc >> 1) * pitch + 16 * (kc & 1));
+            return *reinterpret_cast<const float4*>(a + (kc >> 1) * pitch + (kc & 1) * hp);
         };
         float4 av[SC_KC];
         av[0] = a0n;
@@ -267,9 +269,9 @@ __device__ __forceinline__ void score_row(const DevLevel& L, int k, int r, const
             ring[49 * SC_RSTR + j] = x9;
         }
         if (t + 1 < ntiles) {
-            const float* __restrict__ an = Fr + min(16 * (t + 1) + j, L.cx + 1) * FPAD;
+            const float* __restrict__ an = Fr + min(16 * (t + 1) + j, L.cx + 1) * FHALF;
             a0n = *reinterpret_cast<const float4*>(an);
-            a1n = *reinterpret_cast<const float4*>(an + 16);
+            a1n = *reinterpret_cast<const float4*>(an + hp);
         }
         wave_lds_order();
 
@@ -314,9 +316,9 @@ __device__ __forceinline__ void score_row16(const DevLevel& L, int k, int r, con
                                             int t_begin, int t_end, int c_lo, int c_hi) {
     static_assert(!XTRA || NT == 4, "a group of 5 filters needs 4 N tiles");
     const int g4 = lane >> 4, j = lane & 15;
-    const int pitch = (L.cx + 2) * FPAD;
-    // the cell's hi halves of channels 8 g4 .. 8 g4 + 7 at float 4 g4,
-    // the lo halves 16 floats further
+    const int pitch = (L.cx + 2) * FPAD, hp = (L.cx + 2) * FHALF;
+    // the cell's hi halves of channels 8 g4 .. 8 g4 + 7 at float 4 g4 of its
+    // 16 floats in the first half-plane, the lo halves in the second
     const float* __restrict__ Fr = Ffr + L.feat_off + (long long)r * pitch + 4 * g4;
     const int f0 = grp * FGROUP + g4, f1 = f0 + 4;
     const bool f0ok = f0 < nf, f1ok = XTRA && g4 == 0;
@@ -327,7 +329,7 @@ __device__ __forceinline__ void score_row16(const DevLevel& L, int k, int r, con
     const int t_first = max(t_begin - 1, 0);
     float carry0 = 0.f, carry1 = 0.f;
     for (int t = t_first; t < t_end; ++t) {
-        const float* __restrict__ a = Fr + min(16 * t + j, L.cx + 1) * FPAD;
+        const float* __restrict__ a = Fr + min(16 * t + j, L.cx + 1) * FHALF;
         floatx4 ah[NT], ac[NT];
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) ah[nt] = ac[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -336,13 +338,13 @@ __device__ __forceinline__ void score_row16(const DevLevel& L, int k, int r, con
 #pragma unroll
         for (int d = 0; d < 2; ++d) {
             x[d][0] = *reinterpret_cast<const uint4*>(a + d * pitch);
-            x[d][1] = *reinterpret_cast<const uint4*>(a + d * pitch + 16);
+            x[d][1] = *reinterpret_cast<const uint4*>(a + d * pitch + hp);
         }
 #pragma unroll
         for (int dr = 0; dr < WIN; ++dr) {
             if (dr + 2 < WIN) {
                 x[(dr + 2) % 3][0] = *reinterpret_cast<const uint4*>(a + (dr + 2) * pitch);
-                x[(dr + 2) % 3][1] = *reinterpret_cast<const uint4*>(a + (dr + 2) * pitch + 16);
+                x[(dr + 2) % 3][1] = *reinterpret_cast<const uint4*>(a + (dr + 2) * pitch + hp);
             }
             const halfx8 hi = __builtin_bit_cast(halfx8, x[dr % 3][0]);
             const halfx8 lo = __builtin_bit_cast(halfx8, x[dr % 3][1]);
@@ -500,7 +502,7 @@ __device__ __forceinline__ void score_row_sep(const DevLevel& L, int k, int r, c
                                               int atomic_key, int lane, int t_begin, int t_end, int c_lo,
                                               int c_hi) {
     const int g4 = lane >> 4, j = lane & 15;
-    const int pitch = (L.cx + 2) * FPAD;
+    const int pitch = (L.cx + 2) * FPAD, hp = (L.cx + 2) * FHALF;
     const float* __restrict__ Fr = Ffr + L.feat_off + (long long)r * pitch + 4 * g4;
     const int fg = min(FGROUP, nf - grp * FGROUP);
     const int f0 = grp * FGROUP + g4, f1 = f0 + 4;
@@ -511,7 +513,7 @@ __device__ __forceinline__ void score_row_sep(const DevLevel& L, int k, int r, c
     const int t_first = max(t_begin - 1, 0);
     float carry0 = 0.f, carry1 = 0.f;
     for (int t = t_first; t < t_end; ++t) {
-        const float* __restrict__ a = Fr + min(16 * t + j, L.cx + 1) * FPAD;
+        const float* __restrict__ a = Fr + min(16 * t + j, L.cx + 1) * FHALF;
         // the K chunks (channels 0..15, 16..31) one after the other, so that
         // only one chunk's ten operands are live; the five filters'
         // accumulators carry over (a filter past the group's end has zero
@@ -523,7 +525,7 @@ __device__ __forceinline__ void score_row_sep(const DevLevel& L, int k, int r, c
         for (int kc = 0; kc < 2; ++kc) {
             float4 av[WIN];
 #pragma unroll
-            for (int dr = 0; dr < WIN; ++dr) av[dr] = *reinterpret_cast<const float4*>(a + dr * pitch + 16 * kc);
+            for (int dr = 0; dr < WIN; ++dr) av[dr] = *reinterpret_cast<const float4*>(a + dr * pitch + kc * hp);
 #pragma unroll
             for (int f = 0; f < FGROUP; ++f) {
                 if (f >= fg) break;
