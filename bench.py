@@ -440,7 +440,7 @@ def batched_leg(hog355, frames, Wt, bt, args, kw=None):
         cands = [{**staged, "split": sp, "nms_rounds": nr, "score_rows": rows}
                  for sp in (1, 2) for nr in (0, 1, 2, 3) for rows in (4, 16)]
         best = None
-        for depth in ((2, 3) if args.in_flight == 0 else (args.in_flight,)):
+        for depth in ((2, 3, 4) if args.in_flight == 0 else (args.in_flight,)):
             fl = [frames] + [frames.clone() for _ in range(depth - 1)]
             t, ms = hog355.tune_clip_stream(fl, Wt, bt, cands)
             if best is None or ms < best[2]:
@@ -621,7 +621,7 @@ def main():
     ap.add_argument("--schedule", choices=("auto", "staged", "fused"), default="auto",
                     help="auto: run the library's autotuner on the clip first")
     ap.add_argument("--in-flight", type=int, default=0,
-                    help="clips in flight for the throughput loop (auto schedule only): 0 picks 2 or 3, 1 is one "
+                    help="clips in flight for the throughput loop (auto schedule only): 0 picks 2, 3 or 4, 1 is one "
                          "captured graph replayed on one stream")
     ap.add_argument("--separable-rank", type=int, default=1,
                     help="also time the clip with separable filters of this rank (0: skip)")
