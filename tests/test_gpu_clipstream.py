@@ -21,7 +21,7 @@ def _check_graph(H, g, ref, nref):
         assert _same(got[i], ref[i]), i
 
 
-@pytest.mark.parametrize("depth", [2, 3])
+@pytest.mark.parametrize("depth", [2, 3, 4])
 def test_clips_in_flight_equal_detect_batch(H, depth):
     # different clips in the buffers, so that a graph reading another's
     # buffer or workspace would show
