@@ -521,13 +521,15 @@ int score_stage(const Plan& P, int m, const float* feat, const Bank& bank, float
 // histograms -> features -> scores -> NMS for frames lo .. lo + m - 1.
 // `mark` (if any) is recorded after the histograms (stagger 1) or after
 // the scores (stagger 2), for the next group of a staggered split.
+// `setup` (if any): the call's set-up, run by extra workgroups of the
+// histogram launch.
 int staged_chain(const Plan& P, int m, const FrameBufs& b, long long fstride, int pitch, const hog_params* prm,
                  const Bank& bank, int cap, int rounds, int score_rows, void* ws, hipStream_t s,
-                 hipEvent_t mark = nullptr, int stagger = 0) {
+                 hipEvent_t mark = nullptr, int stagger = 0, const SetupArgs* setup = nullptr) {
     const LevelTable& T = P.T;
     HOG_TRY(run_cascade(P, m, b.frames, fstride, pitch, b.casc, s));
     HOG_TRY(timed("hist", s, [&] {
-        return launch_hist(T, b.frames, fstride, pitch, m, b.hist, b.regions, b.casc, s);
+        return launch_hist(T, b.frames, fstride, pitch, m, b.hist, b.regions, b.casc, s, setup);
     }));
     if (mark && stagger == 1 && hipEventRecord(mark, s) != hipSuccess) return HOG_E_HIP;
     HOG_TRY(timed("feat", s, [&] { return launch_feat(T, m, b.hist, b.feat, nullptr, s, bank.f16x3); }));
@@ -558,6 +560,17 @@ int detect_sequence(const Plan& P, const hog_params* prm, const uint8_t* frames,
     }
     const bool multi = P.groups > 1;
     unsigned* sync = at<unsigned>(ws, P.o_sync);
+    const int parts = std::min(std::max(tune.split, 1), P.n);
+    if (!tune.fused && parts == 1) {
+        // one group: the set-up's work (first read by the scorer) runs in
+        // extra workgroups of the histogram launch, one launch fewer
+        const SetupArgs sa = setup_args(T, at<int4>(ws, P.o_taps), at<int2>(ws, P.o_boxes), filters, P.nf,
+                                        at<float4>(ws, P.o_bpack),
+                                        multi ? at<unsigned long long>(ws, P.o_key) : nullptr,
+                                        (long long)P.n * T.pos_frame, nullptr, 0, bank.f16x3);
+        return staged_chain(P, P.n, frame_bufs(P, ws, frames, fstride, dets, cap, n_dets, 0, regions), fstride,
+                            pitch, prm, bank, cap, tune.nms_rounds, tune.score_rows, ws, s, nullptr, 0, &sa);
+    }
     HOG_TRY(timed("geom", s, [&] {
         return launch_setup(T, at<int4>(ws, P.o_taps), at<int2>(ws, P.o_boxes), filters, P.nf,
                             at<float4>(ws, P.o_bpack), multi ? at<unsigned long long>(ws, P.o_key) : nullptr,
@@ -578,10 +591,6 @@ int detect_sequence(const Plan& P, const hog_params* prm, const uint8_t* frames,
         return nms_chain(P, P.n, frame_bufs(P, ws, frames, fstride, dets, cap, n_dets, 0), prm, cap, sync,
                          tune.nms_rounds, ws, s);
     }
-    const int parts = std::min(std::max(tune.split, 1), P.n);
-    if (parts == 1)
-        return staged_chain(P, P.n, frame_bufs(P, ws, frames, fstride, dets, cap, n_dets, 0, regions), fstride,
-                            pitch, prm, bank, cap, tune.nms_rounds, tune.score_rows, ws, s);
     // the frames in `parts` groups on forked streams: one group's NMS
     // overlaps another's histograms and scores.  Without the calling
     // thread's helper streams (hog_init) the groups run one after another

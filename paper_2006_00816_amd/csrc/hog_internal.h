@@ -162,13 +162,37 @@ __host__ __device__ inline unsigned int pack_window(int f, int k, int r, int c) 
     return ((unsigned)f << 27) | ((unsigned)k << 22) | ((unsigned)r << 11) | (unsigned)c;
 }
 
+// The per-call set-up (stage_setup.h): segment 0 the taps and box edges,
+// 1 the filter operands (split fp16 ones with f16x3), 2 cleared keys and
+// fused-kernel counters; m elements per segment.
+struct SetupArgs {
+    int4* taps;
+    int2* boxes;
+    const float* W;
+    int nf;
+    float4* bpack;
+    unsigned long long* keys;
+    long long nkeys;
+    unsigned* sync;
+    int nsync;
+    int f16x3;
+    long long m;
+    int segs;
+};
+SetupArgs setup_args(const LevelTable& T, int4* taps, int2* boxes, const float* filters, int nf, float4* bpack,
+                     unsigned long long* poskey_zero, long long poskey_count, unsigned* sync_zero, int sync_count,
+                     bool f16x3);
+
 // Launchers (host functions defined next to their kernels).
 hipError_t launch_setup(const LevelTable& T, int4* taps, int2* boxes,
                         const float* filters, int nf, float4* bpack,
                         unsigned long long* poskey_zero, long long poskey_count, unsigned* sync_zero,
                         int sync_count, hipStream_t s, bool f16x3 = false);
+// setup (optional): the set-up's work runs in extra workgroups of the
+// same launch (nothing the histograms read comes from it)
 hipError_t launch_hist(const LevelTable& T, const uint8_t* frames, long long fstride, int pitch,
-                       int n, float* hist, const hog_region* regions, const uint8_t* casc, hipStream_t s);
+                       int n, float* hist, const hog_region* regions, const uint8_t* casc, hipStream_t s,
+                       const SetupArgs* setup = nullptr);
 // One level of the recursive pyramid for n frames: the 8-bit image
 // [h_out][w_out] at dst_off of each frame's block of `casc`, scaled down by
 // 5/6 from the level image [h_in][w_in] at src_off (src_off < 0: the frame

@@ -3,6 +3,7 @@
 // Sec. V-A: image-scaling and gradient-histogram kernels), fused into one
 // kernel per tile of cells.
 #include "stage_hist.h"
+#include "stage_setup.h"
 
 namespace hog {
 
@@ -27,11 +28,17 @@ __device__ __forceinline__ bool hist_tile_needed(const LevelTable& T, int tile, 
 // ranges, one per XCD: block b runs on XCD b mod 8 (blocks are dealt to
 // the XCDs in turn), and takes item b / 8 of range b mod 8.  A frame's
 // tiles, which read overlapping frame rows, thus share one L2 instead of
-// every XCD fetching every frame.
+// every XCD fetching every frame.  Blocks from hist_blocks on do the
+// call's set-up instead (setup.segs > 0), HIST_THREADS elements each.
 __global__ __launch_bounds__(HIST_THREADS) void hog_hist_kernel(
     LevelTable T, int n, const uint8_t* __restrict__ frames, long long fstride, int pitch,
-    float* __restrict__ hist, const hog_region* __restrict__ regions, const uint8_t* __restrict__ casc) {
+    float* __restrict__ hist, const hog_region* __restrict__ regions, const uint8_t* __restrict__ casc,
+    int hist_blocks, SetupArgs setup) {
     __shared__ HistSmem sm;
+    if ((int)blockIdx.x >= hist_blocks) {
+        setup_flat(T, setup, (long long)(blockIdx.x - hist_blocks) * HIST_THREADS + threadIdx.x);
+        return;
+    }
     const long long items = (long long)T.th_total * n;
     const int x = (int)(blockIdx.x & 7);
     const long long lo = items * x / 8, hi = items * (x + 1) / 8;
@@ -45,13 +52,20 @@ __global__ __launch_bounds__(HIST_THREADS) void hog_hist_kernel(
 }
 
 hipError_t launch_hist(const LevelTable& T, const uint8_t* frames, long long fstride, int pitch, int n,
-                       float* hist, const hog_region* regions, const uint8_t* casc, hipStream_t s) {
+                       float* hist, const hog_region* regions, const uint8_t* casc, hipStream_t s,
+                       const SetupArgs* setup) {
     const long long items = (long long)T.th_total * n;
-    if (items <= 0) return hipSuccess;
+    if (items <= 0 && !setup) return hipSuccess;
     const long long per_xcd = (items + 7) / 8;
-    if (per_xcd * 8 > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(hog_hist_kernel, dim3((unsigned)(per_xcd * 8)), dim3(HIST_THREADS), 0, s, T, n, frames,
-                       fstride, pitch, hist, regions, casc);
+    SetupArgs sa{};
+    long long extra = 0;
+    if (setup) {
+        sa = *setup;
+        extra = (sa.m * sa.segs + HIST_THREADS - 1) / HIST_THREADS;
+    }
+    if (per_xcd * 8 + extra > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(hog_hist_kernel, dim3((unsigned)(per_xcd * 8 + extra)), dim3(HIST_THREADS), 0, s, T, n,
+                       frames, fstride, pitch, hist, regions, casc, (int)(per_xcd * 8), sa);
     return hipGetLastError();
 }
 
