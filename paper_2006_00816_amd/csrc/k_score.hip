@@ -55,7 +55,7 @@ __device__ __forceinline__ bool score_slot(const ScoreOrder& ord, int per_frame,
 // F16: products from split fp16 operands (HOG_ARITH_F16X3).
 template <int ROWS, bool F16>
 __global__ __launch_bounds__(ROWS * 64) void hog_score_kernel(
-    LevelTable T, ScoreOrder ord, int groups, int per_frame, int units, int halves, const float* __restrict__ feat,
+    LevelTable T, ScoreOrder ord, int groups, int per_frame, int units, int parts, const float* __restrict__ feat,
     const float4* __restrict__ bpack, const float* __restrict__ bias, int nf, float thresh,
     float* __restrict__ dense, unsigned long long* __restrict__ poskey, int atomic_key,
     const hog_region* __restrict__ regions) {
@@ -68,16 +68,16 @@ __global__ __launch_bounds__(ROWS * 64) void hog_score_kernel(
     const int tid = threadIdx.x;
     load_bpack(sm, bpack, grp, tid);
     __syncthreads();
-    // halves = 2: slot it runs one half of the tiles of row block it / 2
-    score_item<ROWS, F16>(T, frame, grp, halves == 2 ? it >> 1 : it, sm, sm.P[tid >> 6], feat, nf, bias, thresh,
-                          dense, poskey, atomic_key, tid, halves == 2 ? it & 1 : -1, regions);
+    // parts > 1: slot it runs part it % parts of the tiles of row block it / parts
+    score_item<ROWS, F16>(T, frame, grp, parts > 1 ? it / parts : it, sm, sm.P[tid >> 6], feat, nf, bias, thresh,
+                          dense, poskey, atomic_key, tid, parts > 1 ? it % parts : -1, regions, parts);
 }
 
 // The same work items and dispatch with separable filters (row and column
 // factors, RANK pairs per channel; see score_row_sep).
 template <int ROWS, int RANK>
 __global__ __launch_bounds__(ROWS * 64) void hog_sep_score_kernel(
-    LevelTable T, ScoreOrder ord, int groups, int per_frame, int units, int halves, const float* __restrict__ feat,
+    LevelTable T, ScoreOrder ord, int groups, int per_frame, int units, int parts, const float* __restrict__ feat,
     const float* __restrict__ row, const float* __restrict__ col, const float* __restrict__ bias, int nf,
     float thresh, float* __restrict__ dense, unsigned long long* __restrict__ poskey, int atomic_key,
     const hog_region* __restrict__ regions) {
@@ -89,8 +89,8 @@ __global__ __launch_bounds__(ROWS * 64) void hog_sep_score_kernel(
     const int tid = threadIdx.x;
     load_sep(sm, row, col, nf, grp, tid);
     __syncthreads();
-    score_item_sep<ROWS, RANK>(T, frame, grp, halves == 2 ? it >> 1 : it, sm, sm.P[tid >> 6], feat, nf, bias, thresh,
-                               dense, poskey, atomic_key, tid, halves == 2 ? it & 1 : -1, regions);
+    score_item_sep<ROWS, RANK>(T, frame, grp, parts > 1 ? it / parts : it, sm, sm.P[tid >> 6], feat, nf, bias,
+                               thresh, dense, poskey, atomic_key, tid, parts > 1 ? it % parts : -1, regions, parts);
 }
 
 namespace {
@@ -180,7 +180,7 @@ ScoreOrder score_order(const LevelTable& T, int rows, int per_frame, int units, 
 
 // Grid and dispatch order of a scoring launch (shared by both scorers).
 struct ScoreGrid {
-    int groups, per_frame, units, halves, blocks;
+    int groups, per_frame, units, parts, blocks;
     ScoreOrder ord;
 };
 
@@ -195,16 +195,18 @@ bool score_grid(const LevelTable& T, int n, int nf, int rows, ScoreGrid* g) {
             cus = 0;
     }
     // small items that still leave compute units idle: split the rows'
-    // tiles in two halves, so that a level-0 row takes 3 tile times, not 5
+    // tiles over two slots (a level-0 row takes 3 tile times, not 5), or
+    // four where even those fit the compute units (2 tile times)
     const int blocks_of_rows = (T.rows_total + rows - 1) / rows;
-    const int halves = rows == SCORE_SMALL_ROWS && (long long)blocks_of_rows * units < cus ? 2 : 1;
-    const int per_frame = blocks_of_rows * halves;
+    const long long small = rows == SCORE_SMALL_ROWS ? (long long)blocks_of_rows * units : (long long)cus;
+    const int parts = 4 * small <= cus ? 4 : small < cus ? 2 : 1;
+    const int per_frame = blocks_of_rows * parts;
     const long long items = (long long)per_frame * units;
     if (items <= 0 || items > 0x7fffff00LL) return false;
     g->groups = groups;
     g->per_frame = per_frame;
     g->units = (int)units;
-    g->halves = halves;
+    g->parts = parts;
     g->blocks = units >= 8 ? (int)((units + 7) / 8 * per_frame * 8) : (int)((items + 7) / 8 * 8);
     for (int i = 0; i < SCORE_ORDER_MAX; ++i) g->ord.s[i] = (unsigned char)i;
     if (units >= 8 && per_frame <= SCORE_ORDER_MAX && rows > SCORE_SMALL_ROWS && cus >= 8)
@@ -222,7 +224,7 @@ hipError_t launch_score_sep(const LevelTable& T, int n, const float* feat, const
     const int ak = atomic_key ? 1 : 0;
 #define HOG_SEP_LAUNCH(R, K)                                                                                      \
     hipLaunchKernelGGL((hog_sep_score_kernel<R, K>), dim3(g.blocks), dim3(R * 64), 0, s, T, g.ord, g.groups,      \
-                       g.per_frame, g.units, g.halves, feat, row, col, bias, nf, thresh, dense, poskey, ak, regions)
+                       g.per_frame, g.units, g.parts, feat, row, col, bias, nf, thresh, dense, poskey, ak, regions)
     if (rows == SCORE_SMALL_ROWS) {
         switch (rank) {
             case 1: HOG_SEP_LAUNCH(SCORE_SMALL_ROWS, 1); break;
@@ -264,7 +266,7 @@ hipError_t launch_score(const LevelTable& T, int n, const float* feat, const flo
     if (!score_grid(T, n, nf, rows, &g)) return hipErrorInvalidValue;
 #define HOG_SCORE_LAUNCH(R, F)                                                                                   \
     hipLaunchKernelGGL((hog_score_kernel<R, F>), dim3(g.blocks), dim3(R * 64), 0, s, T, g.ord, g.groups,          \
-                       g.per_frame, g.units, g.halves, feat, bpack, bias, nf, thresh, dense, poskey,             \
+                       g.per_frame, g.units, g.parts, feat, bpack, bias, nf, thresh, dense, poskey,             \
                        atomic_key ? 1 : 0, regions)
     if (rows == SCORE_SMALL_ROWS) {
         if (f16x3) HOG_SCORE_LAUNCH(SCORE_SMALL_ROWS, true);

@@ -40,6 +40,17 @@ __device__ __forceinline__ void load_bpack(Score16SmemT<ROWS>& sm, const float4*
     for (int e = tid; e < B16_PER_GROUP; e += ROWS * 64) sm.B[e] = g[e];
 }
 
+// Tiles [tb, te) of part `part` of a row of ntiles M tiles split over
+// `parts` slots.  Every part after the first recomputes the tile before
+// its range for the carry, so the first part takes one tile more: with
+// c = ceil((ntiles + parts - 1) / parts) the parts' costs in tile times
+// are all at most c (5 tiles: 3 + 2 for two parts, 2 + 1 + 1 + 1 for four).
+__device__ __forceinline__ void row_part_tiles(int ntiles, int part, int parts, int& tb, int& te) {
+    const int c = (ntiles + 2 * parts - 2) / parts;
+    tb = part == 0 ? 0 : min(ntiles, c + (part - 1) * (c - 1));
+    te = min(ntiles, c + part * (c - 1));
+}
+
 // Window scores of M tile t of window row r from the tile's partial
 // products in `ring`, stored column-major: P[(f, dc)][x] at
 // ring[(10 f + dc) * SC_RSTR + x] for the 16 cells x of the tile (f the
@@ -378,15 +389,16 @@ __device__ __forceinline__ void score_row16(const DevLevel& L, int k, int r, con
 
 // One scoring item: window rows q = ROWS * item + wave of the frame's list
 // of rows (levels in order), filter group grp; sm.B holds the group's B.
-// Waves past the last row do nothing.  half < 0: whole rows; half = 0 or 1:
-// the first or second half of the M tiles of rows with three or more tiles
-// (the second half of a shorter row is empty).
+// Waves past the last row do nothing.  part < 0: whole rows; part =
+// 0 .. parts - 1: that part of the row's M tiles (row_part_tiles; a part
+// can be empty).
 template <int ROWS, bool F16 = false, class SM>
 __device__ __forceinline__ void score_item(const LevelTable& T, int frame, int grp, int item, const SM& sm,
                                            float* __restrict__ ring, const float* __restrict__ feat, int nf,
                                            const float* __restrict__ bias, float thresh, float* __restrict__ dense,
                                            unsigned long long* __restrict__ poskey, int atomic_key, int tid,
-                                           int half = -1, const hog_region* __restrict__ regions = nullptr) {
+                                           int part = -1, const hog_region* __restrict__ regions = nullptr,
+                                           int parts = 2) {
     // the wave's row, made wave-uniform so that the level's fields live in
     // scalar registers
     const int q = item * ROWS + __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -401,10 +413,8 @@ __device__ __forceinline__ void score_item(const LevelTable& T, int frame, int g
     const int lane = tid & 63;
     const int ntiles = (L.cx + 15) >> 4;
     int tb = 0, te = ntiles;
-    if (half >= 0) {
-        const int mid = ntiles >= 3 ? (ntiles + 1) >> 1 : ntiles;
-        tb = half ? mid : 0;
-        te = half ? ntiles : mid;
+    if (part >= 0) {
+        row_part_tiles(ntiles, part, parts, tb, te);
         if (tb >= te) return;
     }
     int c_lo, c_hi;
@@ -568,7 +578,8 @@ __device__ __forceinline__ void score_item_sep(const LevelTable& T, int frame, i
                                                const float* __restrict__ feat, int nf, const float* __restrict__ bias,
                                                float thresh, float* __restrict__ dense,
                                                unsigned long long* __restrict__ poskey, int atomic_key, int tid,
-                                               int half = -1, const hog_region* __restrict__ regions = nullptr) {
+                                               int part = -1, const hog_region* __restrict__ regions = nullptr,
+                                               int parts = 2) {
     const int q = item * ROWS + __builtin_amdgcn_readfirstlane(tid >> 6);
     if (q >= T.rows_total) return;
     const int k = HOG_FIND_LEVEL(T, q, row_off);
@@ -581,10 +592,8 @@ __device__ __forceinline__ void score_item_sep(const LevelTable& T, int frame, i
     const int lane = tid & 63;
     const int ntiles = (L.cx + 15) >> 4;
     int tb = 0, te = ntiles;
-    if (half >= 0) {
-        const int mid = ntiles >= 3 ? (ntiles + 1) >> 1 : ntiles;
-        tb = half ? mid : 0;
-        te = half ? ntiles : mid;
+    if (part >= 0) {
+        row_part_tiles(ntiles, part, parts, tb, te);
         if (tb >= te) return;
     }
     int c_lo, c_hi;
